@@ -1,0 +1,209 @@
+/*
+ * bsdmrg: block-sparse U(1)xU(1) two-site DMRG hot path on AMD MI355X (gfx950).
+ *
+ * C ABI of the shared library libbsdmrg.so.  The calls follow the problem
+ * statement of the ab initio DMRG sweep (Menczer & Legeza, arXiv:2412.04676):
+ * load one- and two-electron integrals (Hamiltonian, Eq. 1), set MPS site
+ * tensors (Eq. 2), build and renormalize block operators (Sec. II.B, steps 1
+ * and 3), apply the effective Hamiltonian to a two-site wave function
+ * (Sec. II.B, step 2), and serialize / deserialize / offload block operators
+ * (Sec. III.A strategy 2 and Sec. III.B.2).
+ *
+ * Conventions
+ *  - Spatial orbital i is site i.  Spin-orbital p = 2 i + sigma (sigma 0 alpha,
+ *    1 beta); Jordan-Wigner order 0a, 0b, 1a, 1b, ...  Local site basis:
+ *    0 |0>, 1 a+_a|0>, 2 a+_b|0>, 3 a+_a a+_b|0>.
+ *  - Hamiltonian: H = sum h_pq a+_ps a_qs
+ *        + 1/2 sum (pq|rs) a+_ps a+_rt a_st a_qs  (chemists' order, no core term).
+ *  - A quantum number is (n_alpha, n_beta).  Bond n lies between sites n-1 and
+ *    n; its sector label counts the electrons on sites 0..n-1.
+ *  - All floating-point data are float64, row-major.
+ *  - Buffers are owned by the caller.  "dev" pointers are device memory on the
+ *    current HIP device, "host" pointers are host memory; pinned host memory is
+ *    required where stated.  The library owns only its context and the block
+ *    operators it builds.
+ *  - Stream-ordered calls enqueue work on the given stream and return; calls
+ *    documented as synchronizing wait for their stream before returning.
+ *  - Every call returns a status code (BSDMRG_OK = 0).  On error nothing is
+ *    launched, and bsdmrg_last_error() (thread-local) describes the failure.
+ *    No C++ exception crosses this interface.
+ */
+#ifndef BSDMRG_H
+#define BSDMRG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* bsdmrg_stream_t; /* a hipStream_t (NULL = default stream) */
+typedef struct bsdmrg_ctx bsdmrg_ctx;
+
+enum {
+  BSDMRG_OK = 0,
+  BSDMRG_EINVAL = 1,   /* invalid argument */
+  BSDMRG_ESTATE = 2,   /* call out of order (missing integrals, tensors or blocks) */
+  BSDMRG_ESHAPE = 3,   /* sizes or sectors inconsistent */
+  BSDMRG_ENOMEM = 4,   /* buffer too small or allocation failure */
+  BSDMRG_EHIP = 5,     /* HIP runtime error */
+  BSDMRG_EBUSY = 6,    /* block is not resident on the device */
+  BSDMRG_ECORRUPT = 7  /* serialized stream does not match the target */
+};
+
+enum { BSDMRG_LEFT = 0, BSDMRG_RIGHT = 1 };
+enum { BSDMRG_FP64 = 0 };
+
+/* Last error message of the calling thread (never NULL). */
+const char* bsdmrg_last_error(void);
+
+/* Create a context for L spatial orbitals holding n_alpha + n_beta electrons.
+ * EINVAL if L < 2 or the electron counts do not fit.  Uses the current device. */
+int bsdmrg_create(bsdmrg_ctx** out, int L, int n_alpha, int n_beta);
+int bsdmrg_destroy(bsdmrg_ctx* ctx);
+
+/* Integrals of Eq. 1: h (host, L*L) and eri (host, L^4, (pq|rs) at
+ * ((p*L+q)*L+r)*L+s).  Copied into the context.  EINVAL if h is not symmetric
+ * or eri violates the 8-fold permutational symmetry by more than
+ * 1e-12 * max|eri|, or e_core != 0 (electronic energies only). */
+int bsdmrg_load_integrals(bsdmrg_ctx* ctx, const double* h, const double* eri, double e_core);
+
+/* MPS site tensor (Eq. 2) of `site`, given as n_blocks dense blocks.
+ * meta (host, n_blocks x 5 int32): q_left_alpha, q_left_beta, s, rows, cols, where
+ * q_left is the left-bond sector, s the local state, rows = d_left(q_left) and
+ * cols = d_right(q_left + q_s).  data (host): the blocks one after another,
+ * each row-major and compact.  The tensor must be left-canonical for sites left
+ * of the two-site position and right-canonical to its right; the library does
+ * not check orthogonality.  Copied to the device (synchronizing).  ESHAPE if two
+ * blocks give a bond sector different dimensions. */
+int bsdmrg_set_site_tensor(bsdmrg_ctx* ctx, int site, int n_blocks, const int32_t* meta,
+                           const double* data);
+
+/* Build renormalized block operators (Sec. II.B: preprocessing and
+ * renormalization).  side = BSDMRG_LEFT: blocks for bonds 0..bond from the left
+ * site tensors 0..bond-1 (left blocks keep H, a+_p, a+_p a+_q, a+_p a_q and the
+ * three-operator complementary operators).  side = BSDMRG_RIGHT: blocks for bonds
+ * L..bond from the right site tensors bond..L-1 (right blocks keep H, a+_r and
+ * the complementary operators S_x, P_pq, Q_pq of every spin-orbital to their
+ * left).  Already built blocks are kept.  Synchronizes `stream`. */
+int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream);
+
+/* Layout of the two-site wave function at sites (site, site+1), between the
+ * left block of bond `site` and the right block of bond site+2.  With meta ==
+ * NULL only *n_blocks and *n_elems are returned.  Otherwise meta (host, cap >=
+ * n_blocks x 8 int32) receives q_left_a, q_left_b, s1, s2, q_right_a, q_right_b
+ * (bond labels), rows, cols per block, and offsets (host, n_blocks int64) each
+ * block's element offset.  Blocks are compact row-major and grouped by right
+ * sector. */
+int bsdmrg_psi_layout(bsdmrg_ctx* ctx, int site, int* n_blocks, int64_t* n_elems, int32_t* meta,
+                      int64_t* offsets);
+
+/* Prepare the effective-Hamiltonian product at `site` (the "Tables" step:
+ * term list, aggregated operators, grouped-GEMM tile lists).  ws_bytes bounds
+ * the intermediate workspace (0 = 4 GiB); larger problems are split into
+ * chunks.  Synchronizes `stream`.  Optional: bsdmrg_hpsi prepares on first use. */
+int bsdmrg_hpsi_prepare(bsdmrg_ctx* ctx, int site, int precision, size_t ws_bytes,
+                        bsdmrg_stream_t stream);
+
+/* out = H_eff psi (Sec. II.B step 2) at two-site position `site`; psi and out
+ * are device buffers in the layout of bsdmrg_psi_layout and must not overlap.
+ * Stream-ordered; psi and out must stay valid until the stream reaches it. */
+int bsdmrg_hpsi(bsdmrg_ctx* ctx, int site, const double* psi_dev, double* out_dev, int precision,
+                bsdmrg_stream_t stream);
+
+/* Statistics of the last prepared product at `site`: useful flops per product
+ * (2 m n k summed over all non-identity sector GEMMs), number of channels,
+ * K-segments and aggregated operators, and workspace bytes. */
+int bsdmrg_hpsi_info(bsdmrg_ctx* ctx, int site, int precision, double* flops, int64_t* n_channels,
+                     int64_t* n_segments, int64_t* n_aggregates, int64_t* ws_bytes);
+
+/* Copy one renormalized block operator to the host (synchronizing).  kind is
+ * one of 'H','c','A','B','S','P','Q' with spin-orbital indices p, q (-1 if
+ * unused).  With data == NULL, *n_blocks and *n_elems are returned.  Otherwise
+ * meta (n_blocks x 6 int32: q_in_a, q_in_b, q_out_a, q_out_b, rows, cols; labels
+ * count the electrons inside the block) and data (compact row-major) are filled.
+ * ESTATE if the operator does not exist. */
+int bsdmrg_get_block_op(bsdmrg_ctx* ctx, int side, int bond, char kind, int p, int q,
+                        int* n_blocks, int64_t* n_elems, int32_t* meta, double* data);
+
+/* Batched dense block GEMMs on the matrix cores, the primitive behind every
+ * sector product: C_i = alpha_i op(A_i) op(B_i) + beta_i C_i for each problem
+ * (device pointers, row-major, op = transpose if trans != 0).  Problems must
+ * not write overlapping C regions.  Synchronizes `stream` (problem lists are
+ * uploaded per call). */
+typedef struct {
+  const double* A;
+  const double* B;
+  double* C;
+  int32_t M, N, K;
+  int32_t transA, transB;
+  int32_t pad;
+  int64_t lda, ldb, ldc;
+  double alpha, beta;
+} bsdmrg_gemm_desc;
+int bsdmrg_block_gemm(int n, const bsdmrg_gemm_desc* problems, bsdmrg_stream_t stream);
+
+/* ---------------------------------------------------------------- serializer
+ * Stream format: header (64 B), family table (64 B per family), block tables
+ * (32 B per block), zero padding to 256 B, then every family's payload
+ * (n_layers layers of its blocks, compact row-major, layer after layer) padded
+ * to 256 B.  The size is exact and known before packing (Sec. III.B.2). */
+typedef struct {
+  uint64_t tag;                 /* caller-defined id stored in the stream */
+  int32_t dq[2];                /* quantum-number change of every layer */
+  int32_t n_layers, n_blocks;
+  const int32_t* block_q;       /* host, n_blocks x 2: input sector of each block */
+  const int32_t* rows;          /* host, n_blocks */
+  const int32_t* cols;          /* host, n_blocks */
+  const int32_t* ld;            /* host, n_blocks: leading dimension in memory (>= cols) */
+  const int64_t* elem_offset;   /* host, n_blocks: element offset of each block inside a layer */
+  int64_t layer_stride;         /* elements between consecutive layers */
+  void* data;                   /* device base of layer 0 (16-byte aligned) */
+} bsdmrg_family_desc;
+
+/* Exact size in bytes of the stream of n families (host arithmetic only). */
+int bsdmrg_serialized_size_desc(int n, const bsdmrg_family_desc* fams, size_t* bytes);
+/* Serialize families into dst_dev (device, 256-byte aligned, cap bytes).
+ * ENOMEM if cap is smaller than the exact size.  Synchronizes `stream`. */
+int bsdmrg_pack_desc(int n, const bsdmrg_family_desc* fams, void* dst_dev, size_t cap,
+                     bsdmrg_stream_t stream);
+/* Deserialize src_dev (device, 256-byte aligned) into the families' memory.
+ * The stream's tables must match the families' skeletons exactly, else
+ * ECORRUPT and no family memory is written.  Synchronizes `stream`. */
+int bsdmrg_unpack_desc(int n, const bsdmrg_family_desc* fams, const void* src_dev, size_t bytes,
+                       bsdmrg_stream_t stream);
+
+/* The same for all operator families of a renormalized block. */
+int bsdmrg_serialized_size(bsdmrg_ctx* ctx, int side, int bond, size_t* bytes);
+int bsdmrg_pack(bsdmrg_ctx* ctx, int side, int bond, void* dst_dev, size_t cap, bsdmrg_stream_t stream);
+int bsdmrg_unpack(bsdmrg_ctx* ctx, int side, int bond, const void* src_dev, size_t bytes,
+                  bsdmrg_stream_t stream);
+
+/* Asynchronous offload of a block (Sec. III.A strategy 2, Sec. III.B.4):
+ * pack into staging_dev on `compute` (synchronizing only the host-side
+ * descriptor upload), then a device-to-host copy into pinned_host (allocated
+ * with hipHostMalloc) on `side`, ordered after the pack by an event.  Returns
+ * immediately after enqueueing the copy.  With release != 0 the block's device
+ * memory is freed once the copy completes (the block then reports EBUSY until
+ * prefetched).  staging_dev and pinned_host must hold bsdmrg_serialized_size
+ * bytes and stay valid until bsdmrg_offload_wait returns. */
+int bsdmrg_offload(bsdmrg_ctx* ctx, int side, int bond, void* staging_dev, void* pinned_host,
+                   size_t cap, int release, bsdmrg_stream_t compute, bsdmrg_stream_t side_stream);
+/* Block until the last offload of (side, bond) has reached host memory
+ * ("fetching").  Returns the host-side wait in seconds in *waited_s if non-NULL. */
+int bsdmrg_offload_wait(bsdmrg_ctx* ctx, int side, int bond, double* waited_s);
+/* Reload a block: validate pinned_host on the host, copy it to staging_dev on
+ * `side`, then unpack on `compute` after an event (re-allocating the block's
+ * device memory if it was released).  ECORRUPT if the stream does not match. */
+int bsdmrg_prefetch(bsdmrg_ctx* ctx, int side, int bond, const void* pinned_host, void* staging_dev,
+                    size_t bytes, bsdmrg_stream_t compute, bsdmrg_stream_t side_stream);
+
+/* Device bytes held by the block operators of (side, bond). */
+int bsdmrg_block_bytes(bsdmrg_ctx* ctx, int side, int bond, size_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSDMRG_H */

@@ -1,0 +1,603 @@
+// Renormalized block operators on the device and the renormalization step
+// (Sec. II.B: the enlarged block's operators are mapped to the new basis and
+// kept for later steps).  Operators of one block that share a quantum-number
+// change dq share one skeleton and live as layers of one family (Fig. 4a).
+#include "ctx.h"
+
+#include <algorithm>
+#include <unordered_map>
+
+namespace bsd {
+
+DevBuf::~DevBuf() { release(); }
+void DevBuf::reserve(size_t bytes) {
+  if (bytes <= n && p) return;
+  release();
+  if (bytes == 0) bytes = 256;
+  BSD_HIP(hipMalloc(&p, bytes));
+  n = bytes;
+}
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  n = 0;
+}
+
+Ctx::~Ctx() {}
+
+Block::~Block() {
+  if (offload_done) (void)hipEventDestroy(offload_done);
+}
+
+Skeleton make_skeleton(const Basis& in, const Basis& out, const Q& dq) {
+  Skeleton sk;
+  sk.dq = dq;
+  sk.by_in.assign(in.q.size(), -1);
+  int64_t off = 0;
+  for (int i = 0; i < (int)in.q.size(); ++i) {
+    int j = out.find(in.q[i] + dq);
+    if (j < 0) continue;
+    SkBlock b;
+    b.in = i;
+    b.out = j;
+    b.rows = out.dim[j];
+    b.cols = in.dim[i];
+    b.ld = (b.cols + 1) & ~1;
+    b.off = off;
+    off += (int64_t)b.rows * b.ld;
+    sk.by_in[i] = (int)sk.blocks.size();
+    sk.blocks.push_back(b);
+  }
+  sk.layer_stride = (off + 31) / 32 * 32;
+  return sk;
+}
+
+const double* Block::op_block(const OpKey& k, int in_idx, int* rows, int* cols, int* ld) const {
+  auto it = ops.find(k);
+  if (it == ops.end()) return nullptr;
+  const Family& f = fams[it->second.fam];
+  int b = f.sk.by_in[in_idx];
+  if (b < 0) return nullptr;
+  const SkBlock& sb = f.sk.blocks[b];
+  *rows = sb.rows;
+  *cols = sb.cols;
+  *ld = sb.ld;
+  return f.dev + (int64_t)it->second.layer * f.sk.layer_stride + sb.off;
+}
+
+size_t Block::device_bytes() const {
+  size_t s = 0;
+  for (auto& f : fams) s += f.bytes();
+  return s;
+}
+
+static std::vector<OpKey> block_keys(bool left, int first, int last, int L) {
+  std::vector<OpKey> k;
+  const int NM = 2 * L;
+  auto add = [&](char c, int p, int q) {
+    OpKey o;
+    o.kind = c;
+    o.p = p;
+    o.q = q;
+    k.push_back(o);
+  };
+  if (left) {
+    const int nm = 2 * last;
+    if (last > 0) add('H', -1, -1);
+    for (int p = 0; p < nm; ++p) add('c', p, -1);
+    for (int p = 0; p < nm; ++p)
+      for (int q = p + 1; q < nm; ++q) add('A', p, q);
+    for (int p = 0; p < nm; ++p)
+      for (int q = 0; q < nm; ++q) add('B', p, q);
+    for (int y = nm; y < NM; ++y) add('S', y, -1);
+  } else {
+    const int m0 = 2 * first;
+    if (first < L) add('H', -1, -1);
+    for (int r = m0; r < NM; ++r) add('c', r, -1);
+    for (int x = 0; x < m0; ++x) add('S', x, -1);
+    for (int p = 0; p < m0; ++p)
+      for (int q = p + 1; q < m0; ++q) add('P', p, q);
+    for (int p = 0; p < m0; ++p)
+      for (int q = 0; q < m0; ++q) add('Q', p, q);
+  }
+  return k;
+}
+
+static std::unique_ptr<Block> alloc_block(bool left, int first, int last, const Basis& basis,
+                                          const std::vector<OpKey>& keys, hipStream_t s) {
+  auto B = std::make_unique<Block>();
+  B->left = left;
+  B->first = first;
+  B->last = last;
+  B->basis = basis;
+  std::map<Q, int> famidx;
+  for (const auto& k : keys) {
+    Q dq = key_dq(k, left);
+    auto it = famidx.find(dq);
+    int f;
+    if (it == famidx.end()) {
+      f = (int)B->fams.size();
+      famidx[dq] = f;
+      Family fam;
+      fam.sk = make_skeleton(basis, basis, dq);
+      B->fams.push_back(std::move(fam));
+    } else {
+      f = it->second;
+    }
+    OpRef r;
+    r.fam = f;
+    r.layer = (int)B->fams[f].keys.size();
+    B->fams[f].keys.push_back(k);
+    B->ops[k] = r;
+  }
+  for (auto& f : B->fams) {
+    size_t bytes = f.bytes();
+    auto m = std::make_unique<DevBuf>();
+    m->reserve(bytes);
+    if (bytes) BSD_HIP(hipMemsetAsync(m->p, 0, bytes, s));
+    f.dev = static_cast<double*>(m->p);
+    B->mem.push_back(std::move(m));
+  }
+  return B;
+}
+
+void make_vacuum_blocks(Ctx& ctx) {
+  auto l = std::make_unique<Block>();
+  l->left = true;
+  l->first = l->last = 0;
+  l->basis.add({0, 0}, 1);
+  ctx.left[0] = std::move(l);
+  auto r = std::make_unique<Block>();
+  r->left = false;
+  r->first = r->last = ctx.L;
+  r->basis.add({0, 0}, 1);
+  ctx.right[ctx.L] = std::move(r);
+}
+
+Block* get_block(Ctx& ctx, bool left, int bond) {
+  auto& m = left ? ctx.left : ctx.right;
+  auto it = m.find(bond);
+  if (it == m.end()) return nullptr;
+  return it->second.get();
+}
+
+// ---------------------------------------------------------------- renormalization
+namespace {
+
+Q local_dq(const Mat& M, const SiteSet& C) {
+  for (int i = 0; i < M.n; ++i)
+    for (int j = 0; j < M.n; ++j)
+      if (M(i, j) != 0.0) return C.q[i] - C.q[j];
+  return {0, 0};
+}
+
+// block-side operator of a group: a stored op, the identity, or an aggregate
+struct Ref {
+  int kind;        // 0 stored op, 1 identity, 2 aggregate
+  OpKey key;
+  bool trans = false;
+  int agg = -1;    // index into aggregates
+  Q dq;
+};
+
+struct AggOp {
+  Skeleton sk;
+  int64_t off;     // element offset in the workspace
+  std::vector<Term> terms;
+};
+
+// Pointer to block (in_idx -> out) of op(ref), with its storage orientation.
+struct Operand {
+  const double* p = nullptr;
+  int64_t ld = 0;
+  bool trans = false;
+  bool ident = false;
+  int rows = 0, cols = 0;   // of op(ref) block
+};
+
+}  // namespace
+
+static Operand ref_block(const Block& blk, const Ref& r, const std::vector<AggOp>& aggs,
+                         const double* ws, int in_idx) {
+  Operand o;
+  const Basis& bs = blk.basis;
+  Q qout = bs.q[in_idx] + r.dq;
+  int out_idx = bs.find(qout);
+  if (out_idx < 0) return o;
+  if (r.kind == 1) {
+    o.ident = true;
+    o.rows = o.cols = bs.dim[in_idx];
+    o.p = ws;  // unused
+    return o;
+  }
+  if (r.kind == 2) {
+    const AggOp& a = aggs[r.agg];
+    int b = a.sk.by_in[in_idx];
+    if (b < 0) return o;
+    const SkBlock& sb = a.sk.blocks[b];
+    o.p = ws + a.off + sb.off;
+    o.ld = sb.ld;
+    o.rows = sb.rows;
+    o.cols = sb.cols;
+    return o;
+  }
+  int rr, cc, ld;
+  if (!r.trans) {
+    const double* p = blk.op_block(r.key, in_idx, &rr, &cc, &ld);
+    if (!p) return o;
+    o.p = p;
+    o.ld = ld;
+    o.rows = rr;
+    o.cols = cc;
+  } else {
+    // op(O) = O^T maps in -> out, so O maps out -> in
+    const double* p = blk.op_block(r.key, out_idx, &rr, &cc, &ld);
+    if (!p) return o;
+    o.p = p;
+    o.ld = ld;
+    o.trans = true;
+    o.rows = cc;
+    o.cols = rr;
+  }
+  return o;
+}
+
+static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
+  BSD_CHECK(ctx.have_ints, 1, "integrals not loaded");
+  const int L = ctx.L, NM = 2 * L;
+  Block* old = get_block(ctx, left, bond);
+  BSD_CHECK(old != nullptr, 1, "source block missing");
+  const int site = left ? bond : bond - 1;
+  BSD_CHECK(site >= 0 && site < L, 1, "site out of range");
+  const SiteTensor& T = ctx.sites[site];
+  BSD_CHECK(T.set, 1, "site tensor not set");
+  const SiteSet S = make_siteset(site, 1);
+
+  // new basis (electrons inside the new block) and map site-tensor blocks
+  Basis nb;
+  {
+    std::vector<std::pair<Q, int>> v;
+    const Basis& src = left ? T.right : T.left;
+    for (size_t i = 0; i < src.q.size(); ++i)
+      v.push_back({left ? src.q[i] : ctx.target - src.q[i], src.dim[i]});
+    std::sort(v.begin(), v.end(), [](auto& a, auto& b) { return a.first < b.first; });
+    for (auto& x : v) nb.add(x.first, x.second);
+  }
+  // old block basis must match the tensor's other bond
+  {
+    const Basis& other = left ? T.left : T.right;
+    for (size_t i = 0; i < other.q.size(); ++i) {
+      Q lab = left ? other.q[i] : ctx.target - other.q[i];
+      int j = old->basis.find(lab);
+      BSD_CHECK(j >= 0 && old->basis.dim[j] == other.dim[i], 3, "site tensor does not match block basis");
+    }
+  }
+  // site tensor block for (old sector idx, s) with its new sector idx
+  struct TB {
+    const double* p = nullptr;
+    int rows = 0, cols = 0, nidx = -1;
+  };
+  auto tblock = [&](int old_idx, int sstate) -> TB {
+    TB r;
+    Q qo = old->basis.q[old_idx];
+    if (left) {
+      int l = T.left.find(qo);
+      if (l < 0) return r;
+      auto it = T.by_ls.find({l, sstate});
+      if (it == T.by_ls.end()) return r;
+      const auto& b = T.blocks[it->second];
+      r.p = T.ptr(it->second);
+      r.rows = b.rows;
+      r.cols = b.cols;
+      r.nidx = nb.find(qo + kSiteQ[sstate]);
+    } else {
+      // old R label qo; new label qn = qo + q_s; tensor left bond label = target - qn
+      Q qn = qo + kSiteQ[sstate];
+      int l = T.left.find(ctx.target - qn);
+      if (l < 0) return r;
+      auto it = T.by_ls.find({l, sstate});
+      if (it == T.by_ls.end()) return r;
+      const auto& b = T.blocks[it->second];
+      r.p = T.ptr(it->second);
+      r.rows = b.rows;   // d_new
+      r.cols = b.cols;   // d_R
+      r.nidx = nb.find(qn);
+    }
+    return r;
+  };
+
+  const int nfirst = left ? 0 : site, nlast = left ? site + 1 : L;
+  std::vector<OpKey> keys = block_keys(left, nfirst, nlast, L);
+  auto nw = alloc_block(left, nfirst, nlast, nb, keys, s);
+
+  // expansions and block-side references
+  std::vector<Ref> refs;
+  std::map<std::tuple<int, char, int, int, bool>, int> ref_index;  // stored/identity refs
+  std::vector<AggOp> aggs;
+  int64_t ws_elems = 0;
+  struct GRef {
+    int ref;
+    double coef;
+    Mat M;
+    int mpar;
+  };
+  std::vector<std::vector<GRef>> per_key(keys.size());
+  for (size_t ki = 0; ki < keys.size(); ++ki) {
+    const OpKey& k = keys[ki];
+    std::vector<Group> gs = left ? expand_left(k, 2 * site, S, ctx.ints)
+                                 : expand_right(k, S, 2 * (site + 1), NM, ctx.ints);
+    const Q kdq = key_dq(k, left);
+    for (auto& g : gs) {
+      Q ldq = local_dq(g.M, S);
+      Q bdq = kdq - ldq;
+      int mpar = ldq.parity();
+      GRef gr;
+      gr.M = g.M;
+      gr.mpar = mpar;
+      if (g.terms.size() == 1) {
+        const Term& t = g.terms[0];
+        Ref r;
+        r.kind = t.key.kind == 'I' ? 1 : 0;
+        r.key = t.key;
+        r.trans = t.trans;
+        Q tdq = t.key.kind == 'I' ? Q{0, 0} : key_dq(t.key, left);
+        if (t.trans) tdq = -tdq;
+        BSD_CHECK(tdq == bdq, 1, "inconsistent dq in expansion");
+        if (r.kind == 0 && old->ops.find(t.key) == old->ops.end()) continue;
+        r.dq = bdq;
+        auto id = std::make_tuple(r.kind, t.key.kind, t.key.p, t.key.q, t.trans);
+        auto it = ref_index.find(id);
+        if (it == ref_index.end()) {
+          ref_index[id] = (int)refs.size();
+          gr.ref = (int)refs.size();
+          refs.push_back(r);
+        } else {
+          gr.ref = it->second;
+        }
+        gr.coef = t.coef;
+      } else {
+        AggOp a;
+        a.sk = make_skeleton(old->basis, old->basis, bdq);
+        a.off = ws_elems;
+        ws_elems += a.sk.layer_stride;
+        for (const auto& t : g.terms) {
+          Q tdq = t.key.kind == 'I' ? Q{0, 0} : key_dq(t.key, left);
+          if (t.trans) tdq = -tdq;
+          BSD_CHECK(tdq == bdq, 1, "inconsistent dq in aggregate");
+          if (t.key.kind != 'I' && old->ops.find(t.key) == old->ops.end()) continue;
+          a.terms.push_back(t);
+        }
+        if (a.terms.empty()) {
+          ws_elems -= a.sk.layer_stride;
+          continue;
+        }
+        Ref r;
+        r.kind = 2;
+        r.agg = (int)aggs.size();
+        r.dq = bdq;
+        aggs.push_back(std::move(a));
+        gr.ref = (int)refs.size();
+        refs.push_back(r);
+        gr.coef = 1.0;
+      }
+      per_key[ki].push_back(std::move(gr));
+    }
+  }
+
+  // phase-1 intermediates T(ref, s, old sector): op(ref) applied to the site tensor
+  struct TKey {
+    int ref, sstate, oidx;
+    bool operator<(const TKey& o) const {
+      return std::tie(ref, sstate, oidx) < std::tie(o.ref, o.sstate, o.oidx);
+    }
+  };
+  struct TVal {
+    int64_t off;     // -1: identity (use the site tensor block directly)
+    int rows, cols;  // T rows x cols (ld = cols)
+  };
+  std::map<TKey, TVal> tmap;
+  const int64_t agg_end = ws_elems;
+  // which (ref, s) pairs are needed
+  std::map<std::pair<int, int>, bool> need;
+  for (auto& v : per_key)
+    for (auto& gr : v)
+      for (int sp = 0; sp < 4; ++sp)
+        for (int s0 = 0; s0 < 4; ++s0)
+          if (gr.M(sp, s0) != 0.0) need[{gr.ref, s0}] = true;
+  const double* wsbase = nullptr;  // fixed after allocation; offsets used until then
+  std::vector<std::tuple<TKey, int, int, int>> p1list;  // key, out rows, K, cols
+  for (auto& nd : need) {
+    int ri = nd.first.first, s0 = nd.first.second;
+    const Ref& r = refs[ri];
+    for (int oi = 0; oi < (int)old->basis.q.size(); ++oi) {
+      TB tb = tblock(oi, s0);
+      if (!tb.p || tb.nidx < 0) continue;
+      int oo = old->basis.find(old->basis.q[oi] + r.dq);
+      if (oo < 0) continue;
+      if (r.kind == 1) {
+        tmap[{ri, s0, oi}] = {-1, 0, 0};
+        continue;
+      }
+      // does op(ref) have a block at oi?
+      if (r.kind == 2) {
+        if (aggs[r.agg].sk.by_in[oi] < 0) continue;
+      } else {
+        int rr, cc, ld;
+        int src = r.trans ? oo : oi;
+        if (!old->op_block(r.key, src, &rr, &cc, &ld)) continue;
+      }
+      int trows = old->basis.dim[oo];
+      int tcols = left ? tb.cols : tb.rows;  // d_new
+      tmap[{ri, s0, oi}] = {ws_elems, trows, tcols};
+      ws_elems += ((int64_t)trows * tcols + 1) / 2 * 2;
+    }
+  }
+  ctx.ws.reserve(std::max<int64_t>(ws_elems, 1) * sizeof(double));
+  double* ws = static_cast<double*>(ctx.ws.p);
+  wsbase = ws;
+  (void)wsbase;
+
+  // aggregation
+  {
+    std::vector<AggTask> tasks;
+    std::vector<AggTerm> terms;
+    for (auto& a : aggs)
+      for (const auto& sb : a.sk.blocks) {
+        AggTask t;
+        t.out = ws + a.off + sb.off;
+        t.ldo = sb.ld;
+        t.rows = sb.rows;
+        t.cols = sb.cols;
+        t.t0 = (int)terms.size();
+        for (const auto& tm : a.terms) {
+          AggTerm x;
+          x.coef = tm.coef;
+          x.pad = 0;
+          if (tm.key.kind == 'I') {
+            if (sb.in != sb.out) continue;
+            x.in = nullptr;
+            x.ldi = 0;
+            x.flags = kIdentA;
+          } else {
+            int rr, cc, ld;
+            const double* p = tm.trans ? old->op_block(tm.key, sb.out, &rr, &cc, &ld)
+                                       : old->op_block(tm.key, sb.in, &rr, &cc, &ld);
+            if (!p) continue;
+            x.in = p;
+            x.ldi = ld;
+            x.flags = tm.trans ? kTransA : 0;
+          }
+          terms.push_back(x);
+        }
+        t.nt = (int)terms.size() - t.t0;
+        tasks.push_back(t);
+      }
+    if (!tasks.empty()) {
+      DevBuf dt, dm;
+      dt.reserve(tasks.size() * sizeof(AggTask));
+      dm.reserve(std::max<size_t>(1, terms.size()) * sizeof(AggTerm));
+      BSD_HIP(hipMemcpyAsync(dt.p, tasks.data(), tasks.size() * sizeof(AggTask), hipMemcpyHostToDevice, s));
+      if (!terms.empty())
+        BSD_HIP(hipMemcpyAsync(dm.p, terms.data(), terms.size() * sizeof(AggTerm), hipMemcpyHostToDevice, s));
+      launch_aggregate((const AggTask*)dt.p, (const AggTerm*)dm.p, (int)tasks.size(), s);
+      BSD_HIP(hipStreamSynchronize(s));
+    }
+  }
+  (void)agg_end;
+
+  // phase 1: T = op(ref) X, X = A_s (left) or B_s^T (right)
+  std::vector<GemmProblem> p1;
+  for (auto& kv : tmap) {
+    if (kv.second.off < 0) continue;
+    const TKey& tk = kv.first;
+    const Ref& r = refs[tk.ref];
+    Operand o = ref_block(*old, r, aggs, ws, tk.oidx);
+    TB tb = tblock(tk.oidx, tk.sstate);
+    GemmProblem gp;
+    gp.C = tag_ptr(0, (uint64_t)(ws + kv.second.off));
+    gp.ldc = kv.second.cols;
+    gp.M = kv.second.rows;
+    gp.N = kv.second.cols;
+    gp.beta = 0.0;
+    GSeg sg;
+    sg.alpha = 1.0;
+    sg.K = o.cols;
+    sg.flags = (o.trans ? kTransA : 0) | (o.ident ? kIdentA : 0);
+    sg.A = tag_ptr(0, (uint64_t)o.p);
+    sg.lda = o.ld;
+    sg.B = tag_ptr(0, (uint64_t)tb.p);
+    if (left) {
+      sg.ldb = tb.cols;     // A_s: d_old x d_new
+    } else {
+      sg.flags |= kTransB;  // B_s: d_new x d_old, used transposed
+      sg.ldb = tb.cols;
+    }
+    gp.segs.push_back(sg);
+    p1.push_back(std::move(gp));
+  }
+  double fl = 0.0;
+  if (!p1.empty()) {
+    GemmPlan plan;
+    plan.build(p1);
+    GBases b{{0, 0, 0, 0}};
+    plan.launch(b, s);
+    fl += plan.flops;
+    BSD_HIP(hipStreamSynchronize(s));
+  }
+
+  // phase 2: new op blocks
+  std::vector<GemmProblem> p2;
+  for (size_t ki = 0; ki < keys.size(); ++ki) {
+    const OpRef& orf = nw->ops[keys[ki]];
+    Family& fam = nw->fams[orf.fam];
+    for (const auto& sb : fam.sk.blocks) {
+      GemmProblem gp;
+      gp.C = tag_ptr(0, (uint64_t)(fam.dev + (int64_t)orf.layer * fam.sk.layer_stride + sb.off));
+      gp.ldc = sb.ld;
+      gp.M = sb.rows;
+      gp.N = sb.cols;
+      gp.beta = 0.0;
+      const Q qn = nb.q[sb.in];
+      for (const auto& gr : per_key[ki]) {
+        const Ref& r = refs[gr.ref];
+        for (int s0 = 0; s0 < 4; ++s0) {
+          const Q qo = qn - kSiteQ[s0];
+          int oi = old->basis.find(qo);
+          if (oi < 0) continue;
+          auto it = tmap.find({gr.ref, s0, oi});
+          if (it == tmap.end()) continue;
+          int oo = old->basis.find(qo + r.dq);
+          for (int sp = 0; sp < 4; ++sp) {
+            double m = gr.M(sp, s0);
+            if (m == 0.0) continue;
+            if (old->basis.q[oo] + kSiteQ[sp] != nb.q[sb.out]) continue;
+            TB to = tblock(oo, sp);
+            if (!to.p) continue;
+            double sign;
+            if (left) sign = (gr.mpar && old->basis.q[oi].parity()) ? -1.0 : 1.0;
+            else sign = (r.dq.parity() && kSiteQ[s0].parity()) ? -1.0 : 1.0;
+            GSeg sg;
+            sg.alpha = gr.coef * m * sign;
+            sg.K = old->basis.dim[oo];
+            if (left) {
+              sg.A = tag_ptr(0, (uint64_t)to.p);    // A_{s'}: d_old' x d_new', used transposed
+              sg.lda = to.cols;
+              sg.flags = kTransA;
+            } else {
+              sg.A = tag_ptr(0, (uint64_t)to.p);    // B_{s'}: d_new' x d_old'
+              sg.lda = to.cols;
+              sg.flags = 0;
+            }
+            if (it->second.off >= 0) {
+              sg.B = tag_ptr(0, (uint64_t)(ws + it->second.off));
+              sg.ldb = it->second.cols;
+            } else {
+              TB ti = tblock(oi, s0);
+              sg.B = tag_ptr(0, (uint64_t)ti.p);
+              sg.ldb = ti.cols;
+              if (!left) sg.flags |= kTransB;
+            }
+            gp.segs.push_back(sg);
+          }
+        }
+      }
+      if (!gp.segs.empty()) p2.push_back(std::move(gp));
+    }
+  }
+  if (!p2.empty()) {
+    GemmPlan plan;
+    plan.build(p2);
+    GBases b{{0, 0, 0, 0}};
+    plan.launch(b, s);
+    fl += plan.flops;
+    BSD_HIP(hipStreamSynchronize(s));
+  }
+  ctx.renorm_flops += fl;
+  auto& m = left ? ctx.left : ctx.right;
+  m[left ? bond + 1 : bond - 1] = std::move(nw);
+}
+
+void renormalize_left_block(Ctx& ctx, int bond, hipStream_t s) { renormalize(ctx, true, bond, s); }
+void renormalize_right_block(Ctx& ctx, int bond, hipStream_t s) { renormalize(ctx, false, bond, s); }
+
+}  // namespace bsd

@@ -1,0 +1,569 @@
+// C ABI of the library (declared in include/bsdmrg.h).
+#include "../../include/bsdmrg.h"
+
+#include <chrono>
+#include <cmath>
+
+#include "hpsi.h"
+
+struct bsdmrg_ctx {
+  bsd::Ctx c;
+};
+
+namespace bsd {
+
+static thread_local std::string g_err;
+void set_last_error(const std::string& m) { g_err = m; }
+
+static hipStream_t S(bsdmrg_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+template <class F>
+static int guard(F&& f) {
+  try {
+    f();
+    return BSDMRG_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return BSDMRG_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return BSDMRG_EINVAL;
+  }
+}
+
+static std::vector<FamilyView> block_views(const Block& b, bool left) {
+  std::vector<FamilyView> v;
+  uint64_t tag = 0;
+  for (const auto& f : b.fams) {
+    FamilyView x;
+    x.tag = ((uint64_t)(left ? 0 : 1) << 63) | ((uint64_t)b.first << 40) | ((uint64_t)b.last << 20) | tag++;
+    x.dq = f.sk.dq;
+    x.n_layers = (int)f.keys.size();
+    for (const auto& sb : f.sk.blocks) {
+      x.bq.push_back(b.basis.q[sb.in]);
+      x.rows.push_back(sb.rows);
+      x.cols.push_back(sb.cols);
+      x.ld.push_back(sb.ld);
+      x.off.push_back(sb.off);
+    }
+    x.layer_stride = f.sk.layer_stride;
+    x.data = f.dev;
+    v.push_back(std::move(x));
+  }
+  return v;
+}
+
+static std::vector<FamilyView> desc_views(int n, const bsdmrg_family_desc* d) {
+  BSD_CHECK(n >= 0 && (n == 0 || d != nullptr), BSDMRG_EINVAL, "bad family list");
+  std::vector<FamilyView> v;
+  for (int i = 0; i < n; ++i) {
+    const auto& f = d[i];
+    BSD_CHECK(f.n_layers >= 0 && f.n_blocks >= 0, BSDMRG_EINVAL, "negative family sizes");
+    BSD_CHECK(f.n_blocks == 0 || (f.block_q && f.rows && f.cols && f.ld && f.elem_offset), BSDMRG_EINVAL,
+              "missing block arrays");
+    BSD_CHECK(f.n_layers == 0 || f.n_blocks == 0 || f.data != nullptr, BSDMRG_EINVAL, "missing data pointer");
+    BSD_CHECK(((uintptr_t)f.data % 16) == 0, BSDMRG_EINVAL, "family data must be 16-byte aligned");
+    FamilyView x;
+    x.tag = f.tag;
+    x.dq = {f.dq[0], f.dq[1]};
+    x.n_layers = f.n_layers;
+    int64_t maxend = 0;
+    for (int b = 0; b < f.n_blocks; ++b) {
+      BSD_CHECK(f.rows[b] >= 0 && f.cols[b] >= 0 && f.ld[b] >= f.cols[b] && f.elem_offset[b] >= 0, BSDMRG_EINVAL,
+                "bad block geometry");
+      x.bq.push_back({f.block_q[2 * b], f.block_q[2 * b + 1]});
+      x.rows.push_back(f.rows[b]);
+      x.cols.push_back(f.cols[b]);
+      x.ld.push_back(f.ld[b]);
+      x.off.push_back(f.elem_offset[b]);
+      if (f.rows[b] > 0) maxend = std::max<int64_t>(maxend, f.elem_offset[b] + (int64_t)(f.rows[b] - 1) * f.ld[b] + f.cols[b]);
+    }
+    BSD_CHECK(f.n_layers <= 1 || f.layer_stride >= maxend, BSDMRG_EINVAL, "layers overlap");
+    x.layer_stride = f.layer_stride;
+    x.data = f.data;
+    v.push_back(std::move(x));
+  }
+  return v;
+}
+
+static Block* need_block(Ctx& c, int side, int bond) {
+  BSD_CHECK(side == BSDMRG_LEFT || side == BSDMRG_RIGHT, BSDMRG_EINVAL, "side must be LEFT or RIGHT");
+  Block* b = get_block(c, side == BSDMRG_LEFT, bond);
+  BSD_CHECK(b != nullptr, BSDMRG_ESTATE, "block not built");
+  return b;
+}
+
+static void ensure_splan(Block& b, hipStream_t s) {
+  if (!b.splan) b.splan = serial_plan(block_views(b, b.left), s);
+}
+
+static void realloc_block(Block& b, hipStream_t s) {
+  b.mem.clear();
+  for (auto& f : b.fams) {
+    auto m = std::make_unique<DevBuf>();
+    m->reserve(f.bytes());
+    if (f.bytes()) BSD_HIP(hipMemsetAsync(m->p, 0, f.bytes(), s));
+    f.dev = static_cast<double*>(m->p);
+    b.mem.push_back(std::move(m));
+  }
+  b.splan.reset();
+  b.resident = true;
+}
+
+}  // namespace bsd
+
+using namespace bsd;
+
+extern "C" {
+
+const char* bsdmrg_last_error(void) { return g_err.c_str(); }
+
+int bsdmrg_create(bsdmrg_ctx** out, int L, int n_alpha, int n_beta) {
+  return guard([&] {
+    BSD_CHECK(out != nullptr, BSDMRG_EINVAL, "out is NULL");
+    BSD_CHECK(L >= 2 && L <= 512, BSDMRG_EINVAL, "L out of range");
+    BSD_CHECK(n_alpha >= 0 && n_beta >= 0 && n_alpha <= L && n_beta <= L, BSDMRG_EINVAL,
+              "electron counts do not fit");
+    auto* x = new bsdmrg_ctx();
+    x->c.L = L;
+    x->c.na = n_alpha;
+    x->c.nb = n_beta;
+    x->c.target = {n_alpha, n_beta};
+    x->c.sites.resize(L);
+    make_vacuum_blocks(x->c);
+    *out = x;
+  });
+}
+
+int bsdmrg_destroy(bsdmrg_ctx* ctx) {
+  return guard([&] {
+    if (!ctx) return;
+    (void)hipDeviceSynchronize();
+    delete ctx;
+  });
+}
+
+int bsdmrg_load_integrals(bsdmrg_ctx* ctx, const double* h, const double* eri, double e_core) {
+  return guard([&] {
+    BSD_CHECK(ctx && h && eri, BSDMRG_EINVAL, "NULL argument");
+    BSD_CHECK(e_core == 0.0, BSDMRG_EINVAL, "only electronic energies (e_core = 0) are supported");
+    const int L = ctx->c.L;
+    const size_t n2 = (size_t)L * L, n4 = n2 * n2;
+    double mx = 0.0;
+    for (size_t i = 0; i < n4; ++i) {
+      BSD_CHECK(std::isfinite(eri[i]), BSDMRG_EINVAL, "non-finite integral");
+      mx = std::max(mx, std::fabs(eri[i]));
+    }
+    for (int p = 0; p < L; ++p)
+      for (int q = 0; q < L; ++q) {
+        BSD_CHECK(std::isfinite(h[p * L + q]) && std::fabs(h[p * L + q] - h[q * L + p]) <= 1e-12 * (1.0 + std::fabs(h[p * L + q])),
+                  BSDMRG_EINVAL, "h is not symmetric");
+      }
+    const double tol = 1e-12 * std::max(mx, 1e-300);
+    auto E = [&](int p, int q, int r, int s) { return eri[(((size_t)p * L + q) * L + r) * L + s]; };
+    for (int p = 0; p < L; ++p)
+      for (int q = 0; q < L; ++q)
+        for (int r = 0; r < L; ++r)
+          for (int s = 0; s < L; ++s) {
+            double v = E(p, q, r, s);
+            BSD_CHECK(std::fabs(v - E(q, p, r, s)) <= tol && std::fabs(v - E(p, q, s, r)) <= tol &&
+                          std::fabs(v - E(r, s, p, q)) <= tol,
+                      BSDMRG_EINVAL, "eri violates the 8-fold permutational symmetry");
+          }
+    ctx->c.ints.L = L;
+    ctx->c.ints.h.assign(h, h + n2);
+    ctx->c.ints.eri.assign(eri, eri + n4);
+    ctx->c.have_ints = true;
+    // blocks built from older integrals are stale
+    Ctx& c = ctx->c;
+    c.plans.clear();
+    c.left.clear();
+    c.right.clear();
+    make_vacuum_blocks(c);
+  });
+}
+
+int bsdmrg_set_site_tensor(bsdmrg_ctx* ctx, int site, int n_blocks, const int32_t* meta, const double* data) {
+  return guard([&] {
+    BSD_CHECK(ctx && meta && data, BSDMRG_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    BSD_CHECK(site >= 0 && site < c.L, BSDMRG_EINVAL, "site out of range");
+    BSD_CHECK(n_blocks > 0, BSDMRG_EINVAL, "no blocks");
+    SiteTensor T;
+    std::map<Q, int> ld, rd;
+    int64_t off = 0;
+    std::vector<SiteTensor::Blk> blks;
+    for (int b = 0; b < n_blocks; ++b) {
+      const int32_t* m = meta + 5 * b;
+      BSD_CHECK(m[2] >= 0 && m[2] < 4 && m[3] > 0 && m[4] > 0, BSDMRG_EINVAL, "bad block meta");
+      Q ql{m[0], m[1]};
+      Q qr = ql + kSiteQ[m[2]];
+      auto chk = [&](std::map<Q, int>& d, Q q, int v) {
+        auto it = d.find(q);
+        if (it == d.end()) d[q] = v;
+        else BSD_CHECK(it->second == v, BSDMRG_ESHAPE, "inconsistent bond sector dimension");
+      };
+      chk(ld, ql, m[3]);
+      chk(rd, qr, m[4]);
+      SiteTensor::Blk x;
+      x.s = m[2];
+      x.rows = m[3];
+      x.cols = m[4];
+      x.off = off;
+      off += (int64_t)m[3] * m[4];
+      blks.push_back(x);
+    }
+    for (auto& kv : ld) T.left.add(kv.first, kv.second);
+    for (auto& kv : rd) T.right.add(kv.first, kv.second);
+    for (int b = 0; b < n_blocks; ++b) {
+      const int32_t* m = meta + 5 * b;
+      Q ql{m[0], m[1]};
+      blks[b].l = T.left.find(ql);
+      blks[b].r = T.right.find(ql + kSiteQ[m[2]]);
+      BSD_CHECK(T.by_ls.find({blks[b].l, blks[b].s}) == T.by_ls.end(), BSDMRG_ESHAPE, "duplicate block");
+      T.by_ls[{blks[b].l, blks[b].s}] = b;
+    }
+    T.blocks = blks;
+    T.mem.reserve(std::max<int64_t>(off, 1) * sizeof(double));
+    BSD_HIP(hipMemcpy(T.mem.p, data, off * sizeof(double), hipMemcpyHostToDevice));
+    T.set = true;
+    c.sites[site] = std::move(T);
+    // blocks that depend on this site are stale
+    for (auto it = c.left.begin(); it != c.left.end();) it = it->first > site ? c.left.erase(it) : std::next(it);
+    for (auto it = c.right.begin(); it != c.right.end();) it = it->first <= site ? c.right.erase(it) : std::next(it);
+    c.plans.clear();
+  });
+}
+
+int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    Ctx& c = ctx->c;
+    BSD_CHECK(c.have_ints, BSDMRG_ESTATE, "integrals not loaded");
+    BSD_CHECK(bond >= 0 && bond <= c.L, BSDMRG_EINVAL, "bond out of range");
+    if (side == BSDMRG_LEFT) {
+      for (int b = 0; b < bond; ++b) {
+        if (get_block(c, true, b + 1)) continue;
+        BSD_CHECK(c.sites[b].set, BSDMRG_ESTATE, "site tensor missing");
+        Block* cur = get_block(c, true, b);
+        BSD_CHECK(cur && cur->resident, BSDMRG_EBUSY, "source block not resident");
+        renormalize_left_block(c, b, S(stream));
+      }
+    } else {
+      BSD_CHECK(side == BSDMRG_RIGHT, BSDMRG_EINVAL, "side must be LEFT or RIGHT");
+      for (int b = c.L; b > bond; --b) {
+        if (get_block(c, false, b - 1)) continue;
+        BSD_CHECK(c.sites[b - 1].set, BSDMRG_ESTATE, "site tensor missing");
+        Block* cur = get_block(c, false, b);
+        BSD_CHECK(cur && cur->resident, BSDMRG_EBUSY, "source block not resident");
+        renormalize_right_block(c, b, S(stream));
+      }
+    }
+    BSD_HIP(hipStreamSynchronize(S(stream)));
+  });
+}
+
+static HpsiPlan* get_plan(Ctx& c, int site, int precision, size_t ws, hipStream_t s, bool rebuild) {
+  BSD_CHECK(site >= 0 && site + 1 < c.L, BSDMRG_EINVAL, "site out of range");
+  BSD_CHECK(precision == BSDMRG_FP64, BSDMRG_EINVAL, "unsupported precision");
+  auto key = std::make_pair(site, precision);
+  auto it = c.plans.find(key);
+  if (it != c.plans.end() && !rebuild) return it->second.get();
+  if (ws == 0) ws = (size_t)4 << 30;
+  auto p = build_hpsi_plan(c, site, precision, ws, s);
+  HpsiPlan* raw = p.get();
+  c.plans[key] = std::move(p);
+  return raw;
+}
+
+int bsdmrg_psi_layout(bsdmrg_ctx* ctx, int site, int* n_blocks, int64_t* n_elems, int32_t* meta, int64_t* offsets) {
+  return guard([&] {
+    BSD_CHECK(ctx && n_blocks && n_elems, BSDMRG_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    BSD_CHECK(site >= 0 && site + 1 < c.L, BSDMRG_EINVAL, "site out of range");
+    Block* Lb = get_block(c, true, site);
+    Block* Rb = get_block(c, false, site + 2);
+    BSD_CHECK(Lb && Rb, BSDMRG_ESTATE, "environment blocks not built");
+    PsiLayout lay;
+    SiteSet C = make_siteset(site, 2);
+    build_psi_layout(*Lb, *Rb, C, c.target, lay);
+    *n_blocks = (int)lay.blocks.size();
+    *n_elems = lay.n_elems;
+    if (!meta) return;
+    BSD_CHECK(offsets != nullptr, BSDMRG_EINVAL, "offsets is NULL");
+    for (size_t b = 0; b < lay.blocks.size(); ++b) {
+      const PsiBlk& x = lay.blocks[b];
+      Q ql = Lb->basis.q[x.l];
+      Q qr = c.target - Rb->basis.q[x.r];
+      int32_t* m = meta + 8 * b;
+      m[0] = ql.a;
+      m[1] = ql.b;
+      m[2] = x.c / 4;
+      m[3] = x.c % 4;
+      m[4] = qr.a;
+      m[5] = qr.b;
+      m[6] = x.rows;
+      m[7] = x.cols;
+      offsets[b] = x.off;
+    }
+  });
+}
+
+int bsdmrg_hpsi_prepare(bsdmrg_ctx* ctx, int site, int precision, size_t ws_bytes, bsdmrg_stream_t stream) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    get_plan(ctx->c, site, precision, ws_bytes, S(stream), true);
+    BSD_HIP(hipStreamSynchronize(S(stream)));
+  });
+}
+
+int bsdmrg_hpsi(bsdmrg_ctx* ctx, int site, const double* psi, double* out, int precision, bsdmrg_stream_t stream) {
+  return guard([&] {
+    BSD_CHECK(ctx && psi && out, BSDMRG_EINVAL, "NULL argument");
+    BSD_CHECK(psi != out, BSDMRG_EINVAL, "psi and out must not alias");
+    HpsiPlan* p = get_plan(ctx->c, site, precision, 0, S(stream), false);
+    Block* Lb = get_block(ctx->c, true, site);
+    Block* Rb = get_block(ctx->c, false, site + 2);
+    BSD_CHECK(Lb && Rb && Lb->resident && Rb->resident, BSDMRG_EBUSY, "environment blocks not resident");
+    const double* pe = psi + p->lay.n_elems;
+    BSD_CHECK(!(out < pe && psi < out + p->lay.n_elems), BSDMRG_EINVAL, "psi and out overlap");
+    run_hpsi(*p, psi, out, S(stream));
+    ctx->c.last_hpsi_flops = p->useful_flops;
+  });
+}
+
+int bsdmrg_hpsi_info(bsdmrg_ctx* ctx, int site, int precision, double* flops, int64_t* n_channels,
+                     int64_t* n_segments, int64_t* n_aggregates, int64_t* ws_bytes) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    auto it = ctx->c.plans.find({site, precision});
+    BSD_CHECK(it != ctx->c.plans.end(), BSDMRG_ESTATE, "product not prepared");
+    const HpsiPlan& p = *it->second;
+    if (flops) *flops = p.useful_flops;
+    if (n_channels) *n_channels = p.nchannels;
+    if (n_segments) *n_segments = (int64_t)p.nseg;
+    if (n_aggregates) *n_aggregates = p.naggs;
+    if (ws_bytes) *ws_bytes = (int64_t)(p.agg_bytes + p.v_bytes);
+  });
+}
+
+int bsdmrg_get_block_op(bsdmrg_ctx* ctx, int side, int bond, char kind, int p, int q, int* n_blocks,
+                        int64_t* n_elems, int32_t* meta, double* data) {
+  return guard([&] {
+    BSD_CHECK(ctx && n_blocks && n_elems, BSDMRG_EINVAL, "NULL argument");
+    Block* b = need_block(ctx->c, side, bond);
+    BSD_CHECK(b->resident, BSDMRG_EBUSY, "block not resident");
+    OpKey k;
+    k.kind = kind;
+    k.p = p;
+    k.q = q;
+    auto it = b->ops.find(k);
+    BSD_CHECK(it != b->ops.end(), BSDMRG_ESTATE, "operator not stored in this block");
+    const Family& f = b->fams[it->second.fam];
+    int64_t ne = 0;
+    for (auto& sb : f.sk.blocks) ne += (int64_t)sb.rows * sb.cols;
+    *n_blocks = (int)f.sk.blocks.size();
+    *n_elems = ne;
+    if (!data) return;
+    BSD_CHECK(meta != nullptr, BSDMRG_EINVAL, "meta is NULL");
+    std::vector<double> tmp(f.sk.layer_stride);
+    BSD_HIP(hipMemcpy(tmp.data(), f.dev + (int64_t)it->second.layer * f.sk.layer_stride,
+                      f.sk.layer_stride * sizeof(double), hipMemcpyDeviceToHost));
+    int64_t o = 0;
+    for (size_t i = 0; i < f.sk.blocks.size(); ++i) {
+      const SkBlock& sb = f.sk.blocks[i];
+      Q qi = b->basis.q[sb.in], qo = b->basis.q[sb.out];
+      int32_t* m = meta + 6 * i;
+      m[0] = qi.a;
+      m[1] = qi.b;
+      m[2] = qo.a;
+      m[3] = qo.b;
+      m[4] = sb.rows;
+      m[5] = sb.cols;
+      for (int r = 0; r < sb.rows; ++r)
+        for (int cc = 0; cc < sb.cols; ++cc) data[o++] = tmp[sb.off + (int64_t)r * sb.ld + cc];
+    }
+  });
+}
+
+int bsdmrg_block_gemm(int n, const bsdmrg_gemm_desc* probs, bsdmrg_stream_t stream) {
+  return guard([&] {
+    BSD_CHECK(n >= 0 && (n == 0 || probs), BSDMRG_EINVAL, "bad problem list");
+    std::vector<GemmProblem> v;
+    for (int i = 0; i < n; ++i) {
+      const auto& d = probs[i];
+      BSD_CHECK(d.M >= 0 && d.N >= 0 && d.K >= 0, BSDMRG_EINVAL, "negative sizes");
+      if (d.M == 0 || d.N == 0) continue;
+      BSD_CHECK(d.C && (d.K == 0 || (d.A && d.B)), BSDMRG_EINVAL, "NULL matrix");
+      BSD_CHECK(d.ldc >= d.N, BSDMRG_EINVAL, "ldc too small");
+      BSD_CHECK(d.K == 0 || d.lda >= (d.transA ? d.M : d.K), BSDMRG_EINVAL, "lda too small");
+      BSD_CHECK(d.K == 0 || d.ldb >= (d.transB ? d.K : d.N), BSDMRG_EINVAL, "ldb too small");
+      GemmProblem g;
+      g.C = tag_ptr(0, (uint64_t)d.C);
+      g.ldc = d.ldc;
+      g.M = d.M;
+      g.N = d.N;
+      g.beta = d.beta;
+      if (d.K > 0) {
+        GSeg sg;
+        sg.A = tag_ptr(0, (uint64_t)d.A);
+        sg.B = tag_ptr(0, (uint64_t)d.B);
+        sg.lda = d.lda;
+        sg.ldb = d.ldb;
+        sg.K = d.K;
+        sg.flags = (d.transA ? kTransA : 0) | (d.transB ? kTransB : 0);
+        sg.alpha = d.alpha;
+        g.segs.push_back(sg);
+      }
+      v.push_back(std::move(g));
+    }
+    GemmPlan plan;
+    plan.build(v);
+    GBases b{{0, 0, 0, 0}};
+    plan.launch(b, S(stream));
+    BSD_HIP(hipStreamSynchronize(S(stream)));
+  });
+}
+
+int bsdmrg_serialized_size_desc(int n, const bsdmrg_family_desc* fams, size_t* bytes) {
+  return guard([&] {
+    BSD_CHECK(bytes, BSDMRG_EINVAL, "NULL bytes");
+    *bytes = serialized_size(desc_views(n, fams));
+  });
+}
+
+int bsdmrg_pack_desc(int n, const bsdmrg_family_desc* fams, void* dst, size_t cap, bsdmrg_stream_t stream) {
+  return guard([&] {
+    BSD_CHECK(dst, BSDMRG_EINVAL, "NULL destination");
+    auto v = desc_views(n, fams);
+    BSD_CHECK(cap >= serialized_size(v), BSDMRG_ENOMEM, "destination smaller than the serialized size");
+    auto plan = serial_plan(v, S(stream));
+    serial_pack(*plan, dst, cap, S(stream));
+    BSD_HIP(hipStreamSynchronize(S(stream)));
+  });
+}
+
+int bsdmrg_unpack_desc(int n, const bsdmrg_family_desc* fams, const void* src, size_t bytes, bsdmrg_stream_t stream) {
+  return guard([&] {
+    BSD_CHECK(src, BSDMRG_EINVAL, "NULL source");
+    auto v = desc_views(n, fams);
+    BSD_CHECK(bytes == serialized_size(v), BSDMRG_ECORRUPT, "stream size does not match the families");
+    auto plan = serial_plan(v, S(stream));
+    serial_unpack(*plan, src, bytes, S(stream));
+    int st = serial_status(*plan, S(stream));
+    BSD_CHECK(st == 0, BSDMRG_ECORRUPT, "stream tables do not match the families");
+  });
+}
+
+int bsdmrg_serialized_size(bsdmrg_ctx* ctx, int side, int bond, size_t* bytes) {
+  return guard([&] {
+    BSD_CHECK(ctx && bytes, BSDMRG_EINVAL, "NULL argument");
+    Block* b = need_block(ctx->c, side, bond);
+    *bytes = serialized_size(block_views(*b, b->left));
+  });
+}
+
+int bsdmrg_pack(bsdmrg_ctx* ctx, int side, int bond, void* dst, size_t cap, bsdmrg_stream_t stream) {
+  return guard([&] {
+    BSD_CHECK(ctx && dst, BSDMRG_EINVAL, "NULL argument");
+    Block* b = need_block(ctx->c, side, bond);
+    BSD_CHECK(b->resident, BSDMRG_EBUSY, "block not resident");
+    ensure_splan(*b, S(stream));
+    serial_pack(*b->splan, dst, cap, S(stream));
+    BSD_HIP(hipStreamSynchronize(S(stream)));
+  });
+}
+
+int bsdmrg_unpack(bsdmrg_ctx* ctx, int side, int bond, const void* src, size_t bytes, bsdmrg_stream_t stream) {
+  return guard([&] {
+    BSD_CHECK(ctx && src, BSDMRG_EINVAL, "NULL argument");
+    Block* b = need_block(ctx->c, side, bond);
+    BSD_CHECK(!b->offload_pending, BSDMRG_EBUSY, "offload in flight; wait first");
+    if (!b->resident) realloc_block(*b, S(stream));
+    ensure_splan(*b, S(stream));
+    BSD_CHECK(bytes == serial_bytes(*b->splan), BSDMRG_ECORRUPT, "stream size does not match the block");
+    serial_unpack(*b->splan, src, bytes, S(stream));
+    int st = serial_status(*b->splan, S(stream));
+    BSD_CHECK(st == 0, BSDMRG_ECORRUPT, "stream tables do not match the block");
+    ctx->c.plans.clear();
+  });
+}
+
+int bsdmrg_offload(bsdmrg_ctx* ctx, int side, int bond, void* staging, void* pinned, size_t cap, int release,
+                   bsdmrg_stream_t compute, bsdmrg_stream_t side_stream) {
+  return guard([&] {
+    BSD_CHECK(ctx && staging && pinned, BSDMRG_EINVAL, "NULL argument");
+    Block* b = need_block(ctx->c, side, bond);
+    BSD_CHECK(b->resident, BSDMRG_EBUSY, "block not resident");
+    BSD_CHECK(!b->offload_pending, BSDMRG_EBUSY, "previous offload still pending");
+    ensure_splan(*b, S(compute));
+    const size_t bytes = serial_bytes(*b->splan);
+    BSD_CHECK(cap >= bytes, BSDMRG_ENOMEM, "buffers smaller than the serialized size");
+    serial_pack(*b->splan, staging, cap, S(compute));
+    hipEvent_t packed;
+    BSD_HIP(hipEventCreateWithFlags(&packed, hipEventDisableTiming));
+    BSD_HIP(hipEventRecord(packed, S(compute)));
+    BSD_HIP(hipStreamWaitEvent(S(side_stream), packed, 0));
+    BSD_HIP(hipMemcpyAsync(pinned, staging, bytes, hipMemcpyDeviceToHost, S(side_stream)));
+    if (!b->offload_done) BSD_HIP(hipEventCreateWithFlags(&b->offload_done, hipEventDisableTiming));
+    BSD_HIP(hipEventRecord(b->offload_done, S(side_stream)));
+    BSD_HIP(hipEventDestroy(packed));
+    b->offload_pending = true;
+    b->release_after = release != 0;
+  });
+}
+
+int bsdmrg_offload_wait(bsdmrg_ctx* ctx, int side, int bond, double* waited) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    Block* b = need_block(ctx->c, side, bond);
+    auto t0 = std::chrono::steady_clock::now();
+    if (b->offload_pending) BSD_HIP(hipEventSynchronize(b->offload_done));
+    auto t1 = std::chrono::steady_clock::now();
+    if (waited) *waited = std::chrono::duration<double>(t1 - t0).count();
+    if (b->offload_pending && b->release_after) {
+      b->mem.clear();
+      for (auto& f : b->fams) f.dev = nullptr;
+      b->splan.reset();
+      b->resident = false;
+      // plans referencing this block are stale
+      ctx->c.plans.clear();
+    }
+    b->offload_pending = false;
+  });
+}
+
+int bsdmrg_prefetch(bsdmrg_ctx* ctx, int side, int bond, const void* pinned, void* staging, size_t bytes,
+                    bsdmrg_stream_t compute, bsdmrg_stream_t side_stream) {
+  return guard([&] {
+    BSD_CHECK(ctx && pinned && staging, BSDMRG_EINVAL, "NULL argument");
+    Block* b = need_block(ctx->c, side, bond);
+    BSD_CHECK(!b->offload_pending, BSDMRG_EBUSY, "offload in flight; wait first");
+    int st = validate_stream_host(block_views(*b, b->left), pinned, bytes);
+    BSD_CHECK(st == 0, BSDMRG_ECORRUPT, "host stream does not match the block");
+    const bool realloc = !b->resident;
+    if (realloc) realloc_block(*b, S(compute));
+    ensure_splan(*b, S(compute));   // descriptors first: no host wait after the copy is queued
+    BSD_HIP(hipMemcpyAsync(staging, pinned, bytes, hipMemcpyHostToDevice, S(side_stream)));
+    hipEvent_t loaded;
+    BSD_HIP(hipEventCreateWithFlags(&loaded, hipEventDisableTiming));
+    BSD_HIP(hipEventRecord(loaded, S(side_stream)));
+    BSD_HIP(hipStreamWaitEvent(S(compute), loaded, 0));
+    serial_unpack(*b->splan, staging, bytes, S(compute));
+    BSD_HIP(hipEventDestroy(loaded));
+    if (realloc) ctx->c.plans.clear();
+  });
+}
+
+int bsdmrg_block_bytes(bsdmrg_ctx* ctx, int side, int bond, size_t* bytes) {
+  return guard([&] {
+    BSD_CHECK(ctx && bytes, BSDMRG_EINVAL, "NULL argument");
+    Block* b = need_block(ctx->c, side, bond);
+    *bytes = b->resident ? b->device_bytes() : 0;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,45 @@
+// Library context: integrals, MPS site tensors and renormalized blocks.
+#pragma once
+#include "internal.h"
+
+namespace bsd {
+
+// One MPS site tensor on the device: blocks (q_left, s) of shape
+// d_left(q_left) x d_right(q_left + q_s), bond labels, row-major compact.
+struct SiteTensor {
+  bool set = false;
+  Basis left, right;         // bond labels
+  struct Blk {
+    int l, r, s;             // basis indices and local state
+    int rows, cols;
+    int64_t off;             // element offset in dev
+  };
+  std::vector<Blk> blocks;
+  std::map<std::pair<int, int>, int> by_ls;   // (left index, s) -> block
+  DevBuf mem;
+  const double* ptr(int b) const { return static_cast<const double*>(mem.p) + blocks[b].off; }
+};
+
+struct HpsiPlan;
+
+struct Ctx {
+  int L = 0, na = 0, nb = 0;
+  Q target;
+  Integrals ints;
+  bool have_ints = false;
+  std::vector<SiteTensor> sites;
+  std::map<int, std::unique_ptr<Block>> left, right;   // keyed by bond
+  std::map<std::pair<int, int>, std::shared_ptr<HpsiPlan>> plans;  // (site, precision)
+  DevBuf ws;                 // scratch for renormalization
+  // statistics
+  double last_hpsi_flops = 0.0;
+  double renorm_flops = 0.0;
+  ~Ctx();
+};
+
+void renormalize_left_block(Ctx& ctx, int bond, hipStream_t s);   // bond -> bond+1
+void renormalize_right_block(Ctx& ctx, int bond, hipStream_t s);  // bond -> bond-1
+void make_vacuum_blocks(Ctx& ctx);
+Block* get_block(Ctx& ctx, bool left, int bond);
+
+}  // namespace bsd

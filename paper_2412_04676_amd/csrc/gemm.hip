@@ -1,0 +1,191 @@
+// Grouped block GEMM on CDNA4 FP64 matrix cores.
+//
+// One workgroup computes one output tile of one output matrix:
+//   C_tile = beta C_tile + sum_seg alpha_seg op(A_seg)[tile rows, 0:K_seg] op(B_seg)[0:K_seg, tile cols]
+// so a block of the effective-Hamiltonian product, a renormalized operator
+// block, or a projected block is one "tile list + K-segment list" entry and
+// every uneven sector GEMM of one phase runs in a single launch.  Operands are
+// staged through LDS in K-slices of 16; each wave owns a 32x32 sub-tile made of
+// 2x2 v_mfma_f64_16x16x4 accumulators.
+#include "internal.h"
+
+namespace bsd {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ const double* resolve(uint64_t t, const GBases& b) {
+  return reinterpret_cast<const double*>(b.b[t >> kTagShift] + (t & ((1ull << kTagShift) - 1)));
+}
+
+constexpr int KB = 16;
+
+template <int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN)
+grouped_gemm_kernel(const GTile* __restrict__ tiles, const GSeg* __restrict__ segs, GBases bases) {
+  constexpr int TM = 32 * WM, TN = 32 * WN, NT = 64 * WM * WN;
+  __shared__ double As[TM][KB + 1];
+  __shared__ double Bs[KB][TN + 1];
+
+  const GTile tile = tiles[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = (wave / WN) * 32;
+  const int wc = (wave % WN) * 32;
+  const int mt = min(TM, tile.M - tile.m0);
+  const int nt = min(TN, tile.N - tile.n0);
+
+  double4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+
+  for (int sidx = 0; sidx < tile.nseg; ++sidx) {
+    const GSeg sg = segs[tile.seg0 + sidx];
+    const double* A = resolve(sg.A, bases);
+    const double* B = resolve(sg.B, bases);
+    const bool ta = sg.flags & kTransA, tb = sg.flags & kTransB, ia = sg.flags & kIdentA;
+    const double alpha = sg.alpha;
+    for (int k0 = 0; k0 < sg.K; k0 += KB) {
+      // stage op(A)[m0 + i][k0 + k] * alpha
+      for (int e = tid; e < TM * KB; e += NT) {
+        int i, k;
+        if (ta) { k = e / TM; i = e % TM; } else { i = e / KB; k = e % KB; }
+        const int gi = tile.m0 + i, gk = k0 + k;
+        double v = 0.0;
+        if (i < mt && gk < sg.K) {
+          if (ia) v = (gi == gk) ? alpha : 0.0;
+          else v = alpha * (ta ? A[(int64_t)gk * sg.lda + gi] : A[(int64_t)gi * sg.lda + gk]);
+        }
+        As[i][k] = v;
+      }
+      // stage op(B)[k0 + k][n0 + j]
+      for (int e = tid; e < KB * TN; e += NT) {
+        int j, k;
+        if (tb) { j = e / KB; k = e % KB; } else { k = e / TN; j = e % TN; }
+        const int gj = tile.n0 + j, gk = k0 + k;
+        double v = 0.0;
+        if (j < nt && gk < sg.K) v = tb ? B[(int64_t)gj * sg.ldb + gk] : B[(int64_t)gk * sg.ldb + gj];
+        Bs[k][j] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < KB; kk += 4) {
+        double a[2], b[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) a[i] = As[wr + i * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) b[j] = Bs[kk + (lane >> 4)][wc + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  double* C = const_cast<double*>(resolve(tile.C, bases));
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wr + i * 16 + 4 * (lane >> 4) + v;
+        const int c = wc + j * 16 + (lane & 15);
+        if (r < mt && c < nt) {
+          double* p = C + (int64_t)(tile.m0 + r) * tile.ldc + (tile.n0 + c);
+          double x = acc[i][j][v];
+          if (tile.beta != 0.0) x += tile.beta * (*p);
+          *p = x;
+        }
+      }
+}
+
+void launch_grouped_gemm(const GTile* tiles, int ntiles, int tile, const GSeg* segs,
+                         const GBases& b, hipStream_t s) {
+  if (ntiles <= 0) return;
+  if (tile == 64)
+    hipLaunchKernelGGL((grouped_gemm_kernel<2, 2>), dim3(ntiles), dim3(256), 0, s, tiles, segs, b);
+  else
+    hipLaunchKernelGGL((grouped_gemm_kernel<1, 1>), dim3(ntiles), dim3(64), 0, s, tiles, segs, b);
+  BSD_HIP(hipGetLastError());
+}
+
+// out = sum_t coef_t op(in_t); one workgroup per output block
+__global__ void __launch_bounds__(256)
+aggregate_kernel(const AggTask* __restrict__ tasks, const AggTerm* __restrict__ terms) {
+  const AggTask t = tasks[blockIdx.x];
+  const int n = t.rows * t.cols;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int r = e / t.cols, c = e % t.cols;
+    double acc = 0.0;
+    for (int k = 0; k < t.nt; ++k) {
+      const AggTerm a = terms[t.t0 + k];
+      double v;
+      if (a.flags & kIdentA) v = (r == c) ? 1.0 : 0.0;
+      else if (a.flags & kTransA) v = a.in[(int64_t)c * a.ldi + r];
+      else v = a.in[(int64_t)r * a.ldi + c];
+      acc += a.coef * v;
+    }
+    t.out[(int64_t)r * t.ldo + c] = acc;
+  }
+}
+
+void launch_aggregate(const AggTask* tasks, const AggTerm* terms, int ntasks, hipStream_t s) {
+  if (ntasks <= 0) return;
+  hipLaunchKernelGGL(aggregate_kernel, dim3(ntasks), dim3(256), 0, s, tasks, terms);
+  BSD_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- plan building (host)
+void GemmPlan::build(const std::vector<GemmProblem>& probs) {
+  std::vector<GTile> t64, t32;
+  std::vector<GSeg> sg;
+  flops = 0.0;
+  for (const auto& p : probs) {
+    if (p.M <= 0 || p.N <= 0) continue;
+    int seg0 = (int)sg.size();
+    for (const auto& s : p.segs) {
+      if (s.K <= 0) continue;
+      sg.push_back(s);
+      flops += 2.0 * p.M * (double)p.N * s.K;
+    }
+    int nseg = (int)sg.size() - seg0;
+    const bool small = p.M <= 32 && p.N <= 32;
+    const int T = small ? 32 : 64;
+    for (int m0 = 0; m0 < p.M; m0 += T)
+      for (int n0 = 0; n0 < p.N; n0 += T) {
+        GTile t;
+        t.C = p.C;
+        t.ldc = p.ldc;
+        t.M = p.M;
+        t.N = p.N;
+        t.m0 = m0;
+        t.n0 = n0;
+        t.seg0 = seg0;
+        t.nseg = nseg;
+        t.beta = p.beta;
+        (small ? t32 : t64).push_back(t);
+      }
+  }
+  ntiles64 = (int)t64.size();
+  ntiles32 = (int)t32.size();
+  std::vector<GTile> all = t64;
+  all.insert(all.end(), t32.begin(), t32.end());
+  tiles.reserve(std::max<size_t>(1, all.size()) * sizeof(GTile));
+  segs.reserve(std::max<size_t>(1, sg.size()) * sizeof(GSeg));
+  if (!all.empty()) BSD_HIP(hipMemcpy(tiles.p, all.data(), all.size() * sizeof(GTile), hipMemcpyHostToDevice));
+  if (!sg.empty()) BSD_HIP(hipMemcpy(segs.p, sg.data(), sg.size() * sizeof(GSeg), hipMemcpyHostToDevice));
+}
+
+void GemmPlan::launch(const GBases& bases, hipStream_t s) const {
+  const GTile* t = static_cast<const GTile*>(tiles.p);
+  const GSeg* g = static_cast<const GSeg*>(segs.p);
+  launch_grouped_gemm(t, ntiles64, 64, g, bases, s);
+  launch_grouped_gemm(t + ntiles64, ntiles32, 32, g, bases, s);
+}
+
+}  // namespace bsd

@@ -1,0 +1,479 @@
+// Effective-Hamiltonian product H.psi for the two-site superblock L . C . R
+// (C = sites i, i+1 treated exactly; Sec. II.B step 2).
+//
+// The Hamiltonian is split as X = L . C | Y = R with the partition rule of the
+// operator algebra, so every term is (operator on L . C) (x) (operator on R).
+// Operators on R are the stored complementary set (or the identity); the
+// operator on L . C of each R "channel" is expanded into groups
+// (aggregated L operator) (x) (16 x 16 matrix on C).  With psi stored as one
+// tall matrix per right sector (all (q_l, c) blocks stacked), each channel b is
+//   phase 1:  V_b = Psi R_b^T                  (one GEMM per right sector)
+//   phase 2:  Phi[l', c', r'] += sum alpha Lambda[l' <- l] V_b[(l, c), r']
+// where phase 2 concatenates the K dimension over all channels, groups and
+// local transitions c -> c' that feed one output block.  The sign of a
+// contribution is (-1)^{|M| n_l + |R_b| (n_l + n_c)} (graded tensor product).
+#include "hpsi.h"
+
+#include <algorithm>
+
+namespace bsd {
+
+namespace {
+
+struct LRef {
+  int kind;      // 0 stored, 1 identity, 2 aggregate
+  OpKey key;
+  bool trans = false;
+  int agg = -1;
+  Q dq;
+};
+
+OpKey mk(char k, int p = -1, int q = -1) {
+  OpKey o;
+  o.kind = k;
+  o.p = p;
+  o.q = q;
+  return o;
+}
+
+std::vector<Group> scale_groups(std::vector<Group> g, double c) {
+  for (auto& x : g)
+    for (auto& t : x.terms) t.coef *= c;
+  return g;
+}
+
+}  // namespace
+
+__global__ void zero_fill_kernel(double* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+void zero_fill(double* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  int grid = (int)std::min<int64_t>(4096, (n + 255) / 256);
+  hipLaunchKernelGGL(zero_fill_kernel, dim3(grid), dim3(256), 0, s, p, n);
+  BSD_HIP(hipGetLastError());
+}
+
+void build_psi_layout(const Block& Lb, const Block& Rb, const SiteSet& C, const Q& target,
+                      PsiLayout& lay) {
+  lay.blocks.clear();
+  lay.stack_off.assign(Rb.basis.q.size(), -1);
+  lay.stack_rows.assign(Rb.basis.q.size(), 0);
+  int64_t off = 0;
+  for (int r = 0; r < (int)Rb.basis.q.size(); ++r) {
+    int rows = 0;
+    int64_t base = off;
+    for (int l = 0; l < (int)Lb.basis.q.size(); ++l)
+      for (int c = 0; c < 16; ++c) {
+        if (Lb.basis.q[l] + C.q[c] + Rb.basis.q[r] != target) continue;
+        PsiBlk b;
+        b.l = l;
+        b.c = c;
+        b.r = r;
+        b.rows = Lb.basis.dim[l];
+        b.cols = Rb.basis.dim[r];
+        b.off = off;
+        b.row_in_stack = rows;
+        lay.index[{l, c, r}] = (int)lay.blocks.size();
+        lay.blocks.push_back(b);
+        off += (int64_t)b.rows * b.cols;
+        rows += b.rows;
+      }
+    if (rows > 0) {
+      lay.stack_off[r] = base;
+      lay.stack_rows[r] = rows;
+    }
+  }
+  lay.n_elems = off;
+}
+
+static Operand2 lref_block(const Block& Lb, const LRef& r, const std::vector<Skeleton>& agg_sk,
+                           const std::vector<int64_t>& agg_off, const double* agg_mem, int in_idx) {
+  Operand2 o;
+  const Basis& bs = Lb.basis;
+  int out_idx = bs.find(bs.q[in_idx] + r.dq);
+  if (out_idx < 0) return o;
+  o.out = out_idx;
+  if (r.kind == 1) {
+    o.ident = true;
+    o.ok = true;
+    return o;
+  }
+  if (r.kind == 2) {
+    int b = agg_sk[r.agg].by_in[in_idx];
+    if (b < 0) return o;
+    const SkBlock& sb = agg_sk[r.agg].blocks[b];
+    o.p = agg_mem + agg_off[r.agg] + sb.off;
+    o.ld = sb.ld;
+    o.ok = true;
+    return o;
+  }
+  int rr, cc, ld;
+  const double* p = r.trans ? Lb.op_block(r.key, out_idx, &rr, &cc, &ld) : Lb.op_block(r.key, in_idx, &rr, &cc, &ld);
+  if (!p) return o;
+  o.p = p;
+  o.ld = ld;
+  o.trans = r.trans;
+  o.ok = true;
+  return o;
+}
+
+std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, size_t ws_budget,
+                                          hipStream_t s) {
+  BSD_CHECK(precision == 0, 1, "only the float64 path is available");
+  Block* Lb = get_block(ctx, true, site);
+  Block* Rb = get_block(ctx, false, site + 2);
+  BSD_CHECK(Lb && Rb, 1, "environment blocks for this site are not built");
+  BSD_CHECK(Lb->resident && Rb->resident, 6, "environment block is offloaded");
+  const SiteSet C = make_siteset(site, 2);
+  const int nL = 2 * site;
+  const int r0 = 2 * (site + 2), NM = 2 * ctx.L;
+  auto plan = std::make_unique<HpsiPlan>();
+  plan->site = site;
+  plan->precision = precision;
+  build_psi_layout(*Lb, *Rb, C, ctx.target, plan->lay);
+  const PsiLayout& lay = plan->lay;
+
+  // ---------------------------------------------------------------- channels
+  struct Chan {
+    int rkind;       // 0 stored, 1 identity
+    OpKey rkey;
+    bool rtrans = false;
+    Q rdq;
+    std::vector<Group> groups;
+  };
+  std::vector<Chan> chans;
+  auto add = [&](int rkind, OpKey rkey, bool rtrans, std::vector<Group> g) {
+    if (g.empty()) return;
+    if (rkind == 0 && Rb->ops.find(rkey) == Rb->ops.end()) return;
+    Chan c;
+    c.rkind = rkind;
+    c.rkey = rkey;
+    c.rtrans = rtrans;
+    Q dq = rkind == 1 ? Q{0, 0} : key_dq(rkey, false);
+    c.rdq = rtrans ? -dq : dq;
+    c.groups = std::move(g);
+    chans.push_back(std::move(c));
+  };
+  const Mat I16 = mat_eye(16);
+  add(1, mk('I'), false, expand_left(mk('H'), nL, C, ctx.ints));
+  {
+    Group g;
+    g.M = I16;
+    g.terms.push_back({1.0, mk('I'), false});
+    add(0, mk('H'), false, {g});
+  }
+  for (int x = 0; x < r0; ++x) {
+    auto g = expand_left(mk('c', x), nL, C, ctx.ints);
+    add(0, mk('S', x), false, g);
+    add(0, mk('S', x), true, scale_groups(transpose_groups(g, C, 1), -1.0));
+  }
+  for (int r = r0; r < NM; ++r) {
+    auto g = expand_left(mk('S', r), nL, C, ctx.ints);
+    add(0, mk('c', r), true, g);
+    add(0, mk('c', r), false, scale_groups(transpose_groups(g, C, 1), -1.0));
+  }
+  for (int p = 0; p < r0; ++p)
+    for (int q = p + 1; q < r0; ++q) {
+      auto g = expand_left(mk('A', p, q), nL, C, ctx.ints);
+      add(0, mk('P', p, q), false, g);
+      add(0, mk('P', p, q), true, transpose_groups(g, C, 0));
+    }
+  for (int p = 0; p < r0; ++p)
+    for (int q = 0; q < r0; ++q) add(0, mk('Q', p, q), false, expand_left(mk('B', p, q), nL, C, ctx.ints));
+
+  // ---------------------------------------------------------------- L-side references
+  std::vector<LRef> lrefs;
+  std::map<std::tuple<int, char, int, int, bool>, int> lidx;
+  std::vector<Skeleton> agg_sk;
+  std::vector<int64_t> agg_off;
+  std::vector<std::vector<Term>> agg_terms;
+  int64_t agg_elems = 0;
+  struct G2 {
+    int lref;
+    double coef;
+    Mat M;
+    int mpar;
+  };
+  std::vector<std::vector<G2>> cgroups(chans.size());
+  for (size_t ci = 0; ci < chans.size(); ++ci) {
+    Q total_dq = -chans[ci].rdq;
+    for (auto& g : chans[ci].groups) {
+      Q ldq;
+      int mpar = -1;
+      for (int a = 0; a < 16 && mpar < 0; ++a)
+        for (int b = 0; b < 16; ++b)
+          if (g.M(a, b) != 0.0) {
+            ldq = C.q[a] - C.q[b];
+            mpar = ldq.parity();
+            break;
+          }
+      if (mpar < 0) continue;
+      Q bdq = total_dq - ldq;
+      std::vector<Term> kept;
+      for (auto& t : g.terms) {
+        if (t.key.kind != 'I' && Lb->ops.find(t.key) == Lb->ops.end()) continue;
+        Q tdq = t.key.kind == 'I' ? Q{0, 0} : key_dq(t.key, true);
+        if (t.trans) tdq = -tdq;
+        BSD_CHECK(tdq == bdq, 1, "inconsistent dq in H.psi expansion");
+        kept.push_back(t);
+      }
+      if (kept.empty()) continue;
+      G2 g2;
+      g2.M = g.M;
+      g2.mpar = mpar;
+      if (kept.size() == 1) {
+        const Term& t = kept[0];
+        int kind = t.key.kind == 'I' ? 1 : 0;
+        auto id = std::make_tuple(kind, t.key.kind, t.key.p, t.key.q, t.trans);
+        auto it = lidx.find(id);
+        if (it == lidx.end()) {
+          LRef r;
+          r.kind = kind;
+          r.key = t.key;
+          r.trans = t.trans;
+          r.dq = bdq;
+          lidx[id] = (int)lrefs.size();
+          g2.lref = (int)lrefs.size();
+          lrefs.push_back(r);
+        } else {
+          g2.lref = it->second;
+        }
+        g2.coef = t.coef;
+      } else {
+        LRef r;
+        r.kind = 2;
+        r.agg = (int)agg_sk.size();
+        r.dq = bdq;
+        agg_sk.push_back(make_skeleton(Lb->basis, Lb->basis, bdq));
+        agg_off.push_back(agg_elems);
+        agg_elems += agg_sk.back().layer_stride;
+        agg_terms.push_back(kept);
+        g2.lref = (int)lrefs.size();
+        lrefs.push_back(r);
+        g2.coef = 1.0;
+      }
+      cgroups[ci].push_back(std::move(g2));
+    }
+  }
+  plan->agg.reserve(std::max<int64_t>(1, agg_elems) * sizeof(double));
+  double* agg_mem = static_cast<double*>(plan->agg.p);
+  plan->agg_bytes = agg_elems * sizeof(double);
+  {
+    std::vector<AggTask> tasks;
+    std::vector<AggTerm> terms;
+    for (size_t a = 0; a < agg_sk.size(); ++a)
+      for (const auto& sb : agg_sk[a].blocks) {
+        AggTask t;
+        t.out = agg_mem + agg_off[a] + sb.off;
+        t.ldo = sb.ld;
+        t.rows = sb.rows;
+        t.cols = sb.cols;
+        t.t0 = (int)terms.size();
+        for (const auto& tm : agg_terms[a]) {
+          AggTerm x;
+          x.coef = tm.coef;
+          x.pad = 0;
+          if (tm.key.kind == 'I') {
+            if (sb.in != sb.out) continue;
+            x.in = nullptr;
+            x.ldi = 0;
+            x.flags = kIdentA;
+          } else {
+            int rr, cc, ld;
+            const double* p = tm.trans ? Lb->op_block(tm.key, sb.out, &rr, &cc, &ld)
+                                       : Lb->op_block(tm.key, sb.in, &rr, &cc, &ld);
+            if (!p) continue;
+            x.in = p;
+            x.ldi = ld;
+            x.flags = tm.trans ? kTransA : 0;
+          }
+          terms.push_back(x);
+        }
+        t.nt = (int)terms.size() - t.t0;
+        tasks.push_back(t);
+      }
+    if (!tasks.empty()) {
+      DevBuf dt, dm;
+      dt.reserve(tasks.size() * sizeof(AggTask));
+      dm.reserve(std::max<size_t>(1, terms.size()) * sizeof(AggTerm));
+      BSD_HIP(hipMemcpyAsync(dt.p, tasks.data(), tasks.size() * sizeof(AggTask), hipMemcpyHostToDevice, s));
+      if (!terms.empty())
+        BSD_HIP(hipMemcpyAsync(dm.p, terms.data(), terms.size() * sizeof(AggTerm), hipMemcpyHostToDevice, s));
+      launch_aggregate((const AggTask*)dt.p, (const AggTerm*)dm.p, (int)tasks.size(), s);
+      BSD_HIP(hipStreamSynchronize(s));
+    }
+  }
+
+  // ---------------------------------------------------------------- chunks of channels
+  const int nR = (int)Rb->basis.q.size();
+  std::vector<std::vector<int>> by_c(16);
+  for (int b = 0; b < (int)lay.blocks.size(); ++b) by_c[lay.blocks[b].c].push_back(b);
+  // phase-1 V storage per channel: for each output right sector r' a stack rows x d_R(r')
+  struct VInfo {
+    std::vector<int64_t> off;   // per output right index, element offset in chunk workspace or -1
+    std::vector<int> src;       // input right index feeding r'
+  };
+  std::vector<VInfo> vinfo(chans.size());
+  std::vector<int> chunk_of(chans.size());
+  std::vector<int64_t> chunk_size;
+  int64_t cur = 0;
+  const int64_t budget = (int64_t)(ws_budget / sizeof(double));
+  for (size_t ci = 0; ci < chans.size(); ++ci) {
+    auto& ch = chans[ci];
+    VInfo vi;
+    vi.off.assign(nR, -1);
+    vi.src.assign(nR, -1);
+    int64_t need = 0;
+    if (ch.rkind == 0) {
+      for (int r = 0; r < nR; ++r) {
+        if (lay.stack_rows[r] == 0) continue;
+        int r2 = Rb->basis.find(Rb->basis.q[r] + ch.rdq);
+        if (r2 < 0) continue;
+        int rr, cc, ld;
+        const double* p = ch.rtrans ? Rb->op_block(ch.rkey, r2, &rr, &cc, &ld) : Rb->op_block(ch.rkey, r, &rr, &cc, &ld);
+        if (!p) continue;
+        vi.off[r2] = need;   // relative, fixed below
+        vi.src[r2] = r;
+        need += ((int64_t)lay.stack_rows[r] * Rb->basis.dim[r2] + 1) / 2 * 2;
+      }
+      if (need == 0) {
+        cgroups[ci].clear();
+        chunk_of[ci] = -1;
+        vinfo[ci] = vi;
+        continue;
+      }
+    }
+    if (chunk_size.empty() || (cur + need > budget && cur > 0)) {
+      chunk_size.push_back(0);
+      cur = 0;
+    }
+    for (auto& o : vi.off)
+      if (o >= 0) o += cur;
+    cur += need;
+    chunk_size.back() = cur;
+    chunk_of[ci] = (int)chunk_size.size() - 1;
+    vinfo[ci] = vi;
+  }
+  int64_t ws_elems = 0;
+  for (auto c : chunk_size) ws_elems = std::max(ws_elems, c);
+  plan->V.reserve(std::max<int64_t>(1, ws_elems) * sizeof(double));
+  plan->v_bytes = ws_elems * sizeof(double);
+  double* V = static_cast<double*>(plan->V.p);
+  const int nchunks = (int)chunk_size.size();
+  plan->phase1.resize(nchunks);
+  plan->phase2.resize(nchunks);
+  double useful = 0.0;
+
+  std::vector<std::vector<GemmProblem>> p1(nchunks);
+  // per chunk, per output psi block: list of segments
+  std::vector<std::map<int, GemmProblem>> p2(nchunks);
+  for (size_t ci = 0; ci < chans.size(); ++ci) {
+    if (chunk_of[ci] < 0 || cgroups[ci].empty()) continue;
+    const int ck = chunk_of[ci];
+    const auto& ch = chans[ci];
+    const auto& vi = vinfo[ci];
+    if (ch.rkind == 0) {
+      for (int r2 = 0; r2 < nR; ++r2) {
+        if (vi.off[r2] < 0) continue;
+        int r = vi.src[r2];
+        int rr, cc, ld;
+        const double* p = ch.rtrans ? Rb->op_block(ch.rkey, r2, &rr, &cc, &ld) : Rb->op_block(ch.rkey, r, &rr, &cc, &ld);
+        GemmProblem gp;
+        gp.C = tag_ptr(0, (uint64_t)(V + vi.off[r2]));
+        gp.ldc = Rb->basis.dim[r2];
+        gp.M = lay.stack_rows[r];
+        gp.N = Rb->basis.dim[r2];
+        gp.beta = 0.0;
+        GSeg sg;
+        sg.A = tag_ptr(1, (uint64_t)(lay.stack_off[r] * sizeof(double)));
+        sg.lda = Rb->basis.dim[r];
+        sg.B = tag_ptr(0, (uint64_t)p);
+        sg.ldb = ld;
+        sg.K = Rb->basis.dim[r];
+        sg.flags = ch.rtrans ? 0 : kTransB;   // op(B) = R_b^T
+        sg.alpha = 1.0;
+        gp.segs.push_back(sg);
+        useful += 2.0 * gp.M * (double)gp.N * sg.K;
+        p1[ck].push_back(std::move(gp));
+      }
+    }
+    const int rpar = ch.rdq.parity();
+    for (const auto& g : cgroups[ci]) {
+      const LRef& lr = lrefs[g.lref];
+      for (int c = 0; c < 16; ++c)
+        for (int c2 = 0; c2 < 16; ++c2) {
+          double m = g.M(c2, c);
+          if (m == 0.0) continue;
+          for (int bi : by_c[c]) {
+            const PsiBlk& pb = lay.blocks[bi];
+            // input block (l, c, r); output (l', c2, r')
+            int r2 = ch.rkind == 1 ? pb.r : Rb->basis.find(Rb->basis.q[pb.r] + ch.rdq);
+            if (r2 < 0) continue;
+            if (ch.rkind == 0 && (vi.off[r2] < 0 || vi.src[r2] != pb.r)) continue;
+            Operand2 o = lref_block(*Lb, lr, agg_sk, agg_off, agg_mem, pb.l);
+            if (!o.ok) continue;
+            auto oit = lay.index.find({o.out, c2, r2});
+            if (oit == lay.index.end()) continue;
+            const PsiBlk& ob = lay.blocks[oit->second];
+            const int lpar = Lb->basis.q[pb.l].parity();
+            const int cpar = C.q[c].parity();
+            int sp = (g.mpar & lpar) ^ (rpar & (lpar ^ cpar));
+            GSeg sg;
+            sg.alpha = g.coef * m * (sp ? -1.0 : 1.0);
+            sg.K = pb.rows;
+            sg.flags = (o.trans ? kTransA : 0) | (o.ident ? kIdentA : 0);
+            sg.A = tag_ptr(0, (uint64_t)o.p);
+            sg.lda = o.ld;
+            if (ch.rkind == 1) {
+              sg.B = tag_ptr(1, (uint64_t)(pb.off * sizeof(double)));
+              sg.ldb = pb.cols;
+            } else {
+              int64_t row0 = pb.row_in_stack;
+              sg.B = tag_ptr(0, (uint64_t)(V + vi.off[r2] + row0 * Rb->basis.dim[r2]));
+              sg.ldb = Rb->basis.dim[r2];
+            }
+            auto& gp = p2[ck][oit->second];
+            if (gp.segs.empty()) {
+              gp.C = tag_ptr(2, (uint64_t)(ob.off * sizeof(double)));
+              gp.ldc = ob.cols;
+              gp.M = ob.rows;
+              gp.N = ob.cols;
+              gp.beta = 1.0;
+            }
+            gp.segs.push_back(sg);
+            if (!o.ident) useful += 2.0 * ob.rows * (double)ob.cols * pb.rows;
+          }
+        }
+    }
+  }
+  plan->nseg = 0;
+  for (int k = 0; k < nchunks; ++k) {
+    plan->phase1[k] = std::make_unique<GemmPlan>();
+    plan->phase1[k]->build(p1[k]);
+    std::vector<GemmProblem> v;
+    for (auto& kv : p2[k]) {
+      plan->nseg += kv.second.segs.size();
+      v.push_back(std::move(kv.second));
+    }
+    plan->phase2[k] = std::make_unique<GemmPlan>();
+    plan->phase2[k]->build(v);
+  }
+  plan->useful_flops = useful;
+  plan->nchannels = (int)chans.size();
+  plan->naggs = (int)agg_sk.size();
+  return plan;
+}
+
+void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s) {
+  zero_fill(out, plan.lay.n_elems, s);
+  GBases b{{0, (uint64_t)psi, (uint64_t)out, 0}};
+  for (size_t k = 0; k < plan.phase1.size(); ++k) {
+    plan.phase1[k]->launch(b, s);
+    plan.phase2[k]->launch(b, s);
+  }
+}
+
+}  // namespace bsd

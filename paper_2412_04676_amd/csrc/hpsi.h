@@ -1,0 +1,48 @@
+// Two-site effective-Hamiltonian product: plan ("Tables") and execution.
+#pragma once
+#include "ctx.h"
+
+namespace bsd {
+
+struct PsiBlk {
+  int l, c, r;          // left index, local state of the two sites, right index
+  int rows, cols;
+  int64_t off;          // element offset
+  int row_in_stack;     // row offset inside the right sector's stack
+};
+
+// psi is stored grouped by right sector: for each right sector r, the blocks
+// (l, c) with q_l + q_c + q_r = target follow each other (l ascending, then c),
+// so they form one tall matrix of stack_rows[r] x d_R(r).
+struct PsiLayout {
+  std::vector<PsiBlk> blocks;
+  std::map<std::tuple<int, int, int>, int> index;
+  std::vector<int64_t> stack_off;
+  std::vector<int> stack_rows;
+  int64_t n_elems = 0;
+};
+
+struct Operand2 {
+  bool ok = false, trans = false, ident = false;
+  const double* p = nullptr;
+  int64_t ld = 0;
+  int out = -1;
+};
+
+struct HpsiPlan {
+  int site = 0, precision = 0;
+  PsiLayout lay;
+  DevBuf agg, V;
+  size_t agg_bytes = 0, v_bytes = 0;
+  std::vector<std::unique_ptr<GemmPlan>> phase1, phase2;
+  double useful_flops = 0.0;
+  size_t nseg = 0;
+  int nchannels = 0, naggs = 0;
+};
+
+void build_psi_layout(const Block& Lb, const Block& Rb, const SiteSet& C, const Q& target, PsiLayout& lay);
+std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, size_t ws_budget, hipStream_t s);
+void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s);
+void zero_fill(double* p, int64_t n, hipStream_t s);
+
+}  // namespace bsd

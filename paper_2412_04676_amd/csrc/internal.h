@@ -1,0 +1,315 @@
+// Internal declarations of the block-sparse DMRG library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace bsd {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+void set_last_error(const std::string& m);
+
+#define BSD_HIP(call)                                                               \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      throw ::bsd::Error(5, std::string("HIP error ") + hipGetErrorString(e_) +     \
+                                " at " __FILE__ ":" + std::to_string(__LINE__));    \
+  } while (0)
+
+#define BSD_CHECK(cond, code, msg)          \
+  do {                                      \
+    if (!(cond)) throw ::bsd::Error(code, msg); \
+  } while (0)
+
+// ---------------------------------------------------------------- quantum numbers
+struct Q {
+  int a = 0, b = 0;
+  bool operator<(const Q& o) const { return a != o.a ? a < o.a : b < o.b; }
+  bool operator==(const Q& o) const { return a == o.a && b == o.b; }
+  bool operator!=(const Q& o) const { return !(*this == o); }
+  Q operator+(const Q& o) const { return {a + o.a, b + o.b}; }
+  Q operator-(const Q& o) const { return {a - o.a, b - o.b}; }
+  Q operator-() const { return {-a, -b}; }
+  int parity() const { return ((a + b) % 2 + 2) % 2; }
+};
+inline Q mode_q(int p) { return (p % 2 == 0) ? Q{1, 0} : Q{0, 1}; }
+extern const Q kSiteQ[4];
+
+// ---------------------------------------------------------------- integrals
+struct Integrals {
+  int L = 0;
+  std::vector<double> h, eri;  // h[L*L], eri[L^4] chemists' order
+  double t(int p, int q) const {
+    return (p % 2 == q % 2) ? h[(size_t)(p / 2) * L + q / 2] : 0.0;
+  }
+  // g_pqrs = (i_p i_s | i_q i_r) for sigma_p = sigma_s and sigma_q = sigma_r
+  double g(int p, int q, int r, int s) const {
+    if (p % 2 != s % 2 || q % 2 != r % 2) return 0.0;
+    size_t ip = p / 2, is = s / 2, iq = q / 2, ir = r / 2, l = L;
+    return eri[((ip * l + is) * l + iq) * l + ir];
+  }
+};
+
+// ---------------------------------------------------------------- small dense local matrices
+struct Mat {
+  int n = 0;
+  std::vector<double> a;
+  Mat() {}
+  explicit Mat(int n_) : n(n_), a((size_t)n_ * n_, 0.0) {}
+  double& operator()(int i, int j) { return a[(size_t)i * n + j]; }
+  double operator()(int i, int j) const { return a[(size_t)i * n + j]; }
+  bool zero() const {
+    for (double v : a)
+      if (v != 0.0) return false;
+    return true;
+  }
+};
+Mat mat_mul(const Mat& x, const Mat& y);
+Mat mat_T(const Mat& x);
+Mat mat_scale(const Mat& x, double c);
+void mat_axpy(Mat& y, double c, const Mat& x);
+Mat mat_eye(int n);
+
+// A set of consecutive sites treated exactly (one site for renormalization,
+// two sites for the two-site superblock).  State index = sum s_k 4^(n-1-k).
+struct SiteSet {
+  int first = 0, nsites = 0, dim = 0;
+  std::vector<Mat> cd;         // creation matrix per local mode (2*nsites)
+  std::vector<Q> q;            // quantum number per state
+  int mode0() const { return 2 * first; }
+  int nmodes() const { return 2 * nsites; }
+  bool has(int p) const { return p >= mode0() && p < mode0() + nmodes(); }
+  const Mat& CD(int p) const { return cd[p - mode0()]; }
+  Mat C(int p) const { return mat_T(cd[p - mode0()]); }
+};
+SiteSet make_siteset(int first, int nsites);
+
+// ---------------------------------------------------------------- operator keys
+// kinds: 'I' identity, 'H' block Hamiltonian, 'c' creation a+_p, 'A' a+_p a+_q (p<q),
+// 'B' a+_p a_q, 'S' three-operator complementary op, 'P' and 'Q' two-index
+// complementary ops.
+struct OpKey {
+  char kind = 'I';
+  int p = -1, q = -1;
+  bool operator<(const OpKey& o) const {
+    if (kind != o.kind) return kind < o.kind;
+    if (p != o.p) return p < o.p;
+    return q < o.q;
+  }
+  bool operator==(const OpKey& o) const { return kind == o.kind && p == o.p && q == o.q; }
+};
+
+// a term coef * op(key) with op = transpose if trans
+struct Term {
+  double coef;
+  OpKey key;
+  bool trans;
+};
+// sum_k terms_k (x) M : block part aggregated, local part M (dim x dim)
+struct Group {
+  Mat M;
+  std::vector<Term> terms;
+};
+
+// Operators of an enlarged block L . C in the left (normal) role, C on the right.
+std::vector<Group> expand_left(const OpKey& key, int nL_modes, const SiteSet& C,
+                               const Integrals& I);
+// Operators of s . R in the right (complementary) role, s on the left.
+std::vector<Group> expand_right(const OpKey& key, const SiteSet& s, int R_mode0, int nmodes,
+                                const Integrals& I);
+// Transpose of an expanded operator (graded: sign (-1)^{|M| |O|}).
+std::vector<Group> transpose_groups(const std::vector<Group>& g, const SiteSet& C,
+                                    int op_parity_of_block);
+// dq of a block operator key in the given role (left: normal set, right: complementary set)
+Q key_dq(const OpKey& k, bool left_block);
+int local_parity(const Mat& M, const SiteSet& C);  // parity of a local operator (-1 if zero)
+
+// ---------------------------------------------------------------- block-sparse structures
+struct Basis {
+  std::vector<Q> q;
+  std::vector<int> dim;
+  std::map<Q, int> index;
+  int find(const Q& x) const {
+    auto it = index.find(x);
+    return it == index.end() ? -1 : it->second;
+  }
+  void add(const Q& x, int d) {
+    index[x] = (int)q.size();
+    q.push_back(x);
+    dim.push_back(d);
+  }
+  int64_t total() const {
+    int64_t s = 0;
+    for (int d : dim) s += d;
+    return s;
+  }
+};
+
+// one dense block of a skeleton: rows x cols at element offset off (row-major, ld)
+struct SkBlock {
+  int in, out;   // basis indices
+  int rows, cols, ld;
+  int64_t off;
+};
+struct Skeleton {
+  Q dq;
+  std::vector<SkBlock> blocks;
+  std::vector<int> by_in;   // basis index -> block index or -1
+  int64_t layer_stride = 0; // elements per layer (multiple of 32)
+};
+Skeleton make_skeleton(const Basis& in, const Basis& out, const Q& dq);
+
+// layered operators sharing one skeleton (one device allocation)
+struct Family {
+  Skeleton sk;
+  std::vector<OpKey> keys;
+  double* dev = nullptr;
+  size_t bytes() const { return (size_t)sk.layer_stride * keys.size() * sizeof(double); }
+};
+
+struct OpRef {
+  int fam = -1, layer = -1;
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  DevBuf() {}
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) {
+    o.p = nullptr;
+    o.n = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      n = o.n;
+      o.p = nullptr;
+      o.n = 0;
+    }
+    return *this;
+  }
+  ~DevBuf();
+  void reserve(size_t bytes);
+  void release();
+};
+
+struct SerialPlan;
+struct SerialPlanDeleter {
+  void operator()(SerialPlan* p) const;
+};
+using SerialPlanPtr = std::unique_ptr<SerialPlan, SerialPlanDeleter>;
+
+// A renormalized block with its operator families on the device.
+struct Block {
+  bool left = true;
+  int first = 0, last = 0;   // sites [first, last)
+  Basis basis;               // electrons inside the block
+  std::vector<Family> fams;
+  std::map<OpKey, OpRef> ops;
+  std::vector<std::unique_ptr<DevBuf>> mem;
+  bool resident = true;
+  // serializer descriptors and offload state
+  SerialPlanPtr splan;
+  hipEvent_t offload_done = nullptr;
+  bool offload_pending = false, release_after = false;
+  ~Block();
+  const double* op_block(const OpKey& k, int in_idx, int* rows, int* cols, int* ld) const;
+  size_t device_bytes() const;
+};
+
+// ---------------------------------------------------------------- grouped GEMM
+// Pointers are tagged: bits 56..63 select a base (0 absolute, 1 psi-in, 2 out, 3 spare).
+constexpr int kTagShift = 56;
+inline uint64_t tag_ptr(int cls, uint64_t off) { return ((uint64_t)cls << kTagShift) | off; }
+enum { kTransA = 1, kTransB = 2, kIdentA = 4 };
+
+struct GSeg {
+  uint64_t A, B;
+  int64_t lda, ldb;
+  int32_t K, flags;
+  double alpha;
+};
+struct GTile {
+  uint64_t C;
+  int64_t ldc;
+  int32_t M, N, m0, n0;
+  int32_t seg0, nseg;
+  double beta;
+};
+struct GBases {
+  uint64_t b[4];
+};
+
+// a list of output matrices, each with its own list of K-segments
+struct GemmProblem {
+  uint64_t C;
+  int64_t ldc;
+  int M, N;
+  double beta;
+  std::vector<GSeg> segs;
+};
+
+// Device-resident tile/segment lists for one launch group (64x64 and 32x32 tiles).
+struct GemmPlan {
+  int ntiles64 = 0, ntiles32 = 0;
+  DevBuf tiles, segs;
+  double flops = 0.0;   // useful flops (2 M N K summed over segments)
+  void build(const std::vector<GemmProblem>& probs);
+  void launch(const GBases& bases, hipStream_t s) const;
+};
+
+struct AggTerm {
+  const double* in;
+  int64_t ldi;
+  int32_t flags;  // kTransA: read transposed, kIdentA: identity
+  int32_t pad;
+  double coef;
+};
+struct AggTask {
+  double* out;
+  int64_t ldo;
+  int32_t rows, cols;
+  int32_t t0, nt;
+};
+void launch_aggregate(const AggTask* tasks_dev, const AggTerm* terms_dev, int ntasks,
+                      hipStream_t s);
+void launch_grouped_gemm(const GTile* tiles, int ntiles, int tile, const GSeg* segs,
+                         const GBases& b, hipStream_t s);
+
+// ---------------------------------------------------------------- serializer
+struct FamilyView {
+  uint64_t tag;
+  Q dq;
+  int n_layers;
+  std::vector<Q> bq;
+  std::vector<int> rows, cols, ld;
+  std::vector<int64_t> off;
+  int64_t layer_stride;
+  void* data;
+};
+size_t serialized_size(const std::vector<FamilyView>& fams);
+// device descriptors of a set of families (built once; synchronizes s)
+SerialPlanPtr serial_plan(const std::vector<FamilyView>& fams, hipStream_t s);
+size_t serial_bytes(const SerialPlan& p);
+void serial_pack(const SerialPlan& p, void* dst, size_t cap, hipStream_t s);          // stream-ordered
+void serial_unpack(const SerialPlan& p, const void* src, size_t bytes, hipStream_t s);  // stream-ordered
+int serial_status(const SerialPlan& p, hipStream_t s);  // synchronizes s; 0 or 7 (corrupt)
+int validate_stream_host(const std::vector<FamilyView>& fams, const void* src, size_t bytes);
+
+}  // namespace bsd

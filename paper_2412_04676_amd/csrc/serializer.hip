@@ -1,0 +1,434 @@
+// Parallel serializer for layered block-sparse operator families (Sec. III.B.2).
+//
+// The stream size is exact before anything is written (the host computes it
+// from the skeletons alone); on the device an exclusive wavefront prefix sum
+// over block sizes gives every block its interval in the stream, so all
+// workgroups then copy in complete independence into disjoint intervals of
+// one contiguous buffer.  Byte format (little-endian):
+//   header 64 B | family table 64 B/family | block tables 32 B/block |
+//   zero pad to 256 | per family: n_layers x sum(rows*cols) float64, layer-major,
+//   blocks compact row-major, zero pad to 256.
+// Header: magic "BSDMRG01", u32 version=1, u32 n_families, u64 total, u64 payload,
+// u64 meta, 24 zero bytes.  Family entry: u64 tag, i32 dq[2], u32 n_layers,
+// u32 n_blocks, u32 esize=8, u32 0, u64 blocks_off, u64 payload_off,
+// u64 layer_elems, u64 0.  Block entry: i32 q_in[2], i32 rows, i32 cols,
+// u64 elem_off, u64 0.
+#include "internal.h"
+
+#include <algorithm>
+
+namespace bsd {
+
+namespace {
+
+struct FamDesc {
+  uint64_t tag;
+  int32_t dqa, dqb;
+  int32_t n_layers, n_blocks;
+  int32_t blk0, pad;
+  double* base;
+  int64_t layer_stride;
+};
+struct BlkDesc {
+  int32_t qa, qb, rows, cols, ld, pad;
+  int64_t src_off;
+};
+// per-workgroup copy task: one row slice of one block, or a run of whole blocks
+struct CopyTask {
+  int32_t fam, layer, blk0, blk1, row0, nrows;
+};
+
+constexpr int kCopyElems = 8192;
+
+__host__ __device__ inline int64_t align256(int64_t n) { return (n + 255) / 256 * 256; }
+
+__device__ __forceinline__ int64_t wave_incl_scan(int64_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    int64_t u = __shfl_up(v, d, 64);
+    if (lane >= d) v += u;
+  }
+  return v;
+}
+
+// one workgroup (256 threads) per family: elem_off[b] = exclusive prefix sum of rows*cols
+__global__ void __launch_bounds__(256)
+scan_blocks_kernel(const FamDesc* __restrict__ fams, const BlkDesc* __restrict__ blks,
+                   int64_t* __restrict__ elem_off, int64_t* __restrict__ layer_elems) {
+  __shared__ int64_t wsum[4];
+  __shared__ int64_t carry;
+  const FamDesc f = fams[blockIdx.x];
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int base = 0; base < f.n_blocks; base += 256) {
+    const int b = base + threadIdx.x;
+    int64_t v = 0;
+    if (b < f.n_blocks) v = (int64_t)blks[f.blk0 + b].rows * blks[f.blk0 + b].cols;
+    int64_t incl = wave_incl_scan(v);
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int64_t prefix = carry;
+    for (int w = 0; w < wave; ++w) prefix += wsum[w];
+    if (b < f.n_blocks) elem_off[f.blk0 + b] = prefix + incl - v;
+    __syncthreads();
+    if (threadIdx.x == 255) carry = prefix + incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) layer_elems[blockIdx.x] = carry;
+}
+
+// one wavefront: family-level exclusive prefix sum of aligned payload sizes
+__global__ void __launch_bounds__(64)
+family_offsets_kernel(const FamDesc* __restrict__ fams, int nf, int nb_total,
+                      const int64_t* __restrict__ layer_elems, int64_t* __restrict__ payload_off) {
+  const int64_t meta = align256(64 + 64 * (int64_t)nf + 32 * (int64_t)nb_total);
+  int64_t carry = meta;
+  for (int base = 0; base < nf; base += 64) {
+    const int f = base + (int)threadIdx.x;
+    const int64_t v = f < nf ? align256(fams[f].n_layers * layer_elems[f] * 8) : 0;
+    const int64_t incl = wave_incl_scan(v);
+    if (f < nf) payload_off[f] = carry + incl - v;
+    carry += __shfl(incl, 63, 64);
+  }
+}
+
+// one workgroup: header, family table, block tables, zero padding
+__global__ void __launch_bounds__(256)
+write_meta_kernel(const FamDesc* __restrict__ fams, const BlkDesc* __restrict__ blks, int nf,
+                  int nb_total, const int64_t* __restrict__ elem_off,
+                  const int64_t* __restrict__ layer_elems, const int64_t* __restrict__ payload_off,
+                  unsigned char* __restrict__ out, uint64_t magic) {
+  const int64_t meta = align256(64 + 64 * (int64_t)nf + 32 * (int64_t)nb_total);
+  __shared__ int64_t total;
+  if (threadIdx.x == 0) {
+    int64_t p = nf > 0 ? payload_off[nf - 1] + align256(fams[nf - 1].n_layers * layer_elems[nf - 1] * 8) : meta;
+    total = p;
+    uint64_t* h = reinterpret_cast<uint64_t*>(out);
+    h[0] = magic;
+    reinterpret_cast<uint32_t*>(out)[2] = 1u;
+    reinterpret_cast<uint32_t*>(out)[3] = (uint32_t)nf;
+    h[2] = (uint64_t)p;
+    h[3] = (uint64_t)(p - meta);
+    h[4] = (uint64_t)meta;
+    h[5] = h[6] = h[7] = 0;
+  }
+  __syncthreads();
+  for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+    const FamDesc fd = fams[f];
+    unsigned char* e = out + 64 + 64 * (int64_t)f;
+    reinterpret_cast<uint64_t*>(e)[0] = fd.tag;
+    reinterpret_cast<int32_t*>(e)[2] = fd.dqa;
+    reinterpret_cast<int32_t*>(e)[3] = fd.dqb;
+    reinterpret_cast<uint32_t*>(e)[4] = (uint32_t)fd.n_layers;
+    reinterpret_cast<uint32_t*>(e)[5] = (uint32_t)fd.n_blocks;
+    reinterpret_cast<uint32_t*>(e)[6] = 8u;
+    reinterpret_cast<uint32_t*>(e)[7] = 0u;
+    reinterpret_cast<uint64_t*>(e)[4] = (uint64_t)(64 + 64 * (int64_t)nf + 32 * (int64_t)fd.blk0);
+    reinterpret_cast<uint64_t*>(e)[5] = (uint64_t)payload_off[f];
+    reinterpret_cast<uint64_t*>(e)[6] = (uint64_t)layer_elems[f];
+    reinterpret_cast<uint64_t*>(e)[7] = 0;
+  }
+  for (int b = threadIdx.x; b < nb_total; b += blockDim.x) {
+    const BlkDesc bd = blks[b];
+    unsigned char* e = out + 64 + 64 * (int64_t)nf + 32 * (int64_t)b;
+    reinterpret_cast<int32_t*>(e)[0] = bd.qa;
+    reinterpret_cast<int32_t*>(e)[1] = bd.qb;
+    reinterpret_cast<int32_t*>(e)[2] = bd.rows;
+    reinterpret_cast<int32_t*>(e)[3] = bd.cols;
+    reinterpret_cast<uint64_t*>(e)[2] = (uint64_t)elem_off[b];
+    reinterpret_cast<uint64_t*>(e)[3] = 0;
+  }
+  for (int64_t i = 64 + 64 * (int64_t)nf + 32 * (int64_t)nb_total + threadIdx.x; i < meta; i += blockDim.x) out[i] = 0;
+  for (int f = 0; f < nf; ++f) {
+    const int64_t end = payload_off[f] + fams[f].n_layers * layer_elems[f] * 8;
+    const int64_t stop = (f + 1 < nf) ? payload_off[f + 1] : total;
+    for (int64_t i = end + threadIdx.x; i < stop; i += blockDim.x) out[i] = 0;
+  }
+}
+
+template <bool PACK>
+__global__ void __launch_bounds__(256)
+copy_kernel(const CopyTask* __restrict__ tasks, const FamDesc* __restrict__ fams,
+            const BlkDesc* __restrict__ blks, const int64_t* __restrict__ elem_off,
+            const int64_t* __restrict__ layer_elems, const int64_t* __restrict__ payload_off,
+            unsigned char* __restrict__ stream, const int* __restrict__ status) {
+  if (!PACK && *status != 0) return;
+  const CopyTask t = tasks[blockIdx.x];
+  const FamDesc f = fams[t.fam];
+  double* sbase = reinterpret_cast<double*>(stream + payload_off[t.fam]) + (int64_t)t.layer * layer_elems[t.fam];
+  double* lbase = f.base + (int64_t)t.layer * f.layer_stride;
+  for (int b = t.blk0; b < t.blk1; ++b) {
+    const BlkDesc bd = blks[f.blk0 + b];
+    const int r0 = (t.blk1 == t.blk0 + 1) ? t.row0 : 0;
+    const int nr = (t.blk1 == t.blk0 + 1) ? t.nrows : bd.rows;
+    double* s = sbase + elem_off[f.blk0 + b] + (int64_t)r0 * bd.cols;
+    double* d = lbase + bd.src_off + (int64_t)r0 * bd.ld;
+    const int64_t n = (int64_t)nr * bd.cols;
+    for (int64_t e = threadIdx.x; e < n; e += blockDim.x) {
+      const int64_t r = e / bd.cols, c = e - r * bd.cols;
+      if (PACK) s[e] = d[r * bd.ld + c];
+      else d[r * bd.ld + c] = s[e];
+    }
+  }
+}
+
+// checks the stream's header and tables against the expected skeletons
+__global__ void __launch_bounds__(256)
+validate_kernel(const FamDesc* __restrict__ fams, const BlkDesc* __restrict__ blks, int nf,
+                int nb_total, const int64_t* __restrict__ elem_off,
+                const int64_t* __restrict__ layer_elems, const int64_t* __restrict__ payload_off,
+                const unsigned char* __restrict__ in, int64_t bytes, uint64_t magic,
+                int* __restrict__ status) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  const int64_t meta = align256(64 + 64 * (int64_t)nf + 32 * (int64_t)nb_total);
+  int mybad = 0;
+  if (threadIdx.x == 0) {
+    const uint64_t* h = reinterpret_cast<const uint64_t*>(in);
+    const uint32_t* h32 = reinterpret_cast<const uint32_t*>(in);
+    int64_t total = payload_off[nf - 1 >= 0 ? nf - 1 : 0];
+    total = nf > 0 ? total + align256(fams[nf - 1].n_layers * layer_elems[nf - 1] * 8) : meta;
+    if (h[0] != magic || h32[2] != 1u || h32[3] != (uint32_t)nf || (int64_t)h[2] != bytes ||
+        (int64_t)h[2] != total || (int64_t)h[4] != meta || (int64_t)h[3] != total - meta)
+      mybad = 1;
+  }
+  for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+    const FamDesc fd = fams[f];
+    const unsigned char* e = in + 64 + 64 * (int64_t)f;
+    if (reinterpret_cast<const int32_t*>(e)[2] != fd.dqa || reinterpret_cast<const int32_t*>(e)[3] != fd.dqb ||
+        reinterpret_cast<const uint32_t*>(e)[4] != (uint32_t)fd.n_layers ||
+        reinterpret_cast<const uint32_t*>(e)[5] != (uint32_t)fd.n_blocks ||
+        reinterpret_cast<const uint32_t*>(e)[6] != 8u ||
+        reinterpret_cast<const uint64_t*>(e)[4] != (uint64_t)(64 + 64 * (int64_t)nf + 32 * (int64_t)fd.blk0) ||
+        reinterpret_cast<const uint64_t*>(e)[5] != (uint64_t)payload_off[f] ||
+        reinterpret_cast<const uint64_t*>(e)[6] != (uint64_t)layer_elems[f])
+      mybad = 1;
+  }
+  for (int b = threadIdx.x; b < nb_total; b += blockDim.x) {
+    const BlkDesc bd = blks[b];
+    const unsigned char* e = in + 64 + 64 * (int64_t)nf + 32 * (int64_t)b;
+    if (reinterpret_cast<const int32_t*>(e)[0] != bd.qa || reinterpret_cast<const int32_t*>(e)[1] != bd.qb ||
+        reinterpret_cast<const int32_t*>(e)[2] != bd.rows || reinterpret_cast<const int32_t*>(e)[3] != bd.cols ||
+        reinterpret_cast<const uint64_t*>(e)[2] != (uint64_t)elem_off[b])
+      mybad = 1;
+  }
+  if (mybad) atomicOr(&bad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) *status = bad ? 7 : 0;
+}
+
+uint64_t magic_word() {
+  uint64_t m;
+  std::memcpy(&m, "BSDMRG01", 8);
+  return m;
+}
+
+}  // namespace
+
+struct SerialPlan {
+  DevBuf fams, blks, tasks, elem_off, layer_elems, payload_off, status;
+  int nf = 0, nb = 0, ntasks = 0;
+  size_t bytes = 0;
+};
+
+static void upload(const std::vector<FamilyView>& fv, SerialPlan& d, hipStream_t s) {
+  std::vector<FamDesc> fd;
+  std::vector<BlkDesc> bd;
+  std::vector<CopyTask> tasks;
+  for (size_t f = 0; f < fv.size(); ++f) {
+    const auto& v = fv[f];
+    FamDesc x;
+    x.tag = v.tag;
+    x.dqa = v.dq.a;
+    x.dqb = v.dq.b;
+    x.n_layers = v.n_layers;
+    x.n_blocks = (int)v.bq.size();
+    x.blk0 = (int)bd.size();
+    x.pad = 0;
+    x.base = static_cast<double*>(v.data);
+    x.layer_stride = v.layer_stride;
+    fd.push_back(x);
+    for (size_t b = 0; b < v.bq.size(); ++b) {
+      BlkDesc y;
+      y.qa = v.bq[b].a;
+      y.qb = v.bq[b].b;
+      y.rows = v.rows[b];
+      y.cols = v.cols[b];
+      y.ld = v.ld[b];
+      y.pad = 0;
+      y.src_off = v.off[b];
+      bd.push_back(y);
+    }
+    // copy tasks: large blocks in row slices, small blocks in runs
+    for (int l = 0; l < v.n_layers; ++l) {
+      int b = 0;
+      const int nbk = (int)v.bq.size();
+      while (b < nbk) {
+        int64_t n = (int64_t)v.rows[b] * v.cols[b];
+        if (n >= kCopyElems) {
+          int rows_per = std::max(1, (int)(kCopyElems / std::max(1, v.cols[b])));
+          for (int r0 = 0; r0 < v.rows[b]; r0 += rows_per)
+            tasks.push_back({(int)f, l, b, b + 1, r0, std::min(rows_per, v.rows[b] - r0)});
+          ++b;
+        } else {
+          int b1 = b;
+          int64_t acc = 0;
+          while (b1 < nbk && acc + (int64_t)v.rows[b1] * v.cols[b1] < kCopyElems) {
+            acc += (int64_t)v.rows[b1] * v.cols[b1];
+            ++b1;
+          }
+          if (b1 == b) b1 = b + 1;
+          if (b1 == b + 1)
+            tasks.push_back({(int)f, l, b, b1, 0, v.rows[b]});
+          else
+            tasks.push_back({(int)f, l, b, b1, 0, 0});
+          b = b1;
+        }
+      }
+    }
+  }
+  d.nf = (int)fd.size();
+  d.nb = (int)bd.size();
+  d.ntasks = (int)tasks.size();
+  d.fams.reserve(std::max<size_t>(1, fd.size()) * sizeof(FamDesc));
+  d.blks.reserve(std::max<size_t>(1, bd.size()) * sizeof(BlkDesc));
+  d.tasks.reserve(std::max<size_t>(1, tasks.size()) * sizeof(CopyTask));
+  d.elem_off.reserve(std::max<size_t>(1, bd.size()) * sizeof(int64_t));
+  d.layer_elems.reserve(std::max<size_t>(1, fd.size()) * sizeof(int64_t));
+  d.payload_off.reserve(std::max<size_t>(1, fd.size()) * sizeof(int64_t));
+  d.status.reserve(256);
+  if (!fd.empty()) BSD_HIP(hipMemcpyAsync(d.fams.p, fd.data(), fd.size() * sizeof(FamDesc), hipMemcpyHostToDevice, s));
+  if (!bd.empty()) BSD_HIP(hipMemcpyAsync(d.blks.p, bd.data(), bd.size() * sizeof(BlkDesc), hipMemcpyHostToDevice, s));
+  if (!tasks.empty())
+    BSD_HIP(hipMemcpyAsync(d.tasks.p, tasks.data(), tasks.size() * sizeof(CopyTask), hipMemcpyHostToDevice, s));
+  BSD_HIP(hipStreamSynchronize(s));
+}
+
+static void scan(SerialPlan& d, hipStream_t s) {
+  if (d.nf > 0) {
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(d.nf), dim3(256), 0, s, (const FamDesc*)d.fams.p,
+                       (const BlkDesc*)d.blks.p, (int64_t*)d.elem_off.p, (int64_t*)d.layer_elems.p);
+    BSD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(family_offsets_kernel, dim3(1), dim3(64), 0, s, (const FamDesc*)d.fams.p, d.nf, d.nb,
+                       (const int64_t*)d.layer_elems.p, (int64_t*)d.payload_off.p);
+    BSD_HIP(hipGetLastError());
+  }
+}
+
+size_t serialized_size(const std::vector<FamilyView>& fams) {
+  int64_t nb = 0;
+  for (auto& f : fams) nb += (int64_t)f.bq.size();
+  int64_t total = align256(64 + 64 * (int64_t)fams.size() + 32 * nb);
+  for (auto& f : fams) {
+    int64_t le = 0;
+    for (size_t b = 0; b < f.bq.size(); ++b) le += (int64_t)f.rows[b] * f.cols[b];
+    total += align256((int64_t)f.n_layers * le * 8);
+  }
+  return (size_t)total;
+}
+
+void SerialPlanDeleter::operator()(SerialPlan* p) const { delete p; }
+
+SerialPlanPtr serial_plan(const std::vector<FamilyView>& fams, hipStream_t s) {
+  SerialPlanPtr p(new SerialPlan());
+  p->bytes = serialized_size(fams);
+  upload(fams, *p, s);
+  return p;
+}
+
+size_t serial_bytes(const SerialPlan& p) { return p.bytes; }
+
+void serial_pack(const SerialPlan& d, void* dst, size_t cap, hipStream_t s) {
+  BSD_CHECK(cap >= d.bytes, 4, "destination buffer smaller than the serialized size");
+  BSD_CHECK(((uintptr_t)dst % 256) == 0, 1, "destination must be 256-byte aligned");
+  scan(const_cast<SerialPlan&>(d), s);
+  hipLaunchKernelGGL(write_meta_kernel, dim3(1), dim3(256), 0, s, (const FamDesc*)d.fams.p,
+                     (const BlkDesc*)d.blks.p, d.nf, d.nb, (const int64_t*)d.elem_off.p,
+                     (const int64_t*)d.layer_elems.p, (const int64_t*)d.payload_off.p,
+                     (unsigned char*)dst, magic_word());
+  BSD_HIP(hipGetLastError());
+  if (d.ntasks > 0)
+    hipLaunchKernelGGL((copy_kernel<true>), dim3(d.ntasks), dim3(256), 0, s, (const CopyTask*)d.tasks.p,
+                       (const FamDesc*)d.fams.p, (const BlkDesc*)d.blks.p, (const int64_t*)d.elem_off.p,
+                       (const int64_t*)d.layer_elems.p, (const int64_t*)d.payload_off.p,
+                       (unsigned char*)dst, (const int*)nullptr);
+  BSD_HIP(hipGetLastError());
+}
+
+void serial_unpack(const SerialPlan& d, const void* src, size_t bytes, hipStream_t s) {
+  BSD_CHECK(bytes == d.bytes, 7, "stream size does not match the target skeletons");
+  BSD_CHECK(((uintptr_t)src % 256) == 0, 1, "source must be 256-byte aligned");
+  scan(const_cast<SerialPlan&>(d), s);
+  hipLaunchKernelGGL(validate_kernel, dim3(1), dim3(256), 0, s, (const FamDesc*)d.fams.p,
+                     (const BlkDesc*)d.blks.p, d.nf, d.nb, (const int64_t*)d.elem_off.p,
+                     (const int64_t*)d.layer_elems.p, (const int64_t*)d.payload_off.p,
+                     (const unsigned char*)src, (int64_t)bytes, magic_word(), (int*)d.status.p);
+  BSD_HIP(hipGetLastError());
+  if (d.ntasks > 0)
+    hipLaunchKernelGGL((copy_kernel<false>), dim3(d.ntasks), dim3(256), 0, s, (const CopyTask*)d.tasks.p,
+                       (const FamDesc*)d.fams.p, (const BlkDesc*)d.blks.p, (const int64_t*)d.elem_off.p,
+                       (const int64_t*)d.layer_elems.p, (const int64_t*)d.payload_off.p,
+                       (unsigned char*)const_cast<void*>(src), (const int*)d.status.p);
+  BSD_HIP(hipGetLastError());
+}
+
+int serial_status(const SerialPlan& d, hipStream_t s) {
+  int st = 0;
+  BSD_HIP(hipMemcpyAsync(&st, d.status.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  BSD_HIP(hipStreamSynchronize(s));
+  return st;
+}
+
+int validate_stream_host(const std::vector<FamilyView>& fams, const void* src, size_t bytes) {
+  const size_t need = serialized_size(fams);
+  if (bytes != need) return 7;
+  const unsigned char* p = static_cast<const unsigned char*>(src);
+  uint64_t m;
+  std::memcpy(&m, p, 8);
+  if (m != magic_word()) return 7;
+  uint32_t ver, nf;
+  std::memcpy(&ver, p + 8, 4);
+  std::memcpy(&nf, p + 12, 4);
+  uint64_t total;
+  std::memcpy(&total, p + 16, 8);
+  if (ver != 1 || nf != fams.size() || total != bytes) return 7;
+  int64_t nb = 0;
+  for (auto& f : fams) nb += (int64_t)f.bq.size();
+  int64_t meta = align256(64 + 64 * (int64_t)fams.size() + 32 * nb);
+  int64_t poff = meta, boff = 64 + 64 * (int64_t)fams.size();
+  for (size_t f = 0; f < fams.size(); ++f) {
+    const unsigned char* e = p + 64 + 64 * f;
+    int32_t dq[2];
+    uint32_t nl, nbk;
+    uint64_t bo, po, le;
+    std::memcpy(dq, e + 8, 8);
+    std::memcpy(&nl, e + 16, 4);
+    std::memcpy(&nbk, e + 20, 4);
+    std::memcpy(&bo, e + 32, 8);
+    std::memcpy(&po, e + 40, 8);
+    std::memcpy(&le, e + 48, 8);
+    int64_t lex = 0;
+    for (size_t b = 0; b < fams[f].bq.size(); ++b) {
+      const unsigned char* be = p + boff + 32 * b;
+      int32_t bb[4];
+      uint64_t eo;
+      std::memcpy(bb, be, 16);
+      std::memcpy(&eo, be + 16, 8);
+      if (bb[0] != fams[f].bq[b].a || bb[1] != fams[f].bq[b].b || bb[2] != fams[f].rows[b] ||
+          bb[3] != fams[f].cols[b] || (int64_t)eo != lex)
+        return 7;
+      lex += (int64_t)fams[f].rows[b] * fams[f].cols[b];
+    }
+    if (dq[0] != fams[f].dq.a || dq[1] != fams[f].dq.b || (int)nl != fams[f].n_layers ||
+        nbk != fams[f].bq.size() || (int64_t)bo != boff || (int64_t)po != poff || (int64_t)le != lex)
+      return 7;
+    boff += 32 * (int64_t)nbk;
+    poff += align256((int64_t)nl * lex * 8);
+  }
+  return poff == (int64_t)bytes ? 0 : 7;
+}
+
+}  // namespace bsd

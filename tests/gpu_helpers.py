@@ -1,0 +1,50 @@
+"""Shared helpers of the GPU tests: build a system through the C ABI from the
+seeded synthetic inputs, and move two-site wave functions in and out."""
+import sys
+
+import numpy as np
+
+from synthetic import make_integrals
+from synthetic.mps import random_mps, random_two_site_psi
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def build_system(L, na, nb, D, site, build=True):
+    from paper_2412_04676_amd import bsdmrg as B
+    h, eri = make_integrals(L)
+    dims, T = random_mps(L, na, nb, D, site)
+    ctx = B.bsdmrg_create(L, na, nb)
+    B.bsdmrg_load_integrals(ctx, h, eri)
+    for n, t in enumerate(T):
+        if t is not None:
+            B.bsdmrg_set_site_tensor(ctx, n, t)
+    if build:
+        B.bsdmrg_build_env(ctx, B.LEFT, site)
+        B.bsdmrg_build_env(ctx, B.RIGHT, site + 2)
+    return ctx, h, eri, dims, T
+
+
+def hpsi_gpu(ctx, site, psi):
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    lay = B.bsdmrg_psi_layout(ctx, site)
+    x = torch.from_numpy(B.psi_to_flat(psi, lay)).cuda()
+    y = torch.empty_like(x)
+    B.bsdmrg_hpsi(ctx, site, x, y)
+    torch.cuda.synchronize()
+    return B.flat_to_psi(y.cpu().numpy(), lay), lay
+
+
+def rel(a, b):
+    keys = sorted(b)
+    x = np.concatenate([np.ravel(a[k]) for k in keys])
+    y = np.concatenate([np.ravel(b[k]) for k in keys])
+    return float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-300))
+
+
+def psi_for(dims, site, seed):
+    return random_two_site_psi(dims[site], dims[site + 2], seed)
