@@ -112,11 +112,43 @@ int bsdmrg_hpsi_prepare(bsdmrg_ctx* ctx, int site, int precision, size_t ws_byte
 int bsdmrg_hpsi(bsdmrg_ctx* ctx, int site, const double* psi_dev, double* out_dev, int precision,
                 bsdmrg_stream_t stream);
 
+/* Davidson options (Sec. II.B step 2; the paper names the method but fixes
+ * no parameters).  Defaults: max_iter 50, max_subspace 24, restart 4,
+ * tol 1e-8 on the residual 2-norm, preconditioner floor 1e-4. */
+typedef struct {
+  int32_t max_iter, max_subspace, restart, pad;
+  double tol, precond_floor;
+} bsdmrg_dav_opts;
+
+/* Lowest eigenpair of H_eff at `site` by Davidson in float64 on the device:
+ * diagonal preconditioner (diag H_eff - theta)^-1 with |denominator| >= floor,
+ * two Gram-Schmidt passes per new direction, thick restart.  psi_dev holds the
+ * guess on entry (any nonzero vector) and the normalized eigenvector on return.
+ * energy, iters, resid (host) receive the Ritz value, the iteration count and
+ * the final residual norm; ritz (host, optional, cap entries) the lowest Ritz
+ * value after every iteration.  opts == NULL uses the defaults.  Synchronizes
+ * `stream` once per iteration (a 16-byte read of theta and |r|). */
+int bsdmrg_davidson(bsdmrg_ctx* ctx, int site, double* psi_dev, const bsdmrg_dav_opts* opts, double* energy,
+                    int* iters, double* resid, double* ritz, int cap, bsdmrg_stream_t stream);
+
+/* Diagonal of H_eff at `site` into diag_dev (psi layout), stream-ordered. */
+int bsdmrg_hpsi_diagonal(bsdmrg_ctx* ctx, int site, double* diag_dev, bsdmrg_stream_t stream);
+
 /* Statistics of the last prepared product at `site`: useful flops per product
  * (2 m n k summed over all non-identity sector GEMMs), number of channels,
  * K-segments and aggregated operators, and workspace bytes. */
 int bsdmrg_hpsi_info(bsdmrg_ctx* ctx, int site, int precision, double* flops, int64_t* n_channels,
                      int64_t* n_segments, int64_t* n_aggregates, int64_t* ws_bytes);
+
+/* One product as bsdmrg_hpsi with a HIP event between consecutive kernel
+ * launches (synchronizing).  For launch i (i < cap) it returns the elapsed
+ * milliseconds ms[i], the algorithmic flops flops[i] of that launch and its kind
+ * kind[i] (0 output zero-fill, 1/2 phase-1 grouped GEMM with 64x64/32x32 tiles,
+ * 3/4 phase-2 grouped GEMM with 64x64/32x32 tiles).  *n_launches receives the
+ * number of launches. */
+int bsdmrg_hpsi_profile(bsdmrg_ctx* ctx, int site, const double* psi_dev, double* out_dev, int precision,
+                        bsdmrg_stream_t stream, int cap, double* ms, double* flops, int* kind,
+                        int* n_launches);
 
 /* Copy one renormalized block operator to the host (synchronizing).  kind is
  * one of 'H','c','A','B','S','P','Q' with spin-orbital indices p, q (-1 if

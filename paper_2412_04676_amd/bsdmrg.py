@@ -60,6 +60,11 @@ _SIGS = {
     "bsdmrg_hpsi": ([c_vp, c_int, c_vp, c_vp, c_int, c_vp], c_int),
     "bsdmrg_hpsi_info": ([c_vp, c_int, c_int, ctypes.POINTER(ctypes.c_double), c_i64p, c_i64p,
                           c_i64p, c_i64p], c_int),
+    "bsdmrg_hpsi_profile": ([c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_int, c_vp, c_vp, c_vp,
+                             ctypes.POINTER(c_int)], c_int),
+    "bsdmrg_davidson": ([c_vp, c_int, c_vp, c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_int),
+                         ctypes.POINTER(ctypes.c_double), c_vp, c_int, c_vp], c_int),
+    "bsdmrg_hpsi_diagonal": ([c_vp, c_int, c_vp, c_vp], c_int),
     "bsdmrg_get_block_op": ([c_vp, c_int, c_int, ctypes.c_char, c_int, c_int, ctypes.POINTER(c_int),
                              c_i64p, c_vp, c_vp], c_int),
     "bsdmrg_block_gemm": ([c_int, c_vp, c_vp], c_int),
@@ -184,6 +189,39 @@ def bsdmrg_hpsi_info(ctx, site, precision=FP64):
                                  ctypes.byref(c), ctypes.byref(d)))
     return {"flops": fl.value, "channels": a.value, "segments": b.value, "aggregates": c.value,
             "ws_bytes": d.value}
+
+
+def bsdmrg_hpsi_profile(ctx, site, psi_dev, out_dev, precision=FP64, stream=None, cap=256):
+    """Returns a list of (kind, ms, flops) per kernel launch of one product."""
+    ms = np.zeros(cap)
+    fl = np.zeros(cap)
+    kd = np.zeros(cap, dtype=np.int32)
+    n = c_int()
+    _check(_lib.bsdmrg_hpsi_profile(ctx, site, _ptr(psi_dev), _ptr(out_dev), precision, _stream(stream), cap,
+                                    _ptr(ms), _ptr(fl), _ptr(kd), ctypes.byref(n)))
+    return [(int(kd[i]), float(ms[i]), float(fl[i])) for i in range(min(n.value, cap))]
+
+
+class DavOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("max_subspace", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("tol", ctypes.c_double), ("precond_floor", ctypes.c_double)]
+
+
+def bsdmrg_davidson(ctx, site, psi_dev, max_iter=50, max_subspace=24, restart=4, tol=1e-8,
+                    precond_floor=1e-4, stream=None):
+    """Returns (energy, iterations, residual norm, list of Ritz values); psi_dev is overwritten."""
+    o = DavOpts(max_iter, max_subspace, restart, 0, tol, precond_floor)
+    e = ctypes.c_double()
+    it = c_int()
+    r = ctypes.c_double()
+    ritz = np.zeros(max_iter + 1)
+    _check(_lib.bsdmrg_davidson(ctx, site, _ptr(psi_dev), ctypes.byref(o), ctypes.byref(e), ctypes.byref(it),
+                                ctypes.byref(r), _ptr(ritz), len(ritz), _stream(stream)))
+    return e.value, it.value, r.value, list(ritz[:it.value])
+
+
+def bsdmrg_hpsi_diagonal(ctx, site, diag_dev, stream=None):
+    _check(_lib.bsdmrg_hpsi_diagonal(ctx, site, _ptr(diag_dev), _stream(stream)))
 
 
 def bsdmrg_get_block_op(ctx, side, bond, kind, p=-1, q=-1):

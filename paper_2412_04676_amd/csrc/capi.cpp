@@ -4,7 +4,7 @@
 #include <chrono>
 #include <cmath>
 
-#include "hpsi.h"
+#include "davidson.h"
 
 struct bsdmrg_ctx {
   bsd::Ctx c;
@@ -332,6 +332,56 @@ int bsdmrg_hpsi(bsdmrg_ctx* ctx, int site, const double* psi, double* out, int p
     BSD_CHECK(!(out < pe && psi < out + p->lay.n_elems), BSDMRG_EINVAL, "psi and out overlap");
     run_hpsi(*p, psi, out, S(stream));
     ctx->c.last_hpsi_flops = p->useful_flops;
+  });
+}
+
+int bsdmrg_hpsi_profile(bsdmrg_ctx* ctx, int site, const double* psi, double* out, int precision,
+                        bsdmrg_stream_t stream, int cap, double* ms, double* flops, int* kind, int* n) {
+  return guard([&] {
+    BSD_CHECK(ctx && psi && out && n && (cap <= 0 || (ms && flops && kind)), BSDMRG_EINVAL, "NULL argument");
+    HpsiPlan* p = get_plan(ctx->c, site, precision, 0, S(stream), false);
+    Block* Lb = get_block(ctx->c, true, site);
+    Block* Rb = get_block(ctx->c, false, site + 2);
+    BSD_CHECK(Lb && Rb && Lb->resident && Rb->resident, BSDMRG_EBUSY, "environment blocks not resident");
+    *n = profile_hpsi(*p, psi, out, S(stream), cap, ms, flops, kind);
+  });
+}
+
+int bsdmrg_davidson(bsdmrg_ctx* ctx, int site, double* psi, const bsdmrg_dav_opts* opts, double* energy,
+                    int* iters, double* resid, double* ritz, int cap, bsdmrg_stream_t stream) {
+  return guard([&] {
+    BSD_CHECK(ctx && psi && energy && iters && resid, BSDMRG_EINVAL, "NULL argument");
+    HpsiPlan* p = get_plan(ctx->c, site, BSDMRG_FP64, 0, S(stream), false);
+    Block* Lb = get_block(ctx->c, true, site);
+    Block* Rb = get_block(ctx->c, false, site + 2);
+    BSD_CHECK(Lb && Rb && Lb->resident && Rb->resident, BSDMRG_EBUSY, "environment blocks not resident");
+    DavidsonOpts o;
+    if (opts) {
+      BSD_CHECK(opts->max_iter > 0 && opts->max_subspace >= 4 && opts->max_subspace <= 30 && opts->restart >= 1 &&
+                    opts->restart < opts->max_subspace - 1 && opts->tol > 0 && opts->precond_floor > 0,
+                BSDMRG_EINVAL, "bad Davidson options");
+      o.max_iter = opts->max_iter;
+      o.max_sub = opts->max_subspace;
+      o.restart = opts->restart;
+      o.tol = opts->tol;
+      o.precond_floor = opts->precond_floor;
+    }
+    const double* d = hpsi_diagonal(*p, S(stream));
+    DavidsonResult r = davidson(*p, d, psi, o, p->dav_work, S(stream));
+    *energy = r.energy;
+    *iters = r.iters;
+    *resid = r.resid;
+    if (ritz)
+      for (int i = 0; i < cap && i < (int)r.ritz.size(); ++i) ritz[i] = r.ritz[i];
+  });
+}
+
+int bsdmrg_hpsi_diagonal(bsdmrg_ctx* ctx, int site, double* diag, bsdmrg_stream_t stream) {
+  return guard([&] {
+    BSD_CHECK(ctx && diag, BSDMRG_EINVAL, "NULL argument");
+    HpsiPlan* p = get_plan(ctx->c, site, BSDMRG_FP64, 0, S(stream), false);
+    const double* d = hpsi_diagonal(*p, S(stream));
+    BSD_HIP(hipMemcpyAsync(diag, d, p->lay.n_elems * sizeof(double), hipMemcpyDeviceToDevice, S(stream)));
   });
 }
 

@@ -145,16 +145,21 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs) {
   std::vector<GTile> t64, t32;
   std::vector<GSeg> sg;
   flops = 0.0;
+  flops64 = flops32 = 0.0;
   for (const auto& p : probs) {
     if (p.M <= 0 || p.N <= 0) continue;
     int seg0 = (int)sg.size();
+    const bool small = p.M <= 32 && p.N <= 32;
     for (const auto& s : p.segs) {
       if (s.K <= 0) continue;
       sg.push_back(s);
-      flops += 2.0 * p.M * (double)p.N * s.K;
+      if (!(s.flags & kIdentA)) {
+        double f = 2.0 * p.M * (double)p.N * s.K;
+        flops += f;
+        (small ? flops32 : flops64) += f;
+      }
     }
     int nseg = (int)sg.size() - seg0;
-    const bool small = p.M <= 32 && p.N <= 32;
     const int T = small ? 32 : 64;
     for (int m0 = 0; m0 < p.M; m0 += T)
       for (int n0 = 0; n0 < p.N; n0 += T) {
@@ -181,11 +186,16 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs) {
   if (!sg.empty()) BSD_HIP(hipMemcpy(segs.p, sg.data(), sg.size() * sizeof(GSeg), hipMemcpyHostToDevice));
 }
 
+void GemmPlan::launch64(const GBases& bases, hipStream_t s) const {
+  launch_grouped_gemm(static_cast<const GTile*>(tiles.p), ntiles64, 64, static_cast<const GSeg*>(segs.p), bases, s);
+}
+void GemmPlan::launch32(const GBases& bases, hipStream_t s) const {
+  launch_grouped_gemm(static_cast<const GTile*>(tiles.p) + ntiles64, ntiles32, 32,
+                      static_cast<const GSeg*>(segs.p), bases, s);
+}
 void GemmPlan::launch(const GBases& bases, hipStream_t s) const {
-  const GTile* t = static_cast<const GTile*>(tiles.p);
-  const GSeg* g = static_cast<const GSeg*>(segs.p);
-  launch_grouped_gemm(t, ntiles64, 64, g, bases, s);
-  launch_grouped_gemm(t + ntiles64, ntiles32, 32, g, bases, s);
+  launch64(bases, s);
+  launch32(bases, s);
 }
 
 }  // namespace bsd

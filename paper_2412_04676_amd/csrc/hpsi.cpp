@@ -449,6 +449,64 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
         }
     }
   }
+  // diagonal of H_eff: for every channel and group without a quantum-number
+  // change, diag(Lambda) (x) M[c][c] (x) diag(R_b), as K = 1 sector products
+  {
+    int maxd = 1;
+    for (int d : Lb->basis.dim) maxd = std::max(maxd, d);
+    for (int d : Rb->basis.dim) maxd = std::max(maxd, d);
+    plan->ones.reserve(maxd * sizeof(double));
+    std::vector<double> ones(maxd, 1.0);
+    BSD_HIP(hipMemcpy(plan->ones.p, ones.data(), maxd * sizeof(double), hipMemcpyHostToDevice));
+    const double* one = static_cast<const double*>(plan->ones.p);
+    std::map<int, GemmProblem> dprob;
+    for (size_t ci = 0; ci < chans.size(); ++ci) {
+      const auto& ch = chans[ci];
+      if (ch.rdq != Q{0, 0}) continue;
+      for (const auto& g : cgroups[ci]) {
+        const LRef& lr = lrefs[g.lref];
+        if (lr.dq != Q{0, 0}) continue;
+        for (int c = 0; c < 16; ++c) {
+          const double m = g.M(c, c);
+          if (m == 0.0) continue;
+          for (int bi : by_c[c]) {
+            const PsiBlk& pb = lay.blocks[bi];
+            Operand2 o = lref_block(*Lb, lr, agg_sk, agg_off, agg_mem, pb.l);
+            if (!o.ok) continue;
+            GSeg sg;
+            sg.K = 1;
+            sg.alpha = g.coef * m;
+            sg.A = tag_ptr(0, (uint64_t)(o.ident ? one : o.p));
+            sg.lda = o.ident ? 1 : o.ld + 1;
+            if (ch.rkind == 1) {
+              sg.B = tag_ptr(0, (uint64_t)one);
+              sg.ldb = 1;
+            } else {
+              int rr, cc, ld;
+              const double* p = Rb->op_block(ch.rkey, pb.r, &rr, &cc, &ld);
+              if (!p) continue;
+              sg.B = tag_ptr(0, (uint64_t)p);
+              sg.ldb = ld + 1;
+            }
+            sg.flags = kTransB;
+            auto& gp = dprob[bi];
+            if (gp.segs.empty()) {
+              gp.C = tag_ptr(2, (uint64_t)(pb.off * sizeof(double)));
+              gp.ldc = pb.cols;
+              gp.M = pb.rows;
+              gp.N = pb.cols;
+              gp.beta = 1.0;
+            }
+            gp.segs.push_back(sg);
+          }
+        }
+      }
+    }
+    std::vector<GemmProblem> v;
+    for (auto& kv : dprob) v.push_back(std::move(kv.second));
+    plan->diag_plan = std::make_unique<GemmPlan>();
+    plan->diag_plan->build(v);
+  }
   plan->nseg = 0;
   for (int k = 0; k < nchunks; ++k) {
     plan->phase1[k] = std::make_unique<GemmPlan>();
@@ -465,6 +523,67 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   plan->nchannels = (int)chans.size();
   plan->naggs = (int)agg_sk.size();
   return plan;
+}
+
+int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int cap,
+                 double* ms, double* flops, int* kind) {
+  // kind: 0 zero-fill, 1 phase-1 64x64 tiles, 2 phase-1 32x32, 3 phase-2 64x64, 4 phase-2 32x32
+  std::vector<hipEvent_t> ev;
+  std::vector<int> kinds;
+  std::vector<double> fl;
+  auto mark = [&]() {
+    hipEvent_t e;
+    BSD_HIP(hipEventCreate(&e));
+    BSD_HIP(hipEventRecord(e, s));
+    ev.push_back(e);
+  };
+  GBases b{{0, (uint64_t)psi, (uint64_t)out, 0}};
+  mark();
+  zero_fill(out, plan.lay.n_elems, s);
+  kinds.push_back(0);
+  fl.push_back(0.0);
+  mark();
+  for (size_t k = 0; k < plan.phase1.size(); ++k) {
+    plan.phase1[k]->launch64(b, s);
+    kinds.push_back(1);
+    fl.push_back(plan.phase1[k]->flops64);
+    mark();
+    plan.phase1[k]->launch32(b, s);
+    kinds.push_back(2);
+    fl.push_back(plan.phase1[k]->flops32);
+    mark();
+    plan.phase2[k]->launch64(b, s);
+    kinds.push_back(3);
+    fl.push_back(plan.phase2[k]->flops64);
+    mark();
+    plan.phase2[k]->launch32(b, s);
+    kinds.push_back(4);
+    fl.push_back(plan.phase2[k]->flops32);
+    mark();
+  }
+  BSD_HIP(hipStreamSynchronize(s));
+  int n = (int)kinds.size();
+  for (int i = 0; i < n && i < cap; ++i) {
+    float t = 0.f;
+    BSD_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+    ms[i] = t;
+    flops[i] = fl[i];
+    kind[i] = kinds[i];
+  }
+  for (auto e : ev) (void)hipEventDestroy(e);
+  return n;
+}
+
+const double* hpsi_diagonal(HpsiPlan& plan, hipStream_t s) {
+  if (!plan.diag_ready) {
+    plan.diag.reserve(std::max<int64_t>(1, plan.lay.n_elems) * sizeof(double));
+    double* d = static_cast<double*>(plan.diag.p);
+    zero_fill(d, plan.lay.n_elems, s);
+    GBases b{{0, 0, (uint64_t)d, 0}};
+    plan.diag_plan->launch(b, s);
+    plan.diag_ready = true;
+  }
+  return static_cast<const double*>(plan.diag.p);
 }
 
 void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s) {

@@ -35,6 +35,9 @@ struct HpsiPlan {
   DevBuf agg, V;
   size_t agg_bytes = 0, v_bytes = 0;
   std::vector<std::unique_ptr<GemmPlan>> phase1, phase2;
+  std::unique_ptr<GemmPlan> diag_plan;   // diagonal of H_eff (rank-1 sector products)
+  DevBuf ones, diag, dav_work;
+  bool diag_ready = false;
   double useful_flops = 0.0;
   size_t nseg = 0;
   int nchannels = 0, naggs = 0;
@@ -43,6 +46,10 @@ struct HpsiPlan {
 void build_psi_layout(const Block& Lb, const Block& Rb, const SiteSet& C, const Q& target, PsiLayout& lay);
 std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, size_t ws_budget, hipStream_t s);
 void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s);
+int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int cap, double* ms,
+                 double* flops, int* kind);
 void zero_fill(double* p, int64_t n, hipStream_t s);
+// diagonal of H_eff into the plan's own buffer (computed once per plan)
+const double* hpsi_diagonal(HpsiPlan& plan, hipStream_t s);
 
 }  // namespace bsd

@@ -269,9 +269,12 @@ struct GemmProblem {
 struct GemmPlan {
   int ntiles64 = 0, ntiles32 = 0;
   DevBuf tiles, segs;
-  double flops = 0.0;   // useful flops (2 M N K summed over segments)
+  double flops = 0.0;               // useful flops (2 M N K over non-identity segments)
+  double flops64 = 0.0, flops32 = 0.0;  // per launch group
   void build(const std::vector<GemmProblem>& probs);
   void launch(const GBases& bases, hipStream_t s) const;
+  void launch64(const GBases& bases, hipStream_t s) const;
+  void launch32(const GBases& bases, hipStream_t s) const;
 };
 
 struct AggTerm {
