@@ -53,7 +53,12 @@ enum {
 };
 
 enum { BSDMRG_LEFT = 0, BSDMRG_RIGHT = 1 };
-enum { BSDMRG_FP64 = 0 };
+/* Precision of the sector GEMMs.  FP64: float64 matrix cores.  BF16X3 /
+ * BF16X6: every float64 operand is split into 2 / 3 bfloat16 parts (round to
+ * nearest even) and the 3 / 6 leading cross products run on bf16 matrix cores
+ * with float32 accumulation, added into float64 every 256 values of K; inputs,
+ * outputs and all vector arithmetic stay float64. */
+enum { BSDMRG_FP64 = 0, BSDMRG_BF16X3 = 1, BSDMRG_BF16X6 = 2 };
 
 /* Last error message of the calling thread (never NULL). */
 const char* bsdmrg_last_error(void);
@@ -116,7 +121,7 @@ int bsdmrg_hpsi(bsdmrg_ctx* ctx, int site, const double* psi_dev, double* out_de
  * no parameters).  Defaults: max_iter 50, max_subspace 24, restart 4,
  * tol 1e-8 on the residual 2-norm, preconditioner floor 1e-4. */
 typedef struct {
-  int32_t max_iter, max_subspace, restart, pad;
+  int32_t max_iter, max_subspace, restart, precision;  /* precision of the H.psi products */
   double tol, precond_floor;
 } bsdmrg_dav_opts;
 
@@ -174,7 +179,7 @@ typedef struct {
   int64_t lda, ldb, ldc;
   double alpha, beta;
 } bsdmrg_gemm_desc;
-int bsdmrg_block_gemm(int n, const bsdmrg_gemm_desc* problems, bsdmrg_stream_t stream);
+int bsdmrg_block_gemm(int n, const bsdmrg_gemm_desc* problems, int precision, bsdmrg_stream_t stream);
 
 /* ---------------------------------------------------------------- serializer
  * Stream format: header (64 B), family table (64 B per family), block tables

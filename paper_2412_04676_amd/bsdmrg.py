@@ -16,7 +16,7 @@ LIBPATH = os.path.join(HERE, "libbsdmrg.so")
 
 OK, EINVAL, ESTATE, ESHAPE, ENOMEM, EHIP, EBUSY, ECORRUPT = range(8)
 LEFT, RIGHT = 0, 1
-FP64 = 0
+FP64, BF16X3, BF16X6 = 0, 1, 2
 QS = ((0, 0), (1, 0), (0, 1), (1, 1))
 
 
@@ -67,7 +67,7 @@ _SIGS = {
     "bsdmrg_hpsi_diagonal": ([c_vp, c_int, c_vp, c_vp], c_int),
     "bsdmrg_get_block_op": ([c_vp, c_int, c_int, ctypes.c_char, c_int, c_int, ctypes.POINTER(c_int),
                              c_i64p, c_vp, c_vp], c_int),
-    "bsdmrg_block_gemm": ([c_int, c_vp, c_vp], c_int),
+    "bsdmrg_block_gemm": ([c_int, c_vp, c_int, c_vp], c_int),
     "bsdmrg_serialized_size_desc": ([c_int, c_vp, ctypes.POINTER(c_sz)], c_int),
     "bsdmrg_pack_desc": ([c_int, c_vp, c_vp, c_sz, c_vp], c_int),
     "bsdmrg_unpack_desc": ([c_int, c_vp, c_vp, c_sz, c_vp], c_int),
@@ -204,13 +204,13 @@ def bsdmrg_hpsi_profile(ctx, site, psi_dev, out_dev, precision=FP64, stream=None
 
 class DavOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("max_subspace", ctypes.c_int32), ("restart", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("tol", ctypes.c_double), ("precond_floor", ctypes.c_double)]
+                ("precision", ctypes.c_int32), ("tol", ctypes.c_double), ("precond_floor", ctypes.c_double)]
 
 
 def bsdmrg_davidson(ctx, site, psi_dev, max_iter=50, max_subspace=24, restart=4, tol=1e-8,
-                    precond_floor=1e-4, stream=None):
+                    precond_floor=1e-4, precision=FP64, stream=None):
     """Returns (energy, iterations, residual norm, list of Ritz values); psi_dev is overwritten."""
-    o = DavOpts(max_iter, max_subspace, restart, 0, tol, precond_floor)
+    o = DavOpts(max_iter, max_subspace, restart, precision, tol, precond_floor)
     e = ctypes.c_double()
     it = c_int()
     r = ctypes.c_double()
@@ -246,7 +246,7 @@ def bsdmrg_get_block_op(ctx, side, bond, kind, p=-1, q=-1):
     return out
 
 
-def bsdmrg_block_gemm(problems, stream=None):
+def bsdmrg_block_gemm(problems, precision=FP64, stream=None):
     """problems: list of dicts with torch tensors A, B, C and M, N, K, lda, ldb, ldc,
     transA, transB, alpha, beta."""
     arr = (GemmDesc * max(1, len(problems)))()
@@ -254,7 +254,7 @@ def bsdmrg_block_gemm(problems, stream=None):
         arr[i] = GemmDesc(_ptr(p["A"]), _ptr(p["B"]), _ptr(p["C"]), p["M"], p["N"], p["K"],
                           int(p.get("transA", 0)), int(p.get("transB", 0)), 0, p["lda"], p["ldb"], p["ldc"],
                           p.get("alpha", 1.0), p.get("beta", 0.0))
-    _check(_lib.bsdmrg_block_gemm(len(problems), arr, _stream(stream)))
+    _check(_lib.bsdmrg_block_gemm(len(problems), arr, precision, _stream(stream)))
 
 
 def make_family_descs(fams):

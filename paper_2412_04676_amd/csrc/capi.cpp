@@ -268,8 +268,8 @@ int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream
 
 static HpsiPlan* get_plan(Ctx& c, int site, int precision, size_t ws, hipStream_t s, bool rebuild) {
   BSD_CHECK(site >= 0 && site + 1 < c.L, BSDMRG_EINVAL, "site out of range");
-  BSD_CHECK(precision == BSDMRG_FP64, BSDMRG_EINVAL, "unsupported precision");
-  auto key = std::make_pair(site, precision);
+  BSD_CHECK(precision >= BSDMRG_FP64 && precision <= BSDMRG_BF16X6, BSDMRG_EINVAL, "unsupported precision");
+  auto key = std::make_pair(site, 0);   // one plan serves every precision
   auto it = c.plans.find(key);
   if (it != c.plans.end() && !rebuild) return it->second.get();
   if (ws == 0) ws = (size_t)4 << 30;
@@ -330,7 +330,7 @@ int bsdmrg_hpsi(bsdmrg_ctx* ctx, int site, const double* psi, double* out, int p
     BSD_CHECK(Lb && Rb && Lb->resident && Rb->resident, BSDMRG_EBUSY, "environment blocks not resident");
     const double* pe = psi + p->lay.n_elems;
     BSD_CHECK(!(out < pe && psi < out + p->lay.n_elems), BSDMRG_EINVAL, "psi and out overlap");
-    run_hpsi(*p, psi, out, S(stream));
+    run_hpsi(*p, psi, out, S(stream), precision);
     ctx->c.last_hpsi_flops = p->useful_flops;
   });
 }
@@ -343,7 +343,7 @@ int bsdmrg_hpsi_profile(bsdmrg_ctx* ctx, int site, const double* psi, double* ou
     Block* Lb = get_block(ctx->c, true, site);
     Block* Rb = get_block(ctx->c, false, site + 2);
     BSD_CHECK(Lb && Rb && Lb->resident && Rb->resident, BSDMRG_EBUSY, "environment blocks not resident");
-    *n = profile_hpsi(*p, psi, out, S(stream), cap, ms, flops, kind);
+    *n = profile_hpsi(*p, psi, out, S(stream), precision, cap, ms, flops, kind);
   });
 }
 
@@ -358,8 +358,10 @@ int bsdmrg_davidson(bsdmrg_ctx* ctx, int site, double* psi, const bsdmrg_dav_opt
     DavidsonOpts o;
     if (opts) {
       BSD_CHECK(opts->max_iter > 0 && opts->max_subspace >= 4 && opts->max_subspace <= 30 && opts->restart >= 1 &&
-                    opts->restart < opts->max_subspace - 1 && opts->tol > 0 && opts->precond_floor > 0,
+                    opts->restart < opts->max_subspace - 1 && opts->tol > 0 && opts->precond_floor > 0 &&
+                    opts->precision >= BSDMRG_FP64 && opts->precision <= BSDMRG_BF16X6,
                 BSDMRG_EINVAL, "bad Davidson options");
+      o.precision = opts->precision;
       o.max_iter = opts->max_iter;
       o.max_sub = opts->max_subspace;
       o.restart = opts->restart;
@@ -389,7 +391,8 @@ int bsdmrg_hpsi_info(bsdmrg_ctx* ctx, int site, int precision, double* flops, in
                      int64_t* n_segments, int64_t* n_aggregates, int64_t* ws_bytes) {
   return guard([&] {
     BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
-    auto it = ctx->c.plans.find({site, precision});
+    BSD_CHECK(precision >= BSDMRG_FP64 && precision <= BSDMRG_BF16X6, BSDMRG_EINVAL, "unsupported precision");
+    auto it = ctx->c.plans.find({site, 0});
     BSD_CHECK(it != ctx->c.plans.end(), BSDMRG_ESTATE, "product not prepared");
     const HpsiPlan& p = *it->second;
     if (flops) *flops = p.useful_flops;
@@ -439,9 +442,10 @@ int bsdmrg_get_block_op(bsdmrg_ctx* ctx, int side, int bond, char kind, int p, i
   });
 }
 
-int bsdmrg_block_gemm(int n, const bsdmrg_gemm_desc* probs, bsdmrg_stream_t stream) {
+int bsdmrg_block_gemm(int n, const bsdmrg_gemm_desc* probs, int precision, bsdmrg_stream_t stream) {
   return guard([&] {
     BSD_CHECK(n >= 0 && (n == 0 || probs), BSDMRG_EINVAL, "bad problem list");
+    BSD_CHECK(precision >= BSDMRG_FP64 && precision <= BSDMRG_BF16X6, BSDMRG_EINVAL, "unsupported precision");
     std::vector<GemmProblem> v;
     for (int i = 0; i < n; ++i) {
       const auto& d = probs[i];
@@ -473,7 +477,7 @@ int bsdmrg_block_gemm(int n, const bsdmrg_gemm_desc* probs, bsdmrg_stream_t stre
     GemmPlan plan;
     plan.build(v);
     GBases b{{0, 0, 0, 0}};
-    plan.launch(b, S(stream));
+    plan.launch(b, S(stream), precision);
     BSD_HIP(hipStreamSynchronize(S(stream)));
   });
 }

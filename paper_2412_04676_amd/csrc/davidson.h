@@ -10,6 +10,7 @@ struct DavidsonOpts {
   int restart = 4;
   double tol = 1e-8;
   double precond_floor = 1e-4;
+  int precision = 0;   // precision of the H.psi products
 };
 
 struct DavidsonResult {

@@ -253,7 +253,7 @@ DavidsonResult davidson(const HpsiPlan& plan, const double* diag, double* psi, c
   w.ev = w.Y + 32 * 32;
   w.sc = w.ev + 32;
   const int G = grid_for(n);
-  auto H = [&](const double* in, double* out) { run_hpsi(plan, in, out, s); };
+  auto H = [&](const double* in, double* out) { run_hpsi(plan, in, out, s, o.precision); };
   auto normalize_into = [&](const double* in, double* out) {
     dots(w, in, 1, in, w.sc + 2, s);
     hipLaunchKernelGGL(scale_by_inv_kernel, dim3(G), dim3(256), 0, s, in, w.sc + 2, out, n);

@@ -104,13 +104,171 @@ grouped_gemm_kernel(const GTile* __restrict__ tiles, const GSeg* __restrict__ se
       }
 }
 
+// ---------------------------------------------------------------- split-bf16 variant
+// Each float64 operand x is split while it is staged into LDS:
+//   2 parts: x ~ h + m,          3 parts: x ~ h + m + l,
+// with h = bf16(x), m = bf16(x - h), l = bf16(x - h - m) (round to nearest
+// even).  The products kept are h h + h m + m h (3 MFMA products) or
+// h h + h m + m h + h l + m m + l h (6 products); v_mfma_f32_16x16x32_bf16
+// accumulates them in float32, and the float32 accumulators are added into
+// float64 accumulators after every 256 values of K.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ double bf16_to_double(unsigned short h) {
+  return (double)__uint_as_float(((unsigned int)h) << 16);
+}
+
+constexpr int KB16 = 32;     // K per MFMA step
+constexpr int KPAD = 40;     // LDS row stride in bf16 (80 bytes)
+constexpr int kFlushSteps = 8;
+
+template <int WM, int WN, int NPARTS>
+__global__ void __launch_bounds__(64 * WM * WN)
+grouped_gemm_bf16_kernel(const GTile* __restrict__ tiles, const GSeg* __restrict__ segs, GBases bases) {
+  constexpr int TM = 32 * WM, TN = 32 * WN, NT = 64 * WM * WN;
+  __shared__ __attribute__((aligned(16))) unsigned short As[NPARTS][TM][KPAD];
+  __shared__ __attribute__((aligned(16))) unsigned short Bs[NPARTS][TN][KPAD];
+
+  const GTile tile = tiles[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wr = (wave / WN) * 32;
+  const int wc = (wave % WN) * 32;
+  const int mt = min(TM, tile.M - tile.m0);
+  const int nt = min(TN, tile.N - tile.n0);
+
+  float4_t acc[2][2];
+  double4_t acc64[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+      acc64[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    }
+  int steps = 0;
+
+  for (int sidx = 0; sidx < tile.nseg; ++sidx) {
+    const GSeg sg = segs[tile.seg0 + sidx];
+    const double* A = resolve(sg.A, bases);
+    const double* B = resolve(sg.B, bases);
+    const bool ta = sg.flags & kTransA, tb = sg.flags & kTransB, ia = sg.flags & kIdentA;
+    const double alpha = sg.alpha;
+    for (int k0 = 0; k0 < sg.K; k0 += KB16) {
+      for (int e = tid; e < TM * KB16; e += NT) {
+        int i, k;
+        if (ta) { k = e / TM; i = e % TM; } else { i = e / KB16; k = e % KB16; }
+        const int gi = tile.m0 + i, gk = k0 + k;
+        double v = 0.0;
+        if (i < mt && gk < sg.K) {
+          if (ia) v = (gi == gk) ? alpha : 0.0;
+          else v = alpha * (ta ? A[(int64_t)gk * sg.lda + gi] : A[(int64_t)gi * sg.lda + gk]);
+        }
+        const unsigned short h = bf16_rne((float)v);
+        As[0][i][k] = h;
+        const double r1 = v - bf16_to_double(h);
+        const unsigned short m = bf16_rne((float)r1);
+        As[1][i][k] = m;
+        if (NPARTS == 3) As[NPARTS - 1][i][k] = bf16_rne((float)(r1 - bf16_to_double(m)));
+      }
+      for (int e = tid; e < KB16 * TN; e += NT) {
+        int j, k;
+        if (tb) { j = e / KB16; k = e % KB16; } else { k = e / TN; j = e % TN; }
+        const int gj = tile.n0 + j, gk = k0 + k;
+        double v = 0.0;
+        if (j < nt && gk < sg.K) v = tb ? B[(int64_t)gj * sg.ldb + gk] : B[(int64_t)gk * sg.ldb + gj];
+        const unsigned short h = bf16_rne((float)v);
+        Bs[0][j][k] = h;
+        const double r1 = v - bf16_to_double(h);
+        const unsigned short m = bf16_rne((float)r1);
+        Bs[1][j][k] = m;
+        if (NPARTS == 3) Bs[NPARTS - 1][j][k] = bf16_rne((float)(r1 - bf16_to_double(m)));
+      }
+      __syncthreads();
+      const int kq = (lane >> 4) * 8;
+      bf16x8_t a[NPARTS][2], b[NPARTS][2];
+#pragma unroll
+      for (int p = 0; p < NPARTS; ++p) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          a[p][i] = *reinterpret_cast<const bf16x8_t*>(&As[p][wr + i * 16 + (lane & 15)][kq]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          b[p][j] = *reinterpret_cast<const bf16x8_t*>(&Bs[p][wc + j * 16 + (lane & 15)][kq]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          float4_t c = acc[i][j];
+          if (NPARTS == 3) {
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2][i], b[0][j], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[1][j], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[2][j], c, 0, 0, 0);
+          }
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1][i], b[0][j], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[1][j], c, 0, 0, 0);
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][i], b[0][j], c, 0, 0, 0);
+          acc[i][j] = c;
+        }
+      __syncthreads();
+      if (++steps == kFlushSteps) {
+        steps = 0;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];
+            acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+          }
+      }
+    }
+  }
+  double* C = const_cast<double*>(resolve(tile.C, bases));
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = wr + i * 16 + 4 * (lane >> 4) + v;
+        const int c = wc + j * 16 + (lane & 15);
+        if (r < mt && c < nt) {
+          double* p = C + (int64_t)(tile.m0 + r) * tile.ldc + (tile.n0 + c);
+          double x = acc64[i][j][v] + (double)acc[i][j][v];
+          if (tile.beta != 0.0) x += tile.beta * (*p);
+          *p = x;
+        }
+      }
+}
+
 void launch_grouped_gemm(const GTile* tiles, int ntiles, int tile, const GSeg* segs,
-                         const GBases& b, hipStream_t s) {
+                         const GBases& b, hipStream_t s, int precision) {
   if (ntiles <= 0) return;
-  if (tile == 64)
-    hipLaunchKernelGGL((grouped_gemm_kernel<2, 2>), dim3(ntiles), dim3(256), 0, s, tiles, segs, b);
-  else
-    hipLaunchKernelGGL((grouped_gemm_kernel<1, 1>), dim3(ntiles), dim3(64), 0, s, tiles, segs, b);
+  if (precision == 0) {
+    if (tile == 64)
+      hipLaunchKernelGGL((grouped_gemm_kernel<2, 2>), dim3(ntiles), dim3(256), 0, s, tiles, segs, b);
+    else
+      hipLaunchKernelGGL((grouped_gemm_kernel<1, 1>), dim3(ntiles), dim3(64), 0, s, tiles, segs, b);
+  } else if (precision == 1) {
+    if (tile == 64)
+      hipLaunchKernelGGL((grouped_gemm_bf16_kernel<2, 2, 2>), dim3(ntiles), dim3(256), 0, s, tiles, segs, b);
+    else
+      hipLaunchKernelGGL((grouped_gemm_bf16_kernel<1, 1, 2>), dim3(ntiles), dim3(64), 0, s, tiles, segs, b);
+  } else {
+    if (tile == 64)
+      hipLaunchKernelGGL((grouped_gemm_bf16_kernel<2, 2, 3>), dim3(ntiles), dim3(256), 0, s, tiles, segs, b);
+    else
+      hipLaunchKernelGGL((grouped_gemm_bf16_kernel<1, 1, 3>), dim3(ntiles), dim3(64), 0, s, tiles, segs, b);
+  }
   BSD_HIP(hipGetLastError());
 }
 
@@ -186,16 +344,17 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs) {
   if (!sg.empty()) BSD_HIP(hipMemcpy(segs.p, sg.data(), sg.size() * sizeof(GSeg), hipMemcpyHostToDevice));
 }
 
-void GemmPlan::launch64(const GBases& bases, hipStream_t s) const {
-  launch_grouped_gemm(static_cast<const GTile*>(tiles.p), ntiles64, 64, static_cast<const GSeg*>(segs.p), bases, s);
+void GemmPlan::launch64(const GBases& bases, hipStream_t s, int precision) const {
+  launch_grouped_gemm(static_cast<const GTile*>(tiles.p), ntiles64, 64, static_cast<const GSeg*>(segs.p), bases, s,
+                      precision);
 }
-void GemmPlan::launch32(const GBases& bases, hipStream_t s) const {
+void GemmPlan::launch32(const GBases& bases, hipStream_t s, int precision) const {
   launch_grouped_gemm(static_cast<const GTile*>(tiles.p) + ntiles64, ntiles32, 32,
-                      static_cast<const GSeg*>(segs.p), bases, s);
+                      static_cast<const GSeg*>(segs.p), bases, s, precision);
 }
-void GemmPlan::launch(const GBases& bases, hipStream_t s) const {
-  launch64(bases, s);
-  launch32(bases, s);
+void GemmPlan::launch(const GBases& bases, hipStream_t s, int precision) const {
+  launch64(bases, s, precision);
+  launch32(bases, s, precision);
 }
 
 }  // namespace bsd

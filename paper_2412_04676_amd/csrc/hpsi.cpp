@@ -122,7 +122,6 @@ static Operand2 lref_block(const Block& Lb, const LRef& r, const std::vector<Ske
 
 std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, size_t ws_budget,
                                           hipStream_t s) {
-  BSD_CHECK(precision == 0, 1, "only the float64 path is available");
   Block* Lb = get_block(ctx, true, site);
   Block* Rb = get_block(ctx, false, site + 2);
   BSD_CHECK(Lb && Rb, 1, "environment blocks for this site are not built");
@@ -525,7 +524,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   return plan;
 }
 
-int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int cap,
+int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision, int cap,
                  double* ms, double* flops, int* kind) {
   // kind: 0 zero-fill, 1 phase-1 64x64 tiles, 2 phase-1 32x32, 3 phase-2 64x64, 4 phase-2 32x32
   std::vector<hipEvent_t> ev;
@@ -544,19 +543,19 @@ int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream
   fl.push_back(0.0);
   mark();
   for (size_t k = 0; k < plan.phase1.size(); ++k) {
-    plan.phase1[k]->launch64(b, s);
+    plan.phase1[k]->launch64(b, s, precision);
     kinds.push_back(1);
     fl.push_back(plan.phase1[k]->flops64);
     mark();
-    plan.phase1[k]->launch32(b, s);
+    plan.phase1[k]->launch32(b, s, precision);
     kinds.push_back(2);
     fl.push_back(plan.phase1[k]->flops32);
     mark();
-    plan.phase2[k]->launch64(b, s);
+    plan.phase2[k]->launch64(b, s, precision);
     kinds.push_back(3);
     fl.push_back(plan.phase2[k]->flops64);
     mark();
-    plan.phase2[k]->launch32(b, s);
+    plan.phase2[k]->launch32(b, s, precision);
     kinds.push_back(4);
     fl.push_back(plan.phase2[k]->flops32);
     mark();
@@ -586,12 +585,12 @@ const double* hpsi_diagonal(HpsiPlan& plan, hipStream_t s) {
   return static_cast<const double*>(plan.diag.p);
 }
 
-void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s) {
+void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision) {
   zero_fill(out, plan.lay.n_elems, s);
   GBases b{{0, (uint64_t)psi, (uint64_t)out, 0}};
   for (size_t k = 0; k < plan.phase1.size(); ++k) {
-    plan.phase1[k]->launch(b, s);
-    plan.phase2[k]->launch(b, s);
+    plan.phase1[k]->launch(b, s, precision);
+    plan.phase2[k]->launch(b, s, precision);
   }
 }
 

@@ -45,9 +45,10 @@ struct HpsiPlan {
 
 void build_psi_layout(const Block& Lb, const Block& Rb, const SiteSet& C, const Q& target, PsiLayout& lay);
 std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, size_t ws_budget, hipStream_t s);
-void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s);
-int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int cap, double* ms,
-                 double* flops, int* kind);
+// precision: 0 float64, 1 split-bf16 x3, 2 split-bf16 x6 (the plan is shared)
+void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision = 0);
+int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision, int cap,
+                 double* ms, double* flops, int* kind);
 void zero_fill(double* p, int64_t n, hipStream_t s);
 // diagonal of H_eff into the plan's own buffer (computed once per plan)
 const double* hpsi_diagonal(HpsiPlan& plan, hipStream_t s);

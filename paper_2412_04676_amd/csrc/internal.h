@@ -272,9 +272,10 @@ struct GemmPlan {
   double flops = 0.0;               // useful flops (2 M N K over non-identity segments)
   double flops64 = 0.0, flops32 = 0.0;  // per launch group
   void build(const std::vector<GemmProblem>& probs);
-  void launch(const GBases& bases, hipStream_t s) const;
-  void launch64(const GBases& bases, hipStream_t s) const;
-  void launch32(const GBases& bases, hipStream_t s) const;
+  // precision: 0 float64 MFMA, 1 split-bf16 (3 products), 2 split-bf16 (6 products)
+  void launch(const GBases& bases, hipStream_t s, int precision = 0) const;
+  void launch64(const GBases& bases, hipStream_t s, int precision = 0) const;
+  void launch32(const GBases& bases, hipStream_t s, int precision = 0) const;
 };
 
 struct AggTerm {
@@ -293,7 +294,7 @@ struct AggTask {
 void launch_aggregate(const AggTask* tasks_dev, const AggTerm* terms_dev, int ntasks,
                       hipStream_t s);
 void launch_grouped_gemm(const GTile* tiles, int ntiles, int tile, const GSeg* segs,
-                         const GBases& b, hipStream_t s);
+                         const GBases& b, hipStream_t s, int precision = 0);
 
 // ---------------------------------------------------------------- serializer
 struct FamilyView {

@@ -50,3 +50,38 @@ def test_block_gemm_empty_and_k0():
     B.bsdmrg_block_gemm([])
     with pytest.raises(B.BsdmrgError):
         B.bsdmrg_block_gemm([{"A": A, "B": A, "C": C, "M": 4, "N": 4, "K": 2, "lda": 1, "ldb": 4, "ldc": 4}])
+
+
+@pytest.mark.parametrize("precision,nparts", [(1, 2), (2, 3)])
+def test_split_bf16_gemm_error_bound(precision, nparts):
+    """Element-wise bound from the split: each operand keeps 8 nparts mantissa
+    bits (dropped products <= 3 u^nparts |a||b| with u = 2^-8 per part after
+    the leading one), plus float32 accumulation over at most 256 values of K
+    between float64 flushes (<= 2^-24 (sqrt(256) + 2) |a||b| per flush)."""
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    rng = np.random.default_rng(1)
+    shapes = [(7, 9, 5), (64, 64, 300), (100, 37, 1000), (33, 130, 64)]
+    probs, data = [], []
+    for (M, N, K) in shapes:
+        A = rng.normal(size=(M, K)) * np.exp(rng.normal(size=(M, K)))
+        Bm = rng.normal(size=(K, N))
+        tA, tB = torch.from_numpy(A).cuda(), torch.from_numpy(Bm).cuda()
+        tC = torch.zeros(M, N, dtype=torch.float64, device="cuda")
+        probs.append({"A": tA, "B": tB, "C": tC, "M": M, "N": N, "K": K, "lda": K, "ldb": N, "ldc": N})
+        data.append((A, Bm, tC))
+    say(f"split bf16 x{3 if nparts == 2 else 6}")
+    B.bsdmrg_block_gemm(probs, precision)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for A, Bm, tC in data:
+        ref = A @ Bm
+        absprod = np.abs(A) @ np.abs(Bm)
+        u = 2.0 ** -8
+        split = 3.0 * u ** nparts * 2.0 if nparts == 2 else 6.0 * u ** 3 * 2.0
+        acc = 2.0 ** -24 * (np.sqrt(256) + 2) * (A.shape[1] / 256 + 1)
+        bound = (split + acc) * absprod
+        err = np.abs(tC.cpu().numpy() - ref)
+        assert np.all(err <= bound), float((err / bound).max())
+        worst = max(worst, float(np.linalg.norm(err) / np.linalg.norm(ref)))
+    say(f"  worst relative 2-norm error {worst:.2e}")
