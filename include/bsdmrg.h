@@ -136,6 +136,20 @@ typedef struct {
 int bsdmrg_davidson(bsdmrg_ctx* ctx, int site, double* psi_dev, const bsdmrg_dav_opts* opts, double* energy,
                     int* iters, double* resid, double* ritz, int cap, bsdmrg_stream_t stream);
 
+/* Truncation (Sec. II.B step 3) of the two-site wave function psi_dev at
+ * `site` across its middle bond: the Gram matrix of each middle sector is
+ * formed by the grouped GEMM and diagonalized by a parallel Jacobi method
+ * (float64, one workgroup per sector, sectors up to 1024 states).  Kept states:
+ * the D largest singular values, extended to every value >= sigma_D (1 - 1e-10),
+ * values <= 1e-14 sigma_max dropped.  direction 0 (left to right) replaces the
+ * site tensor of `site` by the kept left singular vectors (left-canonical);
+ * direction 1 replaces the tensor of site+1 by the kept right singular vectors
+ * (right-canonical).  Blocks depending on the replaced tensor are dropped.
+ * trunc_err receives the discarded weight, D_kept the kept count, sv (optional,
+ * cap entries) the kept singular values in descending order.  Synchronizing. */
+int bsdmrg_truncate(bsdmrg_ctx* ctx, int site, const double* psi_dev, int D, int direction, double* trunc_err,
+                    int* D_kept, double* sv, int cap, bsdmrg_stream_t stream);
+
 /* Diagonal of H_eff at `site` into diag_dev (psi layout), stream-ordered. */
 int bsdmrg_hpsi_diagonal(bsdmrg_ctx* ctx, int site, double* diag_dev, bsdmrg_stream_t stream);
 

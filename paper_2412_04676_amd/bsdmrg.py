@@ -65,6 +65,8 @@ _SIGS = {
     "bsdmrg_davidson": ([c_vp, c_int, c_vp, c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_int),
                          ctypes.POINTER(ctypes.c_double), c_vp, c_int, c_vp], c_int),
     "bsdmrg_hpsi_diagonal": ([c_vp, c_int, c_vp, c_vp], c_int),
+    "bsdmrg_truncate": ([c_vp, c_int, c_vp, c_int, c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_int),
+                         c_vp, c_int, c_vp], c_int),
     "bsdmrg_get_block_op": ([c_vp, c_int, c_int, ctypes.c_char, c_int, c_int, ctypes.POINTER(c_int),
                              c_i64p, c_vp, c_vp], c_int),
     "bsdmrg_block_gemm": ([c_int, c_vp, c_int, c_vp], c_int),
@@ -222,6 +224,17 @@ def bsdmrg_davidson(ctx, site, psi_dev, max_iter=50, max_subspace=24, restart=4,
 
 def bsdmrg_hpsi_diagonal(ctx, site, diag_dev, stream=None):
     _check(_lib.bsdmrg_hpsi_diagonal(ctx, site, _ptr(diag_dev), _stream(stream)))
+
+
+def bsdmrg_truncate(ctx, site, psi_dev, D, direction, stream=None, cap=None):
+    """Returns (truncation error, kept count, kept singular values)."""
+    cap = cap or 4 * D + 64
+    err = ctypes.c_double()
+    k = c_int()
+    sv = np.zeros(cap)
+    _check(_lib.bsdmrg_truncate(ctx, site, _ptr(psi_dev), D, direction, ctypes.byref(err), ctypes.byref(k),
+                                _ptr(sv), cap, _stream(stream)))
+    return err.value, k.value, sv[:min(k.value, cap)].copy()
 
 
 def bsdmrg_get_block_op(ctx, side, bond, kind, p=-1, q=-1):

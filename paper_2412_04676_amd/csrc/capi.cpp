@@ -5,6 +5,7 @@
 #include <cmath>
 
 #include "davidson.h"
+#include "truncate.h"
 
 struct bsdmrg_ctx {
   bsd::Ctx c;
@@ -186,10 +187,9 @@ int bsdmrg_load_integrals(bsdmrg_ctx* ctx, const double* h, const double* eri, d
   });
 }
 
-int bsdmrg_set_site_tensor(bsdmrg_ctx* ctx, int site, int n_blocks, const int32_t* meta, const double* data) {
-  return guard([&] {
-    BSD_CHECK(ctx && meta && data, BSDMRG_EINVAL, "NULL argument");
-    Ctx& c = ctx->c;
+static HpsiPlan* get_plan(Ctx& c, int site, int precision, size_t ws, hipStream_t s, bool rebuild);
+
+static void set_site_tensor_impl(Ctx& c, int site, int n_blocks, const int32_t* meta, const double* data) {
     BSD_CHECK(site >= 0 && site < c.L, BSDMRG_EINVAL, "site out of range");
     BSD_CHECK(n_blocks > 0, BSDMRG_EINVAL, "no blocks");
     SiteTensor T;
@@ -235,6 +235,36 @@ int bsdmrg_set_site_tensor(bsdmrg_ctx* ctx, int site, int n_blocks, const int32_
     for (auto it = c.left.begin(); it != c.left.end();) it = it->first > site ? c.left.erase(it) : std::next(it);
     for (auto it = c.right.begin(); it != c.right.end();) it = it->first <= site ? c.right.erase(it) : std::next(it);
     c.plans.clear();
+}
+
+int bsdmrg_set_site_tensor(bsdmrg_ctx* ctx, int site, int n_blocks, const int32_t* meta, const double* data) {
+  return guard([&] {
+    BSD_CHECK(ctx && meta && data, BSDMRG_EINVAL, "NULL argument");
+    set_site_tensor_impl(ctx->c, site, n_blocks, meta, data);
+  });
+}
+
+int bsdmrg_truncate(bsdmrg_ctx* ctx, int site, const double* psi, int D, int direction, double* trunc_err,
+                    int* D_kept, double* sv, int cap, bsdmrg_stream_t stream) {
+  return guard([&] {
+    BSD_CHECK(ctx && psi && trunc_err && D_kept, BSDMRG_EINVAL, "NULL argument");
+    BSD_CHECK(D > 0, BSDMRG_EINVAL, "D must be positive");
+    BSD_CHECK(direction == 0 || direction == 1, BSDMRG_EINVAL, "direction must be 0 (left to right) or 1");
+    Ctx& c = ctx->c;
+    HpsiPlan* p = get_plan(c, site, BSDMRG_FP64, 0, S(stream), false);
+    TruncResult r = truncate_psi(c, *p, psi, D, direction == 0, p->dav_work, S(stream));
+    BSD_CHECK(!r.blocks.empty(), BSDMRG_ESHAPE, "nothing kept");
+    std::vector<int32_t> meta;
+    std::vector<double> data;
+    for (const auto& b : r.blocks) {
+      meta.insert(meta.end(), {b.ql.a, b.ql.b, b.s, b.rows, b.cols});
+      data.insert(data.end(), b.data.begin(), b.data.end());
+    }
+    *trunc_err = r.trunc_err;
+    *D_kept = r.D_kept;
+    if (sv)
+      for (int i = 0; i < cap && i < (int)r.sv.size(); ++i) sv[i] = r.sv[i];
+    set_site_tensor_impl(c, direction == 0 ? site : site + 1, (int)r.blocks.size(), meta.data(), data.data());
   });
 }
 

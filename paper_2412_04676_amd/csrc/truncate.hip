@@ -1,0 +1,324 @@
+// Truncation of the two-site wave function (Sec. II.B step 3: "a new basis
+// is formed for the enlarged block via SVD"), float64 on the device.
+//
+// psi is split across the middle bond: rows (s1, q_l), columns (s2, q_r) for
+// each middle sector q_m = q_l + q_s1.  The left (right) singular vectors are
+// the eigenvectors of the Gram matrix G = M M^T (M^T M), formed by the
+// grouped-GEMM engine with the K dimension concatenated over the other local
+// state, and diagonalized by a parallel round-robin Jacobi method in one
+// workgroup per sector.  Singular values are sqrt of the eigenvalues.  The
+// kept states follow one global rule: the D largest, extended to every value
+// >= sigma_D (1 - 1e-10), values <= 1e-14 sigma_max dropped.
+#include "truncate.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace bsd {
+
+// One workgroup per sector.  G (m x m, ld m, m even) is overwritten by its
+// eigenvalues on the diagonal, V (m x m) receives the eigenvectors as columns.
+__global__ void __launch_bounds__(1024)
+jacobi_kernel(const int64_t* __restrict__ goff, const int* __restrict__ dims, double* __restrict__ G,
+              double* __restrict__ V, int max_sweeps) {
+  const int m = dims[blockIdx.x];
+  double* A = G + goff[blockIdx.x];
+  double* Z = V + goff[blockIdx.x];
+  __shared__ double cs[512], sn[512];
+  __shared__ int pp[512], qq[512];
+  __shared__ double red[1024];
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int64_t e = t; e < (int64_t)m * m; e += nt) Z[e] = ((e / m) == (e % m)) ? 1.0 : 0.0;
+  __syncthreads();
+  if (m < 2) return;
+  const int half = m / 2;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    // convergence: off-diagonal norm against the diagonal norm
+    double o = 0.0, d = 0.0;
+    for (int64_t e = t; e < (int64_t)m * m; e += nt) {
+      const double v = A[e];
+      if ((e / m) == (e % m)) d += v * v;
+      else o += v * v;
+    }
+    red[t] = o;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+      if (t < s) red[t] += red[t + s];
+      __syncthreads();
+    }
+    const double off = red[0];
+    __syncthreads();
+    red[t] = d;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+      if (t < s) red[t] += red[t + s];
+      __syncthreads();
+    }
+    const double dia = red[0];
+    __syncthreads();
+    if (off <= 1e-32 * dia || off == 0.0) break;
+    for (int r = 0; r < m - 1; ++r) {
+      for (int k = t; k < half; k += nt) {
+        int p, q;
+        if (k == 0) {
+          p = r;
+          q = m - 1;
+        } else {
+          p = (r + k) % (m - 1);
+          q = (r - k + (m - 1)) % (m - 1);
+        }
+        if (p > q) {
+          int x = p;
+          p = q;
+          q = x;
+        }
+        const double apq = A[(int64_t)p * m + q];
+        double c = 1.0, s = 0.0;
+        if (fabs(apq) > 1e-300) {
+          const double tau = (A[(int64_t)q * m + q] - A[(int64_t)p * m + p]) / (2.0 * apq);
+          const double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + tt * tt);
+          s = tt * c;
+        }
+        cs[k] = c;
+        sn[k] = s;
+        pp[k] = p;
+        qq[k] = q;
+      }
+      __syncthreads();
+      // rows p, q
+      for (int64_t e = t; e < (int64_t)half * m; e += nt) {
+        const int k = (int)(e / m), j = (int)(e % m);
+        const double c = cs[k], s = sn[k];
+        if (s == 0.0) continue;
+        const int p = pp[k], q = qq[k];
+        const double ap = A[(int64_t)p * m + j], aq = A[(int64_t)q * m + j];
+        A[(int64_t)p * m + j] = c * ap - s * aq;
+        A[(int64_t)q * m + j] = s * ap + c * aq;
+      }
+      __syncthreads();
+      // columns p, q and eigenvectors
+      for (int64_t e = t; e < (int64_t)half * m; e += nt) {
+        const int k = (int)(e / m), j = (int)(e % m);
+        const double c = cs[k], s = sn[k];
+        if (s == 0.0) continue;
+        const int p = pp[k], q = qq[k];
+        const double ap = A[(int64_t)j * m + p], aq = A[(int64_t)j * m + q];
+        A[(int64_t)j * m + p] = c * ap - s * aq;
+        A[(int64_t)j * m + q] = s * ap + c * aq;
+        const double zp = Z[(int64_t)j * m + p], zq = Z[(int64_t)j * m + q];
+        Z[(int64_t)j * m + p] = c * zp - s * zq;
+        Z[(int64_t)j * m + q] = s * zp + c * zq;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+TruncResult truncate_psi(Ctx& ctx, const HpsiPlan& plan, const double* psi, int D, bool left_to_right,
+                         DevBuf& work, hipStream_t s) {
+  Block* Lb = get_block(ctx, true, plan.site);
+  Block* Rb = get_block(ctx, false, plan.site + 2);
+  BSD_CHECK(Lb && Rb, 2, "environment blocks missing");
+  const SiteSet C = make_siteset(plan.site, 2);
+  const PsiLayout& lay = plan.lay;
+  // middle sectors and their row (s1, l) / column (s2, r) index spaces
+  struct Sec {
+    Q qm;
+    std::vector<std::pair<int, int>> rows, cols;   // (s, basis idx)
+    std::vector<int> roff, coff;
+    int nr = 0, nc = 0, m = 0;
+    int64_t goff = 0;
+  };
+  std::map<Q, int> sidx;
+  std::vector<Sec> secs;
+  for (const auto& b : lay.blocks) {
+    const int s1 = b.c / 4;
+    Q qm = Lb->basis.q[b.l] + kSiteQ[s1];
+    if (sidx.find(qm) == sidx.end()) {
+      sidx[qm] = (int)secs.size();
+      Sec x;
+      x.qm = qm;
+      secs.push_back(x);
+    }
+  }
+  for (auto& x : secs) {
+    for (int s1 = 0; s1 < 4; ++s1) {
+      int l = Lb->basis.find(x.qm - kSiteQ[s1]);
+      if (l >= 0) {
+        x.rows.push_back({s1, l});
+        x.roff.push_back(x.nr);
+        x.nr += Lb->basis.dim[l];
+      }
+    }
+    for (int s2 = 0; s2 < 4; ++s2) {
+      // right block label counts electrons to the right: target - (q_m + q_s2)
+      int r = Rb->basis.find(ctx.target - (x.qm + kSiteQ[s2]));
+      if (r >= 0) {
+        x.cols.push_back({s2, r});
+        x.coff.push_back(x.nc);
+        x.nc += Rb->basis.dim[r];
+      }
+    }
+    const int n = left_to_right ? x.nr : x.nc;
+    x.m = n + (n & 1);
+    BSD_CHECK(x.m <= 1024, 3, "middle sector larger than 1024 states");
+  }
+  int64_t gtot = 0;
+  for (auto& x : secs) {
+    x.goff = gtot;
+    gtot += (int64_t)x.m * x.m;
+  }
+  work.reserve((size_t)std::max<int64_t>(1, 2 * gtot + 2 * (int64_t)secs.size()) * sizeof(double));
+  double* G = static_cast<double*>(work.p);
+  double* V = G + gtot;
+  zero_fill(G, gtot, s);
+  // Gram matrices by the grouped GEMM (psi blocks: rows d_l, cols d_r)
+  std::vector<GemmProblem> probs;
+  for (auto& x : secs) {
+    const auto& outer = left_to_right ? x.rows : x.cols;
+    const auto& offs = left_to_right ? x.roff : x.coff;
+    for (size_t a = 0; a < outer.size(); ++a)
+      for (size_t b = 0; b < outer.size(); ++b) {
+        GemmProblem gp;
+        const int da = left_to_right ? Lb->basis.dim[outer[a].second] : Rb->basis.dim[outer[a].second];
+        const int db = left_to_right ? Lb->basis.dim[outer[b].second] : Rb->basis.dim[outer[b].second];
+        gp.C = tag_ptr(0, (uint64_t)(G + x.goff + (int64_t)offs[a] * x.m + offs[b]));
+        gp.ldc = x.m;
+        gp.M = da;
+        gp.N = db;
+        gp.beta = 0.0;
+        const auto& inner = left_to_right ? x.cols : x.rows;
+        for (const auto& in : inner) {
+          int la, lb, ra, rb, ca, cb;
+          if (left_to_right) {
+            la = outer[a].second, lb = outer[b].second;
+            ca = outer[a].first * 4 + in.first;
+            cb = outer[b].first * 4 + in.first;
+            ra = rb = in.second;
+          } else {
+            la = lb = in.second;
+            ca = in.first * 4 + outer[a].first;
+            cb = in.first * 4 + outer[b].first;
+            ra = outer[a].second, rb = outer[b].second;
+          }
+          auto ia = lay.index.find({la, ca, ra});
+          auto ib = lay.index.find({lb, cb, rb});
+          if (ia == lay.index.end() || ib == lay.index.end()) continue;
+          const PsiBlk& A = lay.blocks[ia->second];
+          const PsiBlk& B = lay.blocks[ib->second];
+          GSeg sg;
+          sg.alpha = 1.0;
+          sg.A = tag_ptr(1, (uint64_t)(A.off * sizeof(double)));
+          sg.B = tag_ptr(1, (uint64_t)(B.off * sizeof(double)));
+          sg.lda = A.cols;
+          sg.ldb = B.cols;
+          if (left_to_right) {
+            sg.K = A.cols;           // sum over the right index
+            sg.flags = kTransB;      // A (d_la x d_r) * B^T (d_r x d_lb)
+          } else {
+            sg.K = A.rows;           // sum over the left index
+            sg.flags = kTransA;      // A^T (d_ra x d_l) * B (d_l x d_rb)
+          }
+          gp.segs.push_back(sg);
+        }
+        if (!gp.segs.empty()) probs.push_back(std::move(gp));
+      }
+  }
+  {
+    GemmPlan gplan;
+    gplan.build(probs);
+    GBases b{{0, (uint64_t)psi, 0, 0}};
+    gplan.launch(b, s);
+    BSD_HIP(hipStreamSynchronize(s));
+  }
+  // Jacobi per sector
+  std::vector<int64_t> goffs;
+  std::vector<int> dims;
+  for (auto& x : secs) {
+    goffs.push_back(x.goff);
+    dims.push_back(x.m);
+  }
+  {
+    DevBuf dg, dd;
+    dg.reserve(std::max<size_t>(1, goffs.size()) * sizeof(int64_t));
+    dd.reserve(std::max<size_t>(1, dims.size()) * sizeof(int));
+    BSD_HIP(hipMemcpy(dg.p, goffs.data(), goffs.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    BSD_HIP(hipMemcpy(dd.p, dims.data(), dims.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!secs.empty())
+      hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)secs.size()), dim3(1024), 0, s, (const int64_t*)dg.p,
+                         (const int*)dd.p, G, V, 40);
+    BSD_HIP(hipGetLastError());
+    BSD_HIP(hipStreamSynchronize(s));
+  }
+  // eigenvalues and vectors to the host (small: at most (4D)^2 per sector)
+  std::vector<double> Gh(gtot), Vh(gtot);
+  BSD_HIP(hipMemcpy(Gh.data(), G, gtot * sizeof(double), hipMemcpyDeviceToHost));
+  BSD_HIP(hipMemcpy(Vh.data(), V, gtot * sizeof(double), hipMemcpyDeviceToHost));
+  struct SV {
+    double lam;
+    int sec, col;
+  };
+  std::vector<SV> all;
+  for (int k = 0; k < (int)secs.size(); ++k) {
+    const auto& x = secs[k];
+    const int n = left_to_right ? x.nr : x.nc;
+    for (int j = 0; j < n; ++j) all.push_back({std::max(0.0, Gh[x.goff + (int64_t)j * x.m + j]), k, j});
+  }
+  std::sort(all.begin(), all.end(), [](const SV& a, const SV& b) { return a.lam > b.lam; });
+  TruncResult res;
+  double total = 0.0;
+  for (auto& a : all) total += a.lam;
+  const double smax = all.empty() ? 0.0 : std::sqrt(all[0].lam);
+  double cut = -1.0;
+  if ((int)all.size() > D && D > 0) cut = std::sqrt(all[D - 1].lam) * (1.0 - 1e-10);
+  std::vector<std::vector<int>> kept(secs.size());
+  double disc = 0.0;
+  for (auto& a : all) {
+    const double sg = std::sqrt(a.lam);
+    if (sg >= cut && sg > 1e-14 * smax) {
+      kept[a.sec].push_back(a.col);
+      res.sv.push_back(sg);
+    } else {
+      disc += a.lam;
+    }
+  }
+  res.trunc_err = disc;
+  res.norm2 = total;
+  // new site tensor: for left_to_right the blocks (q_l, s1) -> q_m are rows of
+  // the kept eigenvectors; for right_to_left the blocks (q_m, s2) are the kept
+  // eigenvectors transposed
+  for (int k = 0; k < (int)secs.size(); ++k) {
+    const auto& x = secs[k];
+    const auto& kc = kept[k];
+    if (kc.empty()) continue;
+    res.D_kept += (int)kc.size();
+    const auto& outer = left_to_right ? x.rows : x.cols;
+    const auto& offs = left_to_right ? x.roff : x.coff;
+    for (size_t a = 0; a < outer.size(); ++a) {
+      const int d = left_to_right ? Lb->basis.dim[outer[a].second] : Rb->basis.dim[outer[a].second];
+      TruncBlock tb;
+      tb.s = outer[a].first;
+      if (left_to_right) {
+        tb.ql = Lb->basis.q[outer[a].second];
+        tb.rows = d;
+        tb.cols = (int)kc.size();
+        tb.data.resize((size_t)d * kc.size());
+        for (int i = 0; i < d; ++i)
+          for (size_t j = 0; j < kc.size(); ++j)
+            tb.data[i * kc.size() + j] = Vh[x.goff + (int64_t)(offs[a] + i) * x.m + kc[j]];
+      } else {
+        tb.ql = x.qm;   // left bond label of site+1 is the middle sector
+        tb.rows = (int)kc.size();
+        tb.cols = d;
+        tb.data.resize((size_t)d * kc.size());
+        for (size_t j = 0; j < kc.size(); ++j)
+          for (int i = 0; i < d; ++i) tb.data[j * d + i] = Vh[x.goff + (int64_t)(offs[a] + i) * x.m + kc[j]];
+      }
+      res.blocks.push_back(std::move(tb));
+    }
+  }
+  return res;
+}
+
+}  // namespace bsd
