@@ -119,10 +119,14 @@ int bsdmrg_hpsi(bsdmrg_ctx* ctx, int site, const double* psi_dev, double* out_de
 
 /* Davidson options (Sec. II.B step 2; the paper names the method but fixes
  * no parameters).  Defaults: max_iter 50, max_subspace 24, restart 4,
- * tol 1e-8 on the residual 2-norm, preconditioner floor 1e-4. */
+ * float64 products, diagonal preconditioner, tol 1e-8 on the residual 2-norm,
+ * preconditioner floor 1e-4.  precond 0: t = (diag H_eff - theta)^-1 r;
+ * precond 1: t = r (no preconditioner; converges faster when the block bases
+ * are far from converged, e.g. random isometries). */
 typedef struct {
   int32_t max_iter, max_subspace, restart, precision;  /* precision of the H.psi products */
   double tol, precond_floor;
+  int32_t precond, pad;
 } bsdmrg_dav_opts;
 
 /* Lowest eigenpair of H_eff at `site` by Davidson in float64 on the device:

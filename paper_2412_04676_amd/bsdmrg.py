@@ -206,13 +206,14 @@ def bsdmrg_hpsi_profile(ctx, site, psi_dev, out_dev, precision=FP64, stream=None
 
 class DavOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("max_subspace", ctypes.c_int32), ("restart", ctypes.c_int32),
-                ("precision", ctypes.c_int32), ("tol", ctypes.c_double), ("precond_floor", ctypes.c_double)]
+                ("precision", ctypes.c_int32), ("tol", ctypes.c_double), ("precond_floor", ctypes.c_double),
+                ("precond", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 def bsdmrg_davidson(ctx, site, psi_dev, max_iter=50, max_subspace=24, restart=4, tol=1e-8,
-                    precond_floor=1e-4, precision=FP64, stream=None):
+                    precond_floor=1e-4, precision=FP64, precond=0, stream=None):
     """Returns (energy, iterations, residual norm, list of Ritz values); psi_dev is overwritten."""
-    o = DavOpts(max_iter, max_subspace, restart, precision, tol, precond_floor)
+    o = DavOpts(max_iter, max_subspace, restart, precision, tol, precond_floor, precond, 0)
     e = ctypes.c_double()
     it = c_int()
     r = ctypes.c_double()

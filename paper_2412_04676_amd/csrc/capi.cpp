@@ -389,9 +389,11 @@ int bsdmrg_davidson(bsdmrg_ctx* ctx, int site, double* psi, const bsdmrg_dav_opt
     if (opts) {
       BSD_CHECK(opts->max_iter > 0 && opts->max_subspace >= 4 && opts->max_subspace <= 30 && opts->restart >= 1 &&
                     opts->restart < opts->max_subspace - 1 && opts->tol > 0 && opts->precond_floor > 0 &&
-                    opts->precision >= BSDMRG_FP64 && opts->precision <= BSDMRG_BF16X6,
+                    opts->precision >= BSDMRG_FP64 && opts->precision <= BSDMRG_BF16X6 &&
+                    (opts->precond == 0 || opts->precond == 1),
                 BSDMRG_EINVAL, "bad Davidson options");
       o.precision = opts->precision;
+      o.precond = opts->precond;
       o.max_iter = opts->max_iter;
       o.max_sub = opts->max_subspace;
       o.restart = opts->restart;

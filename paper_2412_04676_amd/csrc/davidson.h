@@ -11,6 +11,7 @@ struct DavidsonOpts {
   double tol = 1e-8;
   double precond_floor = 1e-4;
   int precision = 0;   // precision of the H.psi products
+  int precond = 0;     // 0 diagonal, 1 none
 };
 
 struct DavidsonResult {

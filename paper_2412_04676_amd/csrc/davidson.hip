@@ -68,17 +68,21 @@ __global__ void scale_by_inv_kernel(const double* __restrict__ x, const double* 
     y[i] = x[i] * inv;
 }
 
-// r = Hx - theta x ; t = r / (diag - theta) with |denominator| >= floor
+// r = Hx - theta x ; t = r / (diag - theta) with |denominator| >= floor, or t = r
 __global__ void residual_kernel(const double* __restrict__ x, const double* __restrict__ hx,
                                 const double* __restrict__ diag, const double* __restrict__ theta, double floor_,
-                                double* __restrict__ r, double* __restrict__ t, int64_t n) {
+                                int precond, double* __restrict__ r, double* __restrict__ t, int64_t n) {
   const double th = theta[0];
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const double ri = hx[i] - th * x[i];
     r[i] = ri;
-    double d = diag[i] - th;
-    if (fabs(d) < floor_) d = d < 0 ? -floor_ : floor_;
-    t[i] = ri / d;
+    if (precond == 0) {
+      double d = diag[i] - th;
+      if (fabs(d) < floor_) d = d < 0 ? -floor_ : floor_;
+      t[i] = ri / d;
+    } else {
+      t[i] = ri;
+    }
   }
 }
 
@@ -271,7 +275,8 @@ DavidsonResult davidson(const HpsiPlan& plan, const double* diag, double* psi, c
     hipLaunchKernelGGL(column_kernel, dim3(1), dim3(32), 0, s, w.Y, k, 0, w.d);
     hipLaunchKernelGGL(combine_kernel, dim3(G), dim3(256), 0, s, w.V, n, k, w.d, 0.0, 1.0, w.x, n);
     hipLaunchKernelGGL(combine_kernel, dim3(G), dim3(256), 0, s, w.W, n, k, w.d, 0.0, 1.0, w.hx, n);
-    hipLaunchKernelGGL(residual_kernel, dim3(G), dim3(256), 0, s, w.x, w.hx, diag, w.sc, o.precond_floor, w.r, w.t, n);
+    hipLaunchKernelGGL(residual_kernel, dim3(G), dim3(256), 0, s, w.x, w.hx, diag, w.sc, o.precond_floor, o.precond,
+                       w.r, w.t, n);
     dots(w, w.r, 1, w.r, w.sc + 1, s);
     double hs[2];
     BSD_HIP(hipMemcpyAsync(hs, w.sc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));

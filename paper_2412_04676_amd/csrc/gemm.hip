@@ -93,7 +93,8 @@ grouped_gemm_kernel(const GTile* __restrict__ tiles, const GSeg* __restrict__ se
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = wr + i * 16 + 4 * (lane >> 4) + v;
+        // f64 16x16x4 output: accumulator register v of lane l holds row 4 v + l / 16
+        const int r = wr + i * 16 + 4 * v + (lane >> 4);
         const int c = wc + j * 16 + (lane & 15);
         if (r < mt && c < nt) {
           double* p = C + (int64_t)(tile.m0 + r) * tile.ldc + (tile.n0 + c);

@@ -17,14 +17,15 @@ def load_mps(ctx, tensors):
             B.bsdmrg_set_site_tensor(ctx, n, t)
 
 
-def _step(ctx, L, i, D, direction, rng_seed, precision, tol):
+def _step(ctx, L, i, D, direction, rng_seed, precision, tol, max_iter=300, precond=1):
     import torch
     B.bsdmrg_build_env(ctx, B.LEFT, i)
     B.bsdmrg_build_env(ctx, B.RIGHT, i + 2)
     meta, off, ne = B.bsdmrg_psi_layout(ctx, i)
     guess = np.random.default_rng(rng_seed).normal(size=ne)
     x = torch.from_numpy(guess).cuda()
-    e, it, r, ritz = B.bsdmrg_davidson(ctx, i, x, tol=tol, precision=precision)
+    e, it, r, ritz = B.bsdmrg_davidson(ctx, i, x, tol=tol, precision=precision, max_iter=max_iter,
+                                       precond=precond)
     err, kept, sv = B.bsdmrg_truncate(ctx, i, x, D, direction)
     return e, err, kept, it
 

@@ -24,8 +24,9 @@ def oracle_op(h, eri, T, L, na, nb, site):
     return BlockSparseHeff(lb, rb, t, g, (na, nb))
 
 
+@pytest.mark.parametrize("precond", [0, 1])
 @pytest.mark.parametrize("L,na,nb,D,site", [(8, 4, 4, 64, 3), (10, 5, 5, 100, 4), (9, 5, 4, 60, 2)])
-def test_davidson_matches_oracle_lanczos(L, na, nb, D, site):
+def test_davidson_matches_oracle_lanczos(L, na, nb, D, site, precond):
     import torch
     from paper_2412_04676_amd import bsdmrg as B
     say(f"davidson L={L} D={D} site={site}")
@@ -39,7 +40,7 @@ def test_davidson_matches_oracle_lanczos(L, na, nb, D, site):
     w, V = sla.eigsh(A, k=1, which="SA", tol=1e-13, v0=flatten(psi0, keys))
     lay = B.bsdmrg_psi_layout(ctx, site)
     x = torch.from_numpy(B.psi_to_flat(psi0, lay)).cuda()
-    e, it, r, ritz = B.bsdmrg_davidson(ctx, site, x, tol=1e-9)
+    e, it, r, ritz = B.bsdmrg_davidson(ctx, site, x, tol=1e-9, max_iter=300, precond=precond)
     say(f"  E gpu {e:.12f} oracle {w[0]:.12f} iters {it} resid {r:.2e}")
     assert abs(e - w[0]) < 1e-9
     assert r <= 1e-9
