@@ -9,6 +9,8 @@
 // 2x2 v_mfma_f64_16x16x4 accumulators.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace bsd {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
@@ -70,8 +72,10 @@ grouped_gemm_kernel(const GTile* __restrict__ tiles, const GSeg* __restrict__ se
         Bs[k][j] = v;
       }
       __syncthreads();
+      const int kend = min(KB, sg.K - k0);
 #pragma unroll
       for (int kk = 0; kk < KB; kk += 4) {
+        if (kk >= kend) break;
         double a[2], b[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) a[i] = As[wr + i * 16 + (lane & 15)][kk + (lane >> 4)];
@@ -251,24 +255,27 @@ grouped_gemm_bf16_kernel(const GTile* __restrict__ tiles, const GSeg* __restrict
       }
 }
 
-void launch_grouped_gemm(const GTile* tiles, int ntiles, int tile, const GSeg* segs,
+// tile shape classes: 0 64x64, 1 32x32, 2 32x64, 3 64x32
+template <int WM, int WN>
+static void launch_shape(const GTile* tiles, int ntiles, const GSeg* segs, const GBases& b, hipStream_t s,
+                         int precision) {
+  const dim3 grid(ntiles), block(64 * WM * WN);
+  if (precision == 0)
+    hipLaunchKernelGGL((grouped_gemm_kernel<WM, WN>), grid, block, 0, s, tiles, segs, b);
+  else if (precision == 1)
+    hipLaunchKernelGGL((grouped_gemm_bf16_kernel<WM, WN, 2>), grid, block, 0, s, tiles, segs, b);
+  else
+    hipLaunchKernelGGL((grouped_gemm_bf16_kernel<WM, WN, 3>), grid, block, 0, s, tiles, segs, b);
+}
+
+void launch_grouped_gemm(const GTile* tiles, int ntiles, int shape, const GSeg* segs,
                          const GBases& b, hipStream_t s, int precision) {
   if (ntiles <= 0) return;
-  if (precision == 0) {
-    if (tile == 64)
-      hipLaunchKernelGGL((grouped_gemm_kernel<2, 2>), dim3(ntiles), dim3(256), 0, s, tiles, segs, b);
-    else
-      hipLaunchKernelGGL((grouped_gemm_kernel<1, 1>), dim3(ntiles), dim3(64), 0, s, tiles, segs, b);
-  } else if (precision == 1) {
-    if (tile == 64)
-      hipLaunchKernelGGL((grouped_gemm_bf16_kernel<2, 2, 2>), dim3(ntiles), dim3(256), 0, s, tiles, segs, b);
-    else
-      hipLaunchKernelGGL((grouped_gemm_bf16_kernel<1, 1, 2>), dim3(ntiles), dim3(64), 0, s, tiles, segs, b);
-  } else {
-    if (tile == 64)
-      hipLaunchKernelGGL((grouped_gemm_bf16_kernel<2, 2, 3>), dim3(ntiles), dim3(256), 0, s, tiles, segs, b);
-    else
-      hipLaunchKernelGGL((grouped_gemm_bf16_kernel<1, 1, 3>), dim3(ntiles), dim3(64), 0, s, tiles, segs, b);
+  switch (shape) {
+    case 0: launch_shape<2, 2>(tiles, ntiles, segs, b, s, precision); break;
+    case 1: launch_shape<1, 1>(tiles, ntiles, segs, b, s, precision); break;
+    case 2: launch_shape<1, 2>(tiles, ntiles, segs, b, s, precision); break;
+    default: launch_shape<2, 1>(tiles, ntiles, segs, b, s, precision); break;
   }
   BSD_HIP(hipGetLastError());
 }
@@ -301,61 +308,78 @@ void launch_aggregate(const AggTask* tasks, const AggTerm* terms, int ntasks, hi
 
 // ---------------------------------------------------------------- plan building (host)
 void GemmPlan::build(const std::vector<GemmProblem>& probs) {
-  std::vector<GTile> t64, t32;
+  std::vector<GTile> t[kShapes];
+  std::vector<double> work[kShapes];
   std::vector<GSeg> sg;
   flops = 0.0;
-  flops64 = flops32 = 0.0;
+  for (int c = 0; c < kShapes; ++c) shape_flops[c] = 0.0;
   for (const auto& p : probs) {
     if (p.M <= 0 || p.N <= 0) continue;
     int seg0 = (int)sg.size();
-    const bool small = p.M <= 32 && p.N <= 32;
+    // smallest padded area, then fewer tiles
+    const int TMs[kShapes] = {64, 32, 32, 64}, TNs[kShapes] = {64, 32, 64, 32};
+    int cls = 0;
+    int64_t best = -1;
+    for (int c = 0; c < kShapes; ++c) {
+      const int64_t tm = (p.M + TMs[c] - 1) / TMs[c], tn = (p.N + TNs[c] - 1) / TNs[c];
+      const int64_t area = tm * tn * TMs[c] * TNs[c];
+      const int64_t score = area * 4 + tm * tn;  // area first, tile count as tie-break
+      if (best < 0 || score < best) {
+        best = score;
+        cls = c;
+      }
+    }
+    int64_t ktot = 0;
     for (const auto& s : p.segs) {
       if (s.K <= 0) continue;
       sg.push_back(s);
+      ktot += s.K;
       if (!(s.flags & kIdentA)) {
         double f = 2.0 * p.M * (double)p.N * s.K;
         flops += f;
-        (small ? flops32 : flops64) += f;
+        shape_flops[cls] += f;
       }
     }
     int nseg = (int)sg.size() - seg0;
-    const int T = small ? 32 : 64;
-    for (int m0 = 0; m0 < p.M; m0 += T)
-      for (int n0 = 0; n0 < p.N; n0 += T) {
-        GTile t;
-        t.C = p.C;
-        t.ldc = p.ldc;
-        t.M = p.M;
-        t.N = p.N;
-        t.m0 = m0;
-        t.n0 = n0;
-        t.seg0 = seg0;
-        t.nseg = nseg;
-        t.beta = p.beta;
-        (small ? t32 : t64).push_back(t);
+    for (int m0 = 0; m0 < p.M; m0 += TMs[cls])
+      for (int n0 = 0; n0 < p.N; n0 += TNs[cls]) {
+        GTile x;
+        x.C = p.C;
+        x.ldc = p.ldc;
+        x.M = p.M;
+        x.N = p.N;
+        x.m0 = m0;
+        x.n0 = n0;
+        x.seg0 = seg0;
+        x.nseg = nseg;
+        x.beta = p.beta;
+        t[cls].push_back(x);
+        work[cls].push_back((double)ktot + 16.0 * nseg);
       }
   }
-  ntiles64 = (int)t64.size();
-  ntiles32 = (int)t32.size();
-  std::vector<GTile> all = t64;
-  all.insert(all.end(), t32.begin(), t32.end());
+  // longest tiles first inside every launch (LPT order)
+  std::vector<GTile> all;
+  for (int c = 0; c < kShapes; ++c) {
+    std::vector<int> idx(t[c].size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return work[c][a] > work[c][b]; });
+    first[c] = (int)all.size();
+    count[c] = (int)idx.size();
+    for (int i : idx) all.push_back(t[c][i]);
+  }
   tiles.reserve(std::max<size_t>(1, all.size()) * sizeof(GTile));
   segs.reserve(std::max<size_t>(1, sg.size()) * sizeof(GSeg));
   if (!all.empty()) BSD_HIP(hipMemcpy(tiles.p, all.data(), all.size() * sizeof(GTile), hipMemcpyHostToDevice));
   if (!sg.empty()) BSD_HIP(hipMemcpy(segs.p, sg.data(), sg.size() * sizeof(GSeg), hipMemcpyHostToDevice));
 }
 
-void GemmPlan::launch64(const GBases& bases, hipStream_t s, int precision) const {
-  launch_grouped_gemm(static_cast<const GTile*>(tiles.p), ntiles64, 64, static_cast<const GSeg*>(segs.p), bases, s,
-                      precision);
-}
-void GemmPlan::launch32(const GBases& bases, hipStream_t s, int precision) const {
-  launch_grouped_gemm(static_cast<const GTile*>(tiles.p) + ntiles64, ntiles32, 32,
+void GemmPlan::launch_shape_class(int c, const GBases& bases, hipStream_t s, int precision) const {
+  launch_grouped_gemm(static_cast<const GTile*>(tiles.p) + first[c], count[c], c,
                       static_cast<const GSeg*>(segs.p), bases, s, precision);
 }
+
 void GemmPlan::launch(const GBases& bases, hipStream_t s, int precision) const {
-  launch64(bases, s, precision);
-  launch32(bases, s, precision);
+  for (int c = 0; c < kShapes; ++c) launch_shape_class(c, bases, s, precision);
 }
 
 }  // namespace bsd

@@ -526,7 +526,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
 
 int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision, int cap,
                  double* ms, double* flops, int* kind) {
-  // kind: 0 zero-fill, 1 phase-1 64x64 tiles, 2 phase-1 32x32, 3 phase-2 64x64, 4 phase-2 32x32
+  // kind: 0 zero-fill, 10 + c phase-1 grouped GEMM with tile shape class c, 20 + c phase 2
   std::vector<hipEvent_t> ev;
   std::vector<int> kinds;
   std::vector<double> fl;
@@ -543,22 +543,16 @@ int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream
   fl.push_back(0.0);
   mark();
   for (size_t k = 0; k < plan.phase1.size(); ++k) {
-    plan.phase1[k]->launch64(b, s, precision);
-    kinds.push_back(1);
-    fl.push_back(plan.phase1[k]->flops64);
-    mark();
-    plan.phase1[k]->launch32(b, s, precision);
-    kinds.push_back(2);
-    fl.push_back(plan.phase1[k]->flops32);
-    mark();
-    plan.phase2[k]->launch64(b, s, precision);
-    kinds.push_back(3);
-    fl.push_back(plan.phase2[k]->flops64);
-    mark();
-    plan.phase2[k]->launch32(b, s, precision);
-    kinds.push_back(4);
-    fl.push_back(plan.phase2[k]->flops32);
-    mark();
+    for (int ph = 1; ph <= 2; ++ph) {
+      const GemmPlan& gp = ph == 1 ? *plan.phase1[k] : *plan.phase2[k];
+      for (int c = 0; c < kShapes; ++c) {
+        if (gp.count[c] == 0) continue;
+        gp.launch_shape_class(c, b, s, precision);
+        kinds.push_back(10 * ph + c);
+        fl.push_back(gp.shape_flops[c]);
+        mark();
+      }
+    }
   }
   BSD_HIP(hipStreamSynchronize(s));
   int n = (int)kinds.size();

@@ -266,16 +266,17 @@ struct GemmProblem {
 };
 
 // Device-resident tile/segment lists for one launch group (64x64 and 32x32 tiles).
+// Tile shape classes of the grouped GEMM: 0 64x64, 1 32x32, 2 32x64, 3 64x32.
+constexpr int kShapes = 4;
 struct GemmPlan {
-  int ntiles64 = 0, ntiles32 = 0;
+  int first[kShapes] = {0, 0, 0, 0}, count[kShapes] = {0, 0, 0, 0};
   DevBuf tiles, segs;
-  double flops = 0.0;               // useful flops (2 M N K over non-identity segments)
-  double flops64 = 0.0, flops32 = 0.0;  // per launch group
+  double flops = 0.0;                       // useful flops (2 M N K over non-identity segments)
+  double shape_flops[kShapes] = {0, 0, 0, 0};
   void build(const std::vector<GemmProblem>& probs);
   // precision: 0 float64 MFMA, 1 split-bf16 (3 products), 2 split-bf16 (6 products)
   void launch(const GBases& bases, hipStream_t s, int precision = 0) const;
-  void launch64(const GBases& bases, hipStream_t s, int precision = 0) const;
-  void launch32(const GBases& bases, hipStream_t s, int precision = 0) const;
+  void launch_shape_class(int c, const GBases& bases, hipStream_t s, int precision = 0) const;
 };
 
 struct AggTerm {
@@ -293,7 +294,7 @@ struct AggTask {
 };
 void launch_aggregate(const AggTask* tasks_dev, const AggTerm* terms_dev, int ntasks,
                       hipStream_t s);
-void launch_grouped_gemm(const GTile* tiles, int ntiles, int tile, const GSeg* segs,
+void launch_grouped_gemm(const GTile* tiles, int ntiles, int shape, const GSeg* segs,
                          const GBases& b, hipStream_t s, int precision = 0);
 
 // ---------------------------------------------------------------- serializer
