@@ -113,6 +113,8 @@ int bsdmrg_hpsi_prepare(bsdmrg_ctx* ctx, int site, int precision, size_t ws_byte
 
 /* out = H_eff psi (Sec. II.B step 2) at two-site position `site`; psi and out
  * are device buffers in the layout of bsdmrg_psi_layout and must not overlap.
+ * The product (output zero-fill and every grouped launch) is captured once
+ * per (psi, out, precision) into a hipGraph and replayed by later calls.
  * Stream-ordered; psi and out must stay valid until the stream reaches it. */
 int bsdmrg_hpsi(bsdmrg_ctx* ctx, int site, const double* psi_dev, double* out_dev, int precision,
                 bsdmrg_stream_t stream);

@@ -360,7 +360,7 @@ int bsdmrg_hpsi(bsdmrg_ctx* ctx, int site, const double* psi, double* out, int p
     BSD_CHECK(Lb && Rb && Lb->resident && Rb->resident, BSDMRG_EBUSY, "environment blocks not resident");
     const double* pe = psi + p->lay.n_elems;
     BSD_CHECK(!(out < pe && psi < out + p->lay.n_elems), BSDMRG_EINVAL, "psi and out overlap");
-    run_hpsi(*p, psi, out, S(stream), precision);
+    run_hpsi_graph(*p, psi, out, S(stream), precision);
     ctx->c.last_hpsi_flops = p->useful_flops;
   });
 }

@@ -22,7 +22,7 @@ struct DavidsonResult {
 
 // psi: in guess, out normalized eigenvector (psi layout of the plan);
 // diag: diagonal of H_eff in the same layout.
-DavidsonResult davidson(const HpsiPlan& plan, const double* diag, double* psi, const DavidsonOpts& o,
+DavidsonResult davidson(HpsiPlan& plan, const double* diag, double* psi, const DavidsonOpts& o,
                         DevBuf& work, hipStream_t s);
 
 }  // namespace bsd

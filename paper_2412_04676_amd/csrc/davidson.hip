@@ -231,7 +231,7 @@ void dots(const Work& w, const double* Vb, int k, const double* v, double* out, 
 
 }  // namespace
 
-DavidsonResult davidson(const HpsiPlan& plan, const double* diag, double* psi, const DavidsonOpts& o,
+DavidsonResult davidson(HpsiPlan& plan, const double* diag, double* psi, const DavidsonOpts& o,
                         DevBuf& work, hipStream_t s) {
   DavidsonResult res;
   const int64_t n = plan.lay.n_elems;
@@ -257,7 +257,16 @@ DavidsonResult davidson(const HpsiPlan& plan, const double* diag, double* psi, c
   w.ev = w.Y + 32 * 32;
   w.sc = w.ev + 32;
   const int G = grid_for(n);
-  auto H = [&](const double* in, double* out) { run_hpsi(plan, in, out, s, o.precision); };
+  // every product replays one captured graph on fixed staging buffers
+  plan.stage_in.reserve(std::max<int64_t>(1, n) * sizeof(double));
+  plan.stage_out.reserve(std::max<int64_t>(1, n) * sizeof(double));
+  double* sin = static_cast<double*>(plan.stage_in.p);
+  double* sout = static_cast<double*>(plan.stage_out.p);
+  auto H = [&](const double* in, double* out) {
+    BSD_HIP(hipMemcpyAsync(sin, in, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    run_hpsi_graph(plan, sin, sout, s, o.precision);
+    BSD_HIP(hipMemcpyAsync(out, sout, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  };
   auto normalize_into = [&](const double* in, double* out) {
     dots(w, in, 1, in, w.sc + 2, s);
     hipLaunchKernelGGL(scale_by_inv_kernel, dim3(G), dim3(256), 0, s, in, w.sc + 2, out, n);

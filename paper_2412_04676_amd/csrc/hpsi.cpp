@@ -567,6 +567,35 @@ int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream
   return n;
 }
 
+HpsiPlan::~HpsiPlan() {
+  for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+}
+
+void run_hpsi_graph(HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision) {
+  for (auto& g : plan.graphs)
+    if (g.psi == psi && g.out == out && g.precision == precision) {
+      BSD_HIP(hipGraphLaunch(g.exec, s));
+      return;
+    }
+  if (plan.graphs.size() >= 16) {
+    BSD_HIP(hipStreamSynchronize(s));
+    (void)hipGraphExecDestroy(plan.graphs.front().exec);
+    plan.graphs.erase(plan.graphs.begin());
+  }
+  hipStream_t cs;
+  BSD_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipGraph_t graph;
+  BSD_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  run_hpsi(plan, psi, out, cs, precision);
+  BSD_HIP(hipStreamEndCapture(cs, &graph));
+  hipGraphExec_t exec;
+  BSD_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  BSD_HIP(hipGraphDestroy(graph));
+  BSD_HIP(hipStreamDestroy(cs));
+  plan.graphs.push_back({psi, out, precision, exec});
+  BSD_HIP(hipGraphLaunch(exec, s));
+}
+
 const double* hpsi_diagonal(HpsiPlan& plan, hipStream_t s) {
   if (!plan.diag_ready) {
     plan.diag.reserve(std::max<int64_t>(1, plan.lay.n_elems) * sizeof(double));

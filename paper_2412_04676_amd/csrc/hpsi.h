@@ -29,8 +29,18 @@ struct Operand2 {
   int out = -1;
 };
 
+struct GraphEntry {
+  const double* psi;
+  double* out;
+  int precision;
+  hipGraphExec_t exec;
+};
+
 struct HpsiPlan {
   int site = 0, precision = 0;
+  std::vector<GraphEntry> graphs;   // captured products, replayed per call
+  DevBuf stage_in, stage_out;       // fixed operands of the graph used by Davidson
+  ~HpsiPlan();
   PsiLayout lay;
   DevBuf agg, V;
   size_t agg_bytes = 0, v_bytes = 0;
@@ -47,6 +57,9 @@ void build_psi_layout(const Block& Lb, const Block& Rb, const SiteSet& C, const 
 std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, size_t ws_budget, hipStream_t s);
 // precision: 0 float64, 1 split-bf16 x3, 2 split-bf16 x6 (the plan is shared)
 void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision = 0);
+// the same product replayed from a captured hipGraph (captured on first use for
+// this (psi, out, precision); kernels only, no memset nodes)
+void run_hpsi_graph(HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision = 0);
 int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision, int cap,
                  double* ms, double* flops, int* kind);
 void zero_fill(double* p, int64_t n, hipStream_t s);

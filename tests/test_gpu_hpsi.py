@@ -157,3 +157,26 @@ def test_hpsi_split_bf16_against_oracle(precision, bar):
     say(f"  rel err {e:.3e}")
     assert e < bar
     B.bsdmrg_destroy(ctx)
+
+
+def test_graph_replays_equal_eager_product():
+    """Replays of the captured product, with other GPU work and host
+    synchronizations in between, all equal the eager profiled product."""
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    L, na, nb, D, site = 10, 5, 5, 100, 4
+    say("graph replay")
+    ctx, h, eri, dims, T = build_system(L, na, nb, D, site)
+    lay = B.bsdmrg_psi_layout(ctx, site)
+    x = torch.from_numpy(B.psi_to_flat(psi_for(dims, site, 4), lay)).cuda()
+    ref = torch.empty_like(x)
+    B.bsdmrg_hpsi_profile(ctx, site, x, ref)   # eager launches
+    torch.cuda.synchronize()
+    for k in range(5):
+        y = torch.full_like(x, float(k))
+        B.bsdmrg_hpsi(ctx, site, x, y)
+        junk = torch.randn(1000, 1000, device="cuda", dtype=torch.float64)
+        (junk @ junk).sum().item()
+        torch.cuda.synchronize()
+        assert torch.equal(y, ref), k
+    B.bsdmrg_destroy(ctx)
