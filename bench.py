@@ -24,6 +24,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
+BF16_MFMA_PEAK_TFLOPS = 2516.6
 
 
 def log(msg):
@@ -101,6 +102,8 @@ def main():
     ap.add_argument("--D", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--ws-mb", type=int, default=0, help="H.psi workspace budget in MiB (0: library default)")
+    ap.add_argument("--precision", type=int, default=0, help="0 fp64, 1 split-bf16 x3, 2 split-bf16 x6")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
@@ -118,7 +121,7 @@ def main():
     ctx, psi, dims, T, h, eri, t_env = build_workload(L, na, nb, D, site)
     log(f"bench: environments built in {t_env:.1f} s")
     stream = torch.cuda.current_stream()
-    B.bsdmrg_hpsi_prepare(ctx, site, B.FP64, 0, stream)
+    B.bsdmrg_hpsi_prepare(ctx, site, B.FP64, args.ws_mb << 20, stream)
     info = B.bsdmrg_hpsi_info(ctx, site)
     lay = B.bsdmrg_psi_layout(ctx, site)
     x = torch.from_numpy(B.psi_to_flat(psi, lay)).cuda()
@@ -126,39 +129,51 @@ def main():
     log(f"bench: psi {lay[2]} elements, {info['channels']} channels, {info['segments']} K-segments, "
         f"{info['flops']:.3e} flop per product")
 
-    for _ in range(args.warmup):
-        B.bsdmrg_hpsi(ctx, site, x, y, B.FP64, stream)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        B.bsdmrg_hpsi(ctx, site, x, y, B.FP64, stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    tflops = info["flops"] / (ms * 1e-3) / 1e12
-    log(f"bench: H.psi {ms:.3f} ms, {tflops:.2f} TFLOP/s (float64)")
-
-    # dominant kernel: per-launch HIP events on the library's stream
-    prof = [B.bsdmrg_hpsi_profile(ctx, site, x, y, B.FP64, stream) for _ in range(5)]
-    kinds = {}
-    for run in prof:
-        for k, t, f in run:
-            a = kinds.setdefault(k, [0.0, 0.0, 0])
-            a[0] += t
-            a[1] += f
-            a[2] += 1
     shapes = {0: "<2, 2>", 1: "<1, 1>", 2: "<1, 2>", 3: "<2, 1>"}
-    names = {0: "zero_fill_kernel"}
-    for ph in (1, 2):
-        for c, sh in shapes.items():
-            names[10 * ph + c] = f"grouped_gemm_kernel{sh} phase {ph}"
-    dom = max(kinds, key=lambda k: kinds[k][0])
-    t_dom = kinds[dom][0] / kinds[dom][2]
-    f_dom = kinds[dom][1] / kinds[dom][2]
-    ach = f_dom / (t_dom * 1e-3) / 1e12
-    log("bench: per-launch " + ", ".join(f"{names[k]}: {v[0] / v[2]:.3f} ms" for k, v in sorted(kinds.items())))
+
+    def time_precision(prec):
+        for _ in range(args.warmup):
+            B.bsdmrg_hpsi(ctx, site, x, y, prec, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            B.bsdmrg_hpsi(ctx, site, x, y, prec, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_ = e0.elapsed_time(e1) / args.steps
+        out_ = y.clone()
+        # dominant kernel: per-launch HIP events on the library's stream
+        kinds = {}
+        for _ in range(5):
+            for k, t, f in B.bsdmrg_hpsi_profile(ctx, site, x, y, prec, stream):
+                a = kinds.setdefault(k, [0.0, 0.0, 0])
+                a[0] += t
+                a[1] += f
+                a[2] += 1
+        kname = "grouped_gemm_bf16_kernel" if prec else "grouped_gemm_kernel"
+        names = {0: "zero_fill_kernel"}
+        for ph in (1, 2):
+            for c, sh in shapes.items():
+                names[10 * ph + c] = f"{kname}{sh[:-1]}{', ' + str(prec + 1) if prec else ''}> phase {ph}"
+        dom = max(kinds, key=lambda k: kinds[k][0])
+        per = {names[k]: v[0] / v[2] for k, v in sorted(kinds.items())}
+        log(f"bench: precision {prec}: H.psi {ms_:.3f} ms, {info['flops'] / (ms_ * 1e-3) / 1e12:.2f} TFLOP/s; "
+            + ", ".join(f"{n}: {t:.3f} ms" for n, t in per.items()))
+        return ms_, out_, names[dom], kinds[dom][0] / kinds[dom][2], kinds[dom][1] / kinds[dom][2], per
+
+    res = {p: time_precision(p) for p in (B.FP64, B.BF16X3, B.BF16X6)}
+    ref = res[B.FP64][1]
+    errs = {p: float(torch.linalg.norm(res[p][1] - ref) / torch.linalg.norm(ref)) for p in res}
+    log(f"bench: relative error vs fp64: x3 {errs[B.BF16X3]:.2e}, x6 {errs[B.BF16X6]:.2e}")
+    chosen = B.BF16X6 if errs[B.BF16X6] <= 1e-6 else B.FP64
+    ms, _, dname, t_dom, f_dom, per_launch = res[chosen]
+    tflops = info["flops"] / (ms * 1e-3) / 1e12
+    # algorithmic flops of the dominant kernel: the split-bf16 x6 product issues 6
+    # bf16 MFMA products per float64 multiply-add
+    mult = 6.0 if chosen == B.BF16X6 else 1.0
+    peak = BF16_MFMA_PEAK_TFLOPS if chosen == B.BF16X6 else FP64_MFMA_PEAK_TFLOPS
+    ach = mult * f_dom / (t_dom * 1e-3) / 1e12
 
     # serializer and offload of the left environment block
     nbytes = B.bsdmrg_serialized_size(ctx, B.LEFT, site)
@@ -194,13 +209,13 @@ def main():
     torch.cuda.synchronize()
     t0 = time.time()
     for _ in range(nrep):
-        B.bsdmrg_hpsi(ctx, site, x, y, B.FP64, stream)
+        B.bsdmrg_hpsi(ctx, site, x, y, chosen, stream)
     torch.cuda.synchronize()
     t_comp = time.time() - t0
     t0 = time.time()
     B.bsdmrg_offload(ctx, B.LEFT, site, staging, pinned, nbytes, 0, stream, side)
     for _ in range(nrep):
-        B.bsdmrg_hpsi(ctx, site, x, y, B.FP64, stream)
+        B.bsdmrg_hpsi(ctx, site, x, y, chosen, stream)
     B.bsdmrg_offload_wait(ctx, B.LEFT, site)
     torch.cuda.synchronize()
     t_both = time.time() - t0
@@ -239,16 +254,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "bf16x6 (f32 acc, f64 in/out)" if chosen == B.BF16X6 else "f64",
         "data": "synthetic",
         "config": {"workload": f"middle-site two-site H.psi, L={L} N={N} S_z={(na - nb) / 2} D={D} "
                                "(synthetic integrals, random mixed-canonical MPS)",
                    "site": site, "psi_elements": int(lay[2]), "channels": info["channels"],
                    "k_segments": info["segments"], "flops_per_step": info["flops"],
-                   "precision_path": "fp64", "env_build_s": t_env},
-        "roofline": {"bound": "mfma", "achieved": ach, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ach / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
-                     "kernel": names[dom], "kernel_ms": t_dom, "kernel_flops": f_dom},
+                   "precision_path": {0: "fp64", 1: "bf16x3", 2: "bf16x6"}[chosen], "env_build_s": t_env},
+        "precisions": {name: {"ms": res[p][0], "tflops": info["flops"] / (res[p][0] * 1e-3) / 1e12,
+                              "rel_err_vs_fp64": errs[p], "per_launch_ms": res[p][5]}
+                       for name, p in (("fp64", B.FP64), ("bf16x3", B.BF16X3), ("bf16x6", B.BF16X6))},
+        "speedup_bf16x6_vs_fp64": res[B.FP64][0] / res[B.BF16X6][0],
+        "roofline": {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
+                     "frac": ach / peak, "traffic": None,
+                     "kernel": dname, "kernel_ms": t_dom, "kernel_useful_flops": f_dom,
+                     "algorithmic_flops_per_useful_flop": mult},
         "site_step": {"davidson_iters": it_dav, "davidson_ms": t_dav * 1e3, "energy": e_dav,
                       "residual": r_dav, "truncate_ms": t_tr * 1e3, "kept": kept, "trunc_err": err_tr,
                       "renormalize_ms": t_ren * 1e3},
