@@ -129,7 +129,7 @@ def main():
     log(f"bench: psi {lay[2]} elements, {info['channels']} channels, {info['segments']} K-segments, "
         f"{info['flops']:.3e} flop per product")
 
-    shapes = {0: "<2, 2>", 1: "<1, 1>", 2: "<1, 2>", 3: "<2, 1>"}
+    shapes = {0: "<2, 2>", 1: "<1, 1>", 2: "<1, 2>", 3: "<2, 1>", 4: "<16>", 5: "<32>"}
 
     def time_precision(prec):
         for _ in range(args.warmup):
@@ -155,7 +155,10 @@ def main():
         names = {0: "zero_fill_kernel"}
         for ph in (1, 2):
             for c, sh in shapes.items():
-                names[10 * ph + c] = f"{kname}{sh[:-1]}{', ' + str(prec + 1) if prec else ''}> phase {ph}"
+                if c >= 4:
+                    names[10 * ph + c] = f"wave_gemm_kernel{sh} phase {ph}"
+                else:
+                    names[10 * ph + c] = f"{kname}{sh[:-1]}{', ' + str(prec + 1) if prec else ''}> phase {ph}"
         dom = max(kinds, key=lambda k: kinds[k][0])
         per = {names[k]: v[0] / v[2] for k, v in sorted(kinds.items())}
         log(f"bench: precision {prec}: H.psi {ms_:.3f} ms, {info['flops'] / (ms_ * 1e-3) / 1e12:.2f} TFLOP/s; "

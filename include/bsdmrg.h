@@ -169,8 +169,9 @@ int bsdmrg_hpsi_info(bsdmrg_ctx* ctx, int site, int precision, double* flops, in
  * launches (synchronizing).  For launch i (i < cap) it returns the elapsed
  * milliseconds ms[i], the algorithmic flops flops[i] of that launch and its kind
  * kind[i] (0 output zero-fill; 10 + c phase-1 and 20 + c phase-2 grouped GEMM
- * with tile shape class c: 0 64x64, 1 32x32, 2 32x64, 3 64x32).  Launches with
- * no tiles are skipped.  *n_launches receives the number of launches. */
+ * with tile shape class c: 0 64x64, 1 32x32, 2 32x64, 3 64x32 workgroup tiles,
+ * 4 16x16 and 5 32x32 wave tiles).  Launches with no tiles are skipped.
+ * *n_launches receives the number of launches. */
 int bsdmrg_hpsi_profile(bsdmrg_ctx* ctx, int site, const double* psi_dev, double* out_dev, int precision,
                         bsdmrg_stream_t stream, int cap, double* ms, double* flops, int* kind,
                         int* n_launches);

@@ -507,7 +507,7 @@ int bsdmrg_block_gemm(int n, const bsdmrg_gemm_desc* probs, int precision, bsdmr
       v.push_back(std::move(g));
     }
     GemmPlan plan;
-    plan.build(v);
+    plan.build(v, precision == BSDMRG_FP64);
     GBases b{{0, 0, 0, 0}};
     plan.launch(b, S(stream), precision);
     BSD_HIP(hipStreamSynchronize(S(stream)));

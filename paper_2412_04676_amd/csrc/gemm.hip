@@ -255,7 +255,99 @@ grouped_gemm_bf16_kernel(const GTile* __restrict__ tiles, const GSeg* __restrict
       }
 }
 
-// tile shape classes: 0 64x64, 1 32x32, 2 32x64, 3 64x32
+// ---------------------------------------------------------------- wave tiles
+// For small sector blocks (at most 64 x 64) the K dimension arrives in many
+// short segments, so LDS staging and workgroup barriers per segment would
+// dominate.  Here every wave owns one TW x TW output tile (TW = 16 or 32),
+// loads its MFMA operands straight from global memory / L2 (lane l holds
+// A[l % 16][k + l / 16] and B[k + l / 16][l % 16]) and never synchronizes; a
+// workgroup is four independent waves.
+template <int TW>
+__global__ void __launch_bounds__(256)
+wave_gemm_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __restrict__ segs, GBases bases) {
+  constexpr int NI = TW / 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ti = blockIdx.x * 4 + wave;
+  if (ti >= ntiles) return;
+  const GTile tile = tiles[ti];
+  const int mt = min(TW, tile.M - tile.m0);
+  const int nt = min(TW, tile.N - tile.n0);
+  const int r16 = lane & 15, kq = lane >> 4;
+  double4_t acc[NI][NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+  for (int sidx = 0; sidx < tile.nseg; ++sidx) {
+    const GSeg sg = segs[tile.seg0 + sidx];
+    const double* A = resolve(sg.A, bases);
+    const double* B = resolve(sg.B, bases);
+    const bool ta = sg.flags & kTransA, tb = sg.flags & kTransB, ia = sg.flags & kIdentA;
+    const double alpha = sg.alpha;
+    bool rowok[NI], colok[NI];
+    int gi[NI], gj[NI];
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      rowok[i] = i * 16 + r16 < mt;
+      gi[i] = tile.m0 + i * 16 + r16;
+      colok[i] = i * 16 + r16 < nt;
+      gj[i] = tile.n0 + i * 16 + r16;
+    }
+    // 16 values of K per pass: every operand load of the pass is issued before its MFMAs
+    for (int k0 = 0; k0 < sg.K; k0 += 16) {
+      double a[4][NI], b[4][NI];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int k = k0 + 4 * st + kq;
+        const bool kok = k < sg.K;
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          double v = 0.0;
+          if (rowok[i] && kok) {
+            if (ia) v = (gi[i] == k) ? alpha : 0.0;
+            else v = alpha * (ta ? A[(int64_t)k * sg.lda + gi[i]] : A[(int64_t)gi[i] * sg.lda + k]);
+          }
+          a[st][i] = v;
+        }
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+          double v = 0.0;
+          if (colok[j] && kok) v = tb ? B[(int64_t)gj[j] * sg.ldb + k] : B[(int64_t)k * sg.ldb + gj[j]];
+          b[st][j] = v;
+        }
+      }
+      const int nst = min(4, (sg.K - k0 + 3) / 4);
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        if (st >= nst) break;
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+          for (int j = 0; j < NI; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][i], b[st][j], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+  double* C = const_cast<double*>(resolve(tile.C, bases));
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = i * 16 + 4 * v + kq;
+        const int c = j * 16 + r16;
+        if (r < mt && c < nt) {
+          double* p = C + (int64_t)(tile.m0 + r) * tile.ldc + (tile.n0 + c);
+          double x = acc[i][j][v];
+          if (tile.beta != 0.0) x += tile.beta * (*p);
+          *p = x;
+        }
+      }
+}
+
+// tile shape classes: 0 64x64, 1 32x32, 2 32x64, 3 64x32 (workgroup tiles),
+// 4 16x16 and 5 32x32 wave tiles (float64 only; split-bf16 uses 1 and 0)
 template <int WM, int WN>
 static void launch_shape(const GTile* tiles, int ntiles, const GSeg* segs, const GBases& b, hipStream_t s,
                          int precision) {
@@ -271,11 +363,21 @@ static void launch_shape(const GTile* tiles, int ntiles, const GSeg* segs, const
 void launch_grouped_gemm(const GTile* tiles, int ntiles, int shape, const GSeg* segs,
                          const GBases& b, hipStream_t s, int precision) {
   if (ntiles <= 0) return;
+  if (shape >= 4 && precision == 0) {
+    const dim3 grid((ntiles + 3) / 4), block(256);
+    if (shape == 4)
+      hipLaunchKernelGGL((wave_gemm_kernel<16>), grid, block, 0, s, tiles, ntiles, segs, b);
+    else
+      hipLaunchKernelGGL((wave_gemm_kernel<32>), grid, block, 0, s, tiles, ntiles, segs, b);
+    BSD_HIP(hipGetLastError());
+    return;
+  }
   switch (shape) {
     case 0: launch_shape<2, 2>(tiles, ntiles, segs, b, s, precision); break;
     case 1: launch_shape<1, 1>(tiles, ntiles, segs, b, s, precision); break;
     case 2: launch_shape<1, 2>(tiles, ntiles, segs, b, s, precision); break;
-    default: launch_shape<2, 1>(tiles, ntiles, segs, b, s, precision); break;
+    case 3: launch_shape<2, 1>(tiles, ntiles, segs, b, s, precision); break;
+    default: throw Error(1, "wave-tile lists are float64 only");
   }
   BSD_HIP(hipGetLastError());
 }
@@ -307,7 +409,7 @@ void launch_aggregate(const AggTask* tasks, const AggTerm* terms, int ntasks, hi
 }
 
 // ---------------------------------------------------------------- plan building (host)
-void GemmPlan::build(const std::vector<GemmProblem>& probs) {
+void GemmPlan::build(const std::vector<GemmProblem>& probs, bool wave_tiles) {
   std::vector<GTile> t[kShapes];
   std::vector<double> work[kShapes];
   std::vector<GSeg> sg;
@@ -316,11 +418,16 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs) {
   for (const auto& p : probs) {
     if (p.M <= 0 || p.N <= 0) continue;
     int seg0 = (int)sg.size();
-    // smallest padded area, then fewer tiles
-    const int TMs[kShapes] = {64, 32, 32, 64}, TNs[kShapes] = {64, 32, 64, 32};
+    // wave tiles for blocks up to 64 x 64 (float64 lists); otherwise the
+    // workgroup tile with the smallest padded area, then fewer tiles
+    const int TMs[kShapes] = {64, 32, 32, 64, 16, 32}, TNs[kShapes] = {64, 32, 64, 32, 16, 32};
     int cls = 0;
     int64_t best = -1;
-    for (int c = 0; c < kShapes; ++c) {
+    if (wave_tiles && p.M <= 64 && p.N <= 64) {
+      cls = (p.M <= 16 && p.N <= 16) ? 4 : 5;
+      best = 0;
+    }
+    for (int c = 0; c < 4 && best != 0; ++c) {
       const int64_t tm = (p.M + TMs[c] - 1) / TMs[c], tn = (p.N + TNs[c] - 1) / TNs[c];
       const int64_t area = tm * tn * TMs[c] * TNs[c];
       const int64_t score = area * 4 + tm * tn;  // area first, tile count as tie-break
@@ -357,6 +464,7 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs) {
         work[cls].push_back((double)ktot + 16.0 * nseg);
       }
   }
+  wave = wave_tiles;
   // longest tiles first inside every launch (LPT order)
   std::vector<GTile> all;
   for (int c = 0; c < kShapes; ++c) {
@@ -374,6 +482,7 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs) {
 }
 
 void GemmPlan::launch_shape_class(int c, const GBases& bases, hipStream_t s, int precision) const {
+  BSD_CHECK(!(wave && count[4] + count[5] > 0 && precision != 0), 1, "float64 tile list launched at split precision");
   launch_grouped_gemm(static_cast<const GTile*>(tiles.p) + first[c], count[c], c,
                       static_cast<const GSeg*>(segs.p), bases, s, precision);
 }

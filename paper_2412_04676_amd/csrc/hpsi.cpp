@@ -504,19 +504,25 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     std::vector<GemmProblem> v;
     for (auto& kv : dprob) v.push_back(std::move(kv.second));
     plan->diag_plan = std::make_unique<GemmPlan>();
-    plan->diag_plan->build(v);
+    plan->diag_plan->build(v, true);
   }
   plan->nseg = 0;
+  plan->phase1b.resize(nchunks);
+  plan->phase2b.resize(nchunks);
   for (int k = 0; k < nchunks; ++k) {
     plan->phase1[k] = std::make_unique<GemmPlan>();
-    plan->phase1[k]->build(p1[k]);
+    plan->phase1[k]->build(p1[k], true);
+    plan->phase1b[k] = std::make_unique<GemmPlan>();
+    plan->phase1b[k]->build(p1[k], false);
     std::vector<GemmProblem> v;
     for (auto& kv : p2[k]) {
       plan->nseg += kv.second.segs.size();
       v.push_back(std::move(kv.second));
     }
     plan->phase2[k] = std::make_unique<GemmPlan>();
-    plan->phase2[k]->build(v);
+    plan->phase2[k]->build(v, true);
+    plan->phase2b[k] = std::make_unique<GemmPlan>();
+    plan->phase2b[k]->build(v, false);
   }
   plan->useful_flops = useful;
   plan->nchannels = (int)chans.size();
@@ -544,7 +550,8 @@ int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream
   mark();
   for (size_t k = 0; k < plan.phase1.size(); ++k) {
     for (int ph = 1; ph <= 2; ++ph) {
-      const GemmPlan& gp = ph == 1 ? *plan.phase1[k] : *plan.phase2[k];
+      const GemmPlan& gp = precision == 0 ? (ph == 1 ? *plan.phase1[k] : *plan.phase2[k])
+                                          : (ph == 1 ? *plan.phase1b[k] : *plan.phase2b[k]);
       for (int c = 0; c < kShapes; ++c) {
         if (gp.count[c] == 0) continue;
         gp.launch_shape_class(c, b, s, precision);
@@ -612,8 +619,13 @@ void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t 
   zero_fill(out, plan.lay.n_elems, s);
   GBases b{{0, (uint64_t)psi, (uint64_t)out, 0}};
   for (size_t k = 0; k < plan.phase1.size(); ++k) {
-    plan.phase1[k]->launch(b, s, precision);
-    plan.phase2[k]->launch(b, s, precision);
+    if (precision == 0) {
+      plan.phase1[k]->launch(b, s, 0);
+      plan.phase2[k]->launch(b, s, 0);
+    } else {
+      plan.phase1b[k]->launch(b, s, precision);
+      plan.phase2b[k]->launch(b, s, precision);
+    }
   }
 }
 

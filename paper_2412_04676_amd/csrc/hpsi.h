@@ -44,7 +44,8 @@ struct HpsiPlan {
   PsiLayout lay;
   DevBuf agg, V;
   size_t agg_bytes = 0, v_bytes = 0;
-  std::vector<std::unique_ptr<GemmPlan>> phase1, phase2;
+  std::vector<std::unique_ptr<GemmPlan>> phase1, phase2;      // float64 tile lists
+  std::vector<std::unique_ptr<GemmPlan>> phase1b, phase2b;    // split-bf16 tile lists
   std::unique_ptr<GemmPlan> diag_plan;   // diagonal of H_eff (rank-1 sector products)
   DevBuf ones, diag, dav_work;
   bool diag_ready = false;

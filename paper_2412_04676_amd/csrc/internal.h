@@ -266,14 +266,18 @@ struct GemmProblem {
 };
 
 // Device-resident tile/segment lists for one launch group (64x64 and 32x32 tiles).
-// Tile shape classes of the grouped GEMM: 0 64x64, 1 32x32, 2 32x64, 3 64x32.
-constexpr int kShapes = 4;
+// Tile shape classes of the grouped GEMM: 0 64x64, 1 32x32, 2 32x64, 3 64x32
+// (workgroup tiles staged through LDS), 4 16x16 and 5 32x32 (one wave each,
+// float64 only).
+constexpr int kShapes = 6;
 struct GemmPlan {
-  int first[kShapes] = {0, 0, 0, 0}, count[kShapes] = {0, 0, 0, 0};
+  int first[kShapes] = {0, 0, 0, 0, 0, 0}, count[kShapes] = {0, 0, 0, 0, 0, 0};
+  bool wave = false;
   DevBuf tiles, segs;
   double flops = 0.0;                       // useful flops (2 M N K over non-identity segments)
-  double shape_flops[kShapes] = {0, 0, 0, 0};
-  void build(const std::vector<GemmProblem>& probs);
+  double shape_flops[kShapes] = {0, 0, 0, 0, 0, 0};
+  // wave_tiles: small problems get wave tiles (the list is then float64 only)
+  void build(const std::vector<GemmProblem>& probs, bool wave_tiles = true);
   // precision: 0 float64 MFMA, 1 split-bf16 (3 products), 2 split-bf16 (6 products)
   void launch(const GBases& bases, hipStream_t s, int precision = 0) const;
   void launch_shape_class(int c, const GBases& bases, hipStream_t s, int precision = 0) const;
