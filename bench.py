@@ -151,14 +151,16 @@ def main():
                 a[0] += t
                 a[1] += f
                 a[2] += 1
-        kname = "grouped_gemm_bf16_kernel" if prec else "grouped_gemm_kernel"
-        names = {0: "zero_fill_kernel"}
+        names = {0: "zero_fill_kernel", 1: "split_planes_kernel psi", 2: "split_planes_kernel V"}
         for ph in (1, 2):
             for c, sh in shapes.items():
-                if c >= 4:
+                if c >= 4 and ph == 2 and prec:
+                    names[10 * ph + c] = f"wave_planes_kernel{sh[:-1]}, {3 * prec}> phase {ph}"
+                elif c >= 4:
                     names[10 * ph + c] = f"wave_gemm_kernel{sh} phase {ph}"
                 else:
-                    names[10 * ph + c] = f"{kname}{sh[:-1]}{', ' + str(prec + 1) if prec else ''}> phase {ph}"
+                    names[10 * ph + c] = f"grouped_gemm_kernel{sh} phase {ph}"
+        names[16], names[26] = "split_reduce_kernel phase 1", "split_reduce_kernel phase 2"
         dom = max(kinds, key=lambda k: kinds[k][0])
         per = {names[k]: v[0] / v[2] for k, v in sorted(kinds.items())}
         log(f"bench: precision {prec}: H.psi {ms_:.3f} ms, {info['flops'] / (ms_ * 1e-3) / 1e12:.2f} TFLOP/s; "
@@ -168,8 +170,17 @@ def main():
     res = {p: time_precision(p) for p in (B.FP64, B.BF16X3, B.BF16X6)}
     ref = res[B.FP64][1]
     errs = {p: float(torch.linalg.norm(res[p][1] - ref) / torch.linalg.norm(ref)) for p in res}
-    log(f"bench: relative error vs fp64: x3 {errs[B.BF16X3]:.2e}, x6 {errs[B.BF16X6]:.2e}")
-    chosen = B.BF16X6 if errs[B.BF16X6] <= 1e-6 else B.FP64
+    # energy-scale error of each path on this vector, in hartree: |(H'-H)x|/|x|
+    # bounds the Rayleigh-quotient change, x.(H'-H)x/|x|^2 is that change itself
+    xn = float(torch.linalg.norm(x))
+    de_bound = {p: float(torch.linalg.norm(res[p][1] - ref)) / xn for p in res}
+    de_rq = {p: abs(float(torch.dot(x, res[p][1] - ref))) / xn ** 2 for p in res}
+    log(f"bench: relative error vs fp64: x3 {errs[B.BF16X3]:.2e}, x6 {errs[B.BF16X6]:.2e}; "
+        f"dE(Rayleigh) x3 {de_rq[B.BF16X3]:.2e} Eh, x6 {de_rq[B.BF16X6]:.2e} Eh")
+    # the reported path: the fastest one within 1e-6 relative 2-norm error of the
+    # float64 product whose energy (Rayleigh quotient) moves by at most 1e-6 Eh
+    ok = [p for p in res if errs[p] <= 1e-6 and de_rq[p] <= 1e-6]
+    chosen = min(ok, key=lambda p: res[p][0])
     ms, _, dname, t_dom, f_dom, per_launch = res[chosen]
     tflops = info["flops"] / (ms * 1e-3) / 1e12
     # algorithmic flops of the dominant kernel: the split-bf16 x6 product issues 6
@@ -265,7 +276,8 @@ def main():
                    "k_segments": info["segments"], "flops_per_step": info["flops"],
                    "precision_path": {0: "fp64", 1: "bf16x3", 2: "bf16x6"}[chosen], "env_build_s": t_env},
         "precisions": {name: {"ms": res[p][0], "tflops": info["flops"] / (res[p][0] * 1e-3) / 1e12,
-                              "rel_err_vs_fp64": errs[p], "per_launch_ms": res[p][5]}
+                              "rel_err_vs_fp64": errs[p], "dHx_over_x_Eh": de_bound[p],
+                              "d_rayleigh_Eh": de_rq[p], "per_launch_ms": res[p][5]}
                        for name, p in (("fp64", B.FP64), ("bf16x3", B.BF16X3), ("bf16x6", B.BF16X6))},
         "speedup_bf16x6_vs_fp64": res[B.FP64][0] / res[B.BF16X6][0],
         "roofline": {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",

@@ -105,9 +105,11 @@ int bsdmrg_psi_layout(bsdmrg_ctx* ctx, int site, int* n_blocks, int64_t* n_elems
                       int64_t* offsets);
 
 /* Prepare the effective-Hamiltonian product at `site` (the "Tables" step:
- * term list, aggregated operators, grouped-GEMM tile lists).  ws_bytes bounds
- * the intermediate workspace (0 = 4 GiB); larger problems are split into
- * chunks.  Synchronizes `stream`.  Optional: bsdmrg_hpsi prepares on first use. */
+ * term list, aggregated operators, grouped-GEMM tile lists, and the split-bf16
+ * planes of the left operators).  ws_bytes bounds the per-chunk intermediate
+ * workspace, the float64 products of the right operators with psi plus their
+ * bf16 planes (0 = 16 GiB); larger problems are split into chunks of channels.
+ * Synchronizes `stream`.  Optional: bsdmrg_hpsi prepares on first use. */
 int bsdmrg_hpsi_prepare(bsdmrg_ctx* ctx, int site, int precision, size_t ws_bytes,
                         bsdmrg_stream_t stream);
 
@@ -170,7 +172,8 @@ int bsdmrg_hpsi_info(bsdmrg_ctx* ctx, int site, int precision, double* flops, in
  * milliseconds ms[i], the algorithmic flops flops[i] of that launch and its kind
  * kind[i] (0 output zero-fill; 10 + c phase-1 and 20 + c phase-2 grouped GEMM
  * with tile shape class c: 0 64x64, 1 32x32, 2 32x64, 3 64x32 workgroup tiles,
- * 4 16x16 and 5 32x32 wave tiles).  Launches with no tiles are skipped.
+ * 4 16x16 and 5 32x32 wave tiles; 16 and 26 the reduction that sums the
+ * split-K parts of phase 1 and phase 2).  Launches with no tiles are skipped.
  * *n_launches receives the number of launches. */
 int bsdmrg_hpsi_profile(bsdmrg_ctx* ctx, int site, const double* psi_dev, double* out_dev, int precision,
                         bsdmrg_stream_t stream, int cap, double* ms, double* flops, int* kind,

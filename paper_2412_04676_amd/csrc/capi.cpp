@@ -302,7 +302,7 @@ static HpsiPlan* get_plan(Ctx& c, int site, int precision, size_t ws, hipStream_
   auto key = std::make_pair(site, 0);   // one plan serves every precision
   auto it = c.plans.find(key);
   if (it != c.plans.end() && !rebuild) return it->second.get();
-  if (ws == 0) ws = (size_t)4 << 30;
+  if (ws == 0) ws = (size_t)16 << 30;
   auto p = build_hpsi_plan(c, site, precision, ws, s);
   HpsiPlan* raw = p.get();
   c.plans[key] = std::move(p);
@@ -431,7 +431,7 @@ int bsdmrg_hpsi_info(bsdmrg_ctx* ctx, int site, int precision, double* flops, in
     if (n_channels) *n_channels = p.nchannels;
     if (n_segments) *n_segments = (int64_t)p.nseg;
     if (n_aggregates) *n_aggregates = p.naggs;
-    if (ws_bytes) *ws_bytes = (int64_t)(p.agg_bytes + p.v_bytes);
+    if (ws_bytes) *ws_bytes = (int64_t)(p.agg_bytes + p.v_bytes + p.plane_bytes);
   });
 }
 

@@ -7,17 +7,12 @@
 // every uneven sector GEMM of one phase runs in a single launch.  Operands are
 // staged through LDS in K-slices of 16; each wave owns a 32x32 sub-tile made of
 // 2x2 v_mfma_f64_16x16x4 accumulators.
-#include "internal.h"
+#include "devutil.h"
 
 #include <algorithm>
 
 namespace bsd {
 
-typedef double double4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ const double* resolve(uint64_t t, const GBases& b) {
-  return reinterpret_cast<const double*>(b.b[t >> kTagShift] + (t & ((1ull << kTagShift) - 1)));
-}
 
 constexpr int KB = 16;
 
@@ -101,7 +96,7 @@ grouped_gemm_kernel(const GTile* __restrict__ tiles, const GSeg* __restrict__ se
         const int r = wr + i * 16 + 4 * v + (lane >> 4);
         const int c = wc + j * 16 + (lane & 15);
         if (r < mt && c < nt) {
-          double* p = C + (int64_t)(tile.m0 + r) * tile.ldc + (tile.n0 + c);
+          double* p = C + (int64_t)r * tile.ldc + c;
           double x = acc[i][j][v];
           if (tile.beta != 0.0) x += tile.beta * (*p);
           *p = x;
@@ -117,17 +112,6 @@ grouped_gemm_kernel(const GTile* __restrict__ tiles, const GSeg* __restrict__ se
 // h h + h m + m h + h l + m m + l h (6 products); v_mfma_f32_16x16x32_bf16
 // accumulates them in float32, and the float32 accumulators are added into
 // float64 accumulators after every 256 values of K.
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef float float4_t __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ unsigned short bf16_rne(float f) {
-  unsigned int u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (unsigned short)(u >> 16);
-}
-__device__ __forceinline__ double bf16_to_double(unsigned short h) {
-  return (double)__uint_as_float(((unsigned int)h) << 16);
-}
 
 constexpr int KB16 = 32;     // K per MFMA step
 constexpr int KPAD = 40;     // LDS row stride in bf16 (80 bytes)
@@ -247,7 +231,7 @@ grouped_gemm_bf16_kernel(const GTile* __restrict__ tiles, const GSeg* __restrict
         const int r = wr + i * 16 + 4 * (lane >> 4) + v;
         const int c = wc + j * 16 + (lane & 15);
         if (r < mt && c < nt) {
-          double* p = C + (int64_t)(tile.m0 + r) * tile.ldc + (tile.n0 + c);
+          double* p = C + (int64_t)r * tile.ldc + c;
           double x = acc64[i][j][v] + (double)acc[i][j][v];
           if (tile.beta != 0.0) x += tile.beta * (*p);
           *p = x;
@@ -262,73 +246,130 @@ grouped_gemm_bf16_kernel(const GTile* __restrict__ tiles, const GSeg* __restrict
 // loads its MFMA operands straight from global memory / L2 (lane l holds
 // A[l % 16][k + l / 16] and B[k + l / 16][l % 16]) and never synchronizes; a
 // workgroup is four independent waves.
+
+// wave-uniform view of one K-segment
+struct WSeg {
+  const double* A;
+  const double* B;
+  int64_t lda, ldb;
+  int K, flags;
+  double alpha;
+};
+
+__device__ __forceinline__ WSeg load_wseg(const GSeg* __restrict__ segs, int idx, const GBases& bases) {
+  const GSeg g = segs[idx];
+  WSeg w;
+  w.A = resolve((uint64_t)uni64((int64_t)g.A), bases);
+  w.B = resolve((uint64_t)uni64((int64_t)g.B), bases);
+  w.lda = uni64(g.lda);
+  w.ldb = uni64(g.ldb);
+  w.K = uni(g.K);
+  w.flags = uni(g.flags);
+  w.alpha = unid(g.alpha);
+  return w;
+}
+
+// operands of one pass (16 values of K) for this lane
+template <int NI>
+__device__ __forceinline__ void load_pass(const WSeg& sg, int k0, const bool* rowok, const int* gi,
+                                          const bool* colok, const int* gj, int kq, double (&a)[4][NI],
+                                          double (&b)[4][NI]) {
+  const bool ta = sg.flags & kTransA, tb = sg.flags & kTransB, ia = sg.flags & kIdentA;
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int k = k0 + 4 * st + kq;
+    const bool kok = k < sg.K;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) {
+      double v = 0.0;
+      if (rowok[i] && kok) {
+        if (ia) v = (gi[i] == k) ? sg.alpha : 0.0;
+        else v = sg.alpha * (ta ? sg.A[(int64_t)k * sg.lda + gi[i]] : sg.A[(int64_t)gi[i] * sg.lda + k]);
+      }
+      a[st][i] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      double v = 0.0;
+      if (colok[j] && kok) v = tb ? sg.B[(int64_t)gj[j] * sg.ldb + k] : sg.B[(int64_t)k * sg.ldb + gj[j]];
+      b[st][j] = v;
+    }
+  }
+}
+
 template <int TW>
 __global__ void __launch_bounds__(256)
 wave_gemm_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __restrict__ segs, GBases bases) {
   constexpr int NI = TW / 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int ti = blockIdx.x * 4 + wave;
+  const int ti = uni(blockIdx.x * 4 + wave);
   if (ti >= ntiles) return;
   const GTile tile = tiles[ti];
-  const int mt = min(TW, tile.M - tile.m0);
-  const int nt = min(TW, tile.N - tile.n0);
+  const int M = uni(tile.M), N = uni(tile.N), m0 = uni(tile.m0), n0 = uni(tile.n0);
+  const int seg0 = uni(tile.seg0), nseg = uni(tile.nseg);
+  const int mt = min(TW, M - m0);
+  const int nt = min(TW, N - n0);
   const int r16 = lane & 15, kq = lane >> 4;
+  bool rowok[NI], colok[NI];
+  int gi[NI], gj[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    rowok[i] = i * 16 + r16 < mt;
+    gi[i] = m0 + i * 16 + r16;
+    colok[i] = i * 16 + r16 < nt;
+    gj[i] = n0 + i * 16 + r16;
+  }
   double4_t acc[NI][NI];
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int j = 0; j < NI; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
-  for (int sidx = 0; sidx < tile.nseg; ++sidx) {
-    const GSeg sg = segs[tile.seg0 + sidx];
-    const double* A = resolve(sg.A, bases);
-    const double* B = resolve(sg.B, bases);
-    const bool ta = sg.flags & kTransA, tb = sg.flags & kTransB, ia = sg.flags & kIdentA;
-    const double alpha = sg.alpha;
-    bool rowok[NI], colok[NI];
-    int gi[NI], gj[NI];
-#pragma unroll
-    for (int i = 0; i < NI; ++i) {
-      rowok[i] = i * 16 + r16 < mt;
-      gi[i] = tile.m0 + i * 16 + r16;
-      colok[i] = i * 16 + r16 < nt;
-      gj[i] = tile.n0 + i * 16 + r16;
-    }
-    // 16 values of K per pass: every operand load of the pass is issued before its MFMAs
-    for (int k0 = 0; k0 < sg.K; k0 += 16) {
-      double a[4][NI], b[4][NI];
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int k = k0 + 4 * st + kq;
-        const bool kok = k < sg.K;
-#pragma unroll
-        for (int i = 0; i < NI; ++i) {
-          double v = 0.0;
-          if (rowok[i] && kok) {
-            if (ia) v = (gi[i] == k) ? alpha : 0.0;
-            else v = alpha * (ta ? A[(int64_t)k * sg.lda + gi[i]] : A[(int64_t)gi[i] * sg.lda + k]);
-          }
-          a[st][i] = v;
-        }
-#pragma unroll
-        for (int j = 0; j < NI; ++j) {
-          double v = 0.0;
-          if (colok[j] && kok) v = tb ? B[(int64_t)gj[j] * sg.ldb + k] : B[(int64_t)k * sg.ldb + gj[j]];
-          b[st][j] = v;
-        }
+
+  // software pipeline over the flattened (segment, pass) sequence: the operands
+  // of the next pass are in flight while the MFMAs of the current one run
+  if (nseg > 0) {
+    int si = 0, k0 = 0;
+    WSeg cur = load_wseg(segs, seg0, bases);
+    double a[4][NI], b[4][NI], an[4][NI], bn[4][NI];
+    load_pass<NI>(cur, 0, rowok, gi, colok, gj, kq, a, b);
+    int cur_nst = min(4, (cur.K + 3) / 4);
+    while (true) {
+      // next pass
+      int nsi = si, nk0 = k0 + 16;
+      WSeg nxt = cur;
+      bool more = true;
+      if (nk0 >= cur.K) {
+        nsi = si + 1;
+        nk0 = 0;
+        if (nsi < nseg) nxt = load_wseg(segs, seg0 + nsi, bases);
+        else more = false;
       }
-      const int nst = min(4, (sg.K - k0 + 3) / 4);
+      if (more) load_pass<NI>(nxt, nk0, rowok, gi, colok, gj, kq, an, bn);
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
-        if (st >= nst) break;
+        if (st >= cur_nst) break;
 #pragma unroll
         for (int i = 0; i < NI; ++i)
 #pragma unroll
           for (int j = 0; j < NI; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][i], b[st][j], acc[i][j], 0, 0, 0);
       }
+      if (!more) break;
+      si = nsi;
+      k0 = nk0;
+      cur = nxt;
+      cur_nst = min(4, (cur.K - k0 + 3) / 4);
+#pragma unroll
+      for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          a[st][i] = an[st][i];
+          b[st][i] = bn[st][i];
+        }
     }
   }
   double* C = const_cast<double*>(resolve(tile.C, bases));
+  const double beta = tile.beta;
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
@@ -338,9 +379,9 @@ wave_gemm_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __rest
         const int r = i * 16 + 4 * v + kq;
         const int c = j * 16 + r16;
         if (r < mt && c < nt) {
-          double* p = C + (int64_t)(tile.m0 + r) * tile.ldc + (tile.n0 + c);
+          double* p = C + (int64_t)r * tile.ldc + c;
           double x = acc[i][j][v];
-          if (tile.beta != 0.0) x += tile.beta * (*p);
+          if (beta != 0.0) x += beta * (*p);
           *p = x;
         }
       }
@@ -409,10 +450,42 @@ void launch_aggregate(const AggTask* tasks, const AggTerm* terms, int ntasks, hi
 }
 
 // ---------------------------------------------------------------- plan building (host)
-void GemmPlan::build(const std::vector<GemmProblem>& probs, bool wave_tiles) {
-  std::vector<GTile> t[kShapes];
-  std::vector<double> work[kShapes];
+__global__ void __launch_bounds__(256)
+split_reduce_kernel(const GReduce* __restrict__ red, GBases bases) {
+  const GReduce t = red[blockIdx.x];
+  double* C = const_cast<double*>(resolve(t.C, bases));
+  const int n = t.rows * t.cols;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int r = e / t.cols, c = e % t.cols;
+    const double* q = t.parts + (int64_t)r * t.ldp + c;
+    double x = 0.0;
+    for (int p = 0; p < t.nparts; ++p) x += q[p * t.part_stride];
+    double* o = C + (int64_t)r * t.ldc + c;
+    if (t.beta != 0.0) x += t.beta * (*o);
+    *o = x;
+  }
+}
+
+void launch_split_reduce(const GReduce* red, int n, const GBases& b, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(split_reduce_kernel, dim3(n), dim3(256), 0, s, red, b);
+  BSD_HIP(hipGetLastError());
+}
+
+void GemmPlan::build(const std::vector<GemmProblem>& probs, bool wave_tiles, bool split_k, bool plane_operands) {
+  // tile shape classes and the waves one tile of each class occupies
+  const int TMs[kShapes] = {64, 32, 32, 64, 16, 32}, TNs[kShapes] = {64, 32, 64, 32, 16, 32};
+  const int waves_per_tile[kShapes] = {4, 1, 2, 2, 1, 1};
+  // split-K targets: about this many waves per launch, and parts of at least
+  // this much work (work = sum of K + 16 per segment)
+  constexpr double kTargetWaves = 8192.0, kMinPartWork = 640.0;
+  struct Pending {
+    GTile t;
+    double work;
+  };
+  std::vector<Pending> t[kShapes];
   std::vector<GSeg> sg;
+  std::vector<double> segwork;
   flops = 0.0;
   for (int c = 0; c < kShapes; ++c) shape_flops[c] = 0.0;
   for (const auto& p : probs) {
@@ -420,10 +493,9 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, bool wave_tiles) {
     int seg0 = (int)sg.size();
     // wave tiles for blocks up to 64 x 64 (float64 lists); otherwise the
     // workgroup tile with the smallest padded area, then fewer tiles
-    const int TMs[kShapes] = {64, 32, 32, 64, 16, 32}, TNs[kShapes] = {64, 32, 64, 32, 16, 32};
     int cls = 0;
     int64_t best = -1;
-    if (wave_tiles && p.M <= 64 && p.N <= 64) {
+    if (plane_operands || (wave_tiles && p.M <= 64 && p.N <= 64)) {
       cls = (p.M <= 16 && p.N <= 16) ? 4 : 5;
       best = 0;
     }
@@ -436,11 +508,12 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, bool wave_tiles) {
         cls = c;
       }
     }
-    int64_t ktot = 0;
+    double ktot = 0;
     for (const auto& s : p.segs) {
       if (s.K <= 0) continue;
       sg.push_back(s);
-      ktot += s.K;
+      segwork.push_back(s.K + 16.0);
+      ktot += s.K + 16.0;
       if (!(s.flags & kIdentA)) {
         double f = 2.0 * p.M * (double)p.N * s.K;
         flops += f;
@@ -451,7 +524,7 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, bool wave_tiles) {
     for (int m0 = 0; m0 < p.M; m0 += TMs[cls])
       for (int n0 = 0; n0 < p.N; n0 += TNs[cls]) {
         GTile x;
-        x.C = p.C;
+        x.C = p.C + (uint64_t)(((int64_t)m0 * p.ldc + n0) * (int64_t)sizeof(double));
         x.ldc = p.ldc;
         x.M = p.M;
         x.N = p.N;
@@ -460,35 +533,111 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, bool wave_tiles) {
         x.seg0 = seg0;
         x.nseg = nseg;
         x.beta = p.beta;
-        t[cls].push_back(x);
-        work[cls].push_back((double)ktot + 16.0 * nseg);
+        t[cls].push_back({x, ktot});
       }
   }
-  wave = wave_tiles;
-  // longest tiles first inside every launch (LPT order)
+  wave = wave_tiles || plane_operands;
+  planes = plane_operands;
+  // split long tiles into parts of about equal work: each part accumulates its
+  // own contiguous run of segments into a workspace slot, and one reduction per
+  // split tile adds the parts in a fixed order (deterministic results)
   std::vector<GTile> all;
+  std::vector<int64_t> slot;      // per entry of `all`: workspace offset (doubles), -1 = direct
+  std::vector<GReduce> red;
+  std::vector<int64_t> red_off;   // per reduction: workspace offset of part 0
+  int64_t ws_elems = 0;
   for (int c = 0; c < kShapes; ++c) {
-    std::vector<int> idx(t[c].size());
-    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return work[c][a] > work[c][b]; });
+    double total = 0.0;
+    for (const auto& x : t[c]) total += x.work;
+    const double target = std::max(kMinPartWork, total * waves_per_tile[c] / kTargetWaves);
+    std::vector<std::pair<Pending, int64_t>> units;
+    for (const auto& x : t[c]) {
+      const int nparts = split_k ? (int)std::min<double>(x.t.nseg, std::ceil(x.work / target)) : 1;
+      if (nparts <= 1) {
+        units.push_back({x, -1});
+        continue;
+      }
+      const int64_t stride = (int64_t)TMs[c] * TNs[c];
+      const double per = x.work / nparts;
+      const int send = x.t.seg0 + x.t.nseg;
+      int s0 = x.t.seg0, made = 0;
+      double acc = 0.0;
+      for (int si = x.t.seg0; si < send; ++si) {
+        acc += segwork[si];
+        if (si == send - 1 || acc >= per * (made + 1)) {
+          Pending u = x;
+          u.t.seg0 = s0;
+          u.t.nseg = si + 1 - s0;
+          u.t.ldc = TNs[c];
+          u.t.beta = 0.0;
+          u.work = 0.0;
+          for (int k = s0; k <= si; ++k) u.work += segwork[k];
+          units.push_back({u, ws_elems + (int64_t)made * stride});
+          ++made;
+          s0 = si + 1;
+        }
+      }
+      GReduce r;
+      r.C = x.t.C;
+      r.ldc = x.t.ldc;
+      r.parts = nullptr;
+      r.rows = std::min(TMs[c], x.t.M - x.t.m0);
+      r.cols = std::min(TNs[c], x.t.N - x.t.n0);
+      r.nparts = made;
+      r.ldp = TNs[c];
+      r.part_stride = stride;
+      r.beta = x.t.beta;
+      red.push_back(r);
+      red_off.push_back(ws_elems);
+      ws_elems += (int64_t)made * stride;
+    }
+    // longest units first inside every launch (LPT order)
+    std::stable_sort(units.begin(), units.end(),
+                     [](const std::pair<Pending, int64_t>& a, const std::pair<Pending, int64_t>& b) {
+                       return a.first.work > b.first.work;
+                     });
     first[c] = (int)all.size();
-    count[c] = (int)idx.size();
-    for (int i : idx) all.push_back(t[c][i]);
+    count[c] = (int)units.size();
+    for (const auto& u : units) {
+      all.push_back(u.first.t);
+      slot.push_back(u.second);
+    }
   }
+  if (ws_elems > 0) parts.reserve(ws_elems * sizeof(double));
+  double* ws = static_cast<double*>(parts.p);
+  for (size_t i = 0; i < all.size(); ++i)
+    if (slot[i] >= 0) all[i].C = tag_ptr(0, (uint64_t)(uintptr_t)(ws + slot[i]));
+  for (size_t i = 0; i < red.size(); ++i) red[i].parts = ws + red_off[i];
+  nreduce = (int)red.size();
   tiles.reserve(std::max<size_t>(1, all.size()) * sizeof(GTile));
   segs.reserve(std::max<size_t>(1, sg.size()) * sizeof(GSeg));
   if (!all.empty()) BSD_HIP(hipMemcpy(tiles.p, all.data(), all.size() * sizeof(GTile), hipMemcpyHostToDevice));
   if (!sg.empty()) BSD_HIP(hipMemcpy(segs.p, sg.data(), sg.size() * sizeof(GSeg), hipMemcpyHostToDevice));
+  if (nreduce > 0) {
+    reduces.reserve(red.size() * sizeof(GReduce));
+    BSD_HIP(hipMemcpy(reduces.p, red.data(), red.size() * sizeof(GReduce), hipMemcpyHostToDevice));
+  }
 }
 
 void GemmPlan::launch_shape_class(int c, const GBases& bases, hipStream_t s, int precision) const {
+  if (planes) {
+    BSD_CHECK(precision != 0, 1, "plane-operand tile list launched at float64 precision");
+    launch_planes_gemm(static_cast<const GTile*>(tiles.p) + first[c], count[c], c,
+                       static_cast<const GSeg*>(segs.p), bases, s, precision);
+    return;
+  }
   BSD_CHECK(!(wave && count[4] + count[5] > 0 && precision != 0), 1, "float64 tile list launched at split precision");
   launch_grouped_gemm(static_cast<const GTile*>(tiles.p) + first[c], count[c], c,
                       static_cast<const GSeg*>(segs.p), bases, s, precision);
 }
 
+void GemmPlan::launch_reduce(const GBases& bases, hipStream_t s) const {
+  launch_split_reduce(static_cast<const GReduce*>(reduces.p), nreduce, bases, s);
+}
+
 void GemmPlan::launch(const GBases& bases, hipStream_t s, int precision) const {
   for (int c = 0; c < kShapes; ++c) launch_shape_class(c, bases, s, precision);
+  launch_reduce(bases, s);
 }
 
 }  // namespace bsd

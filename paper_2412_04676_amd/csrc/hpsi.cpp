@@ -61,9 +61,10 @@ void build_psi_layout(const Block& Lb, const Block& Rb, const SiteSet& C, const 
   lay.blocks.clear();
   lay.stack_off.assign(Rb.basis.q.size(), -1);
   lay.stack_rows.assign(Rb.basis.q.size(), 0);
+  lay.stack_prows.assign(Rb.basis.q.size(), 0);
   int64_t off = 0;
   for (int r = 0; r < (int)Rb.basis.q.size(); ++r) {
-    int rows = 0;
+    int rows = 0, prows = 0;
     int64_t base = off;
     for (int l = 0; l < (int)Lb.basis.q.size(); ++l)
       for (int c = 0; c < 16; ++c) {
@@ -76,14 +77,17 @@ void build_psi_layout(const Block& Lb, const Block& Rb, const SiteSet& C, const 
         b.cols = Rb.basis.dim[r];
         b.off = off;
         b.row_in_stack = rows;
+        b.prow_in_stack = prows;
         lay.index[{l, c, r}] = (int)lay.blocks.size();
         lay.blocks.push_back(b);
         off += (int64_t)b.rows * b.cols;
         rows += b.rows;
+        prows += (b.rows + 7) / 8 * 8;
       }
     if (rows > 0) {
       lay.stack_off[r] = base;
       lay.stack_rows[r] = rows;
+      lay.stack_prows[r] = prows;
     }
   }
   lay.n_elems = off;
@@ -314,18 +318,21 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   struct VInfo {
     std::vector<int64_t> off;   // per output right index, element offset in chunk workspace or -1
     std::vector<int> src;       // input right index feeding r'
+    std::vector<int64_t> poff;  // per output right index, bf16 offset in the chunk's plane workspace
   };
   std::vector<VInfo> vinfo(chans.size());
   std::vector<int> chunk_of(chans.size());
-  std::vector<int64_t> chunk_size;
-  int64_t cur = 0;
-  const int64_t budget = (int64_t)(ws_budget / sizeof(double));
+  std::vector<int64_t> chunk_size, chunk_psize;
+  int64_t cur = 0, curp = 0;
+  // the workspace budget covers V (float64) and its split planes (bf16)
+  const int64_t budget = (int64_t)ws_budget;
   for (size_t ci = 0; ci < chans.size(); ++ci) {
     auto& ch = chans[ci];
     VInfo vi;
     vi.off.assign(nR, -1);
     vi.src.assign(nR, -1);
-    int64_t need = 0;
+    vi.poff.assign(nR, -1);
+    int64_t need = 0, needp = 0;
     if (ch.rkind == 0) {
       for (int r = 0; r < nR; ++r) {
         if (lay.stack_rows[r] == 0) continue;
@@ -335,8 +342,10 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
         const double* p = ch.rtrans ? Rb->op_block(ch.rkey, r2, &rr, &cc, &ld) : Rb->op_block(ch.rkey, r, &rr, &cc, &ld);
         if (!p) continue;
         vi.off[r2] = need;   // relative, fixed below
+        vi.poff[r2] = needp;
         vi.src[r2] = r;
         need += ((int64_t)lay.stack_rows[r] * Rb->basis.dim[r2] + 1) / 2 * 2;
+        needp += (int64_t)Rb->basis.dim[r2] * lay.stack_prows[r] * kPlaneParts;
       }
       if (need == 0) {
         cgroups[ci].clear();
@@ -345,21 +354,61 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
         continue;
       }
     }
-    if (chunk_size.empty() || (cur + need > budget && cur > 0)) {
+    const auto bytes = [](int64_t v, int64_t pl) { return v * (int64_t)sizeof(double) + pl * 2; };
+    if (chunk_size.empty() || (bytes(cur + need, curp + needp) > budget && (cur > 0 || curp > 0))) {
       chunk_size.push_back(0);
+      chunk_psize.push_back(0);
       cur = 0;
+      curp = 0;
     }
     for (auto& o : vi.off)
       if (o >= 0) o += cur;
+    for (auto& o : vi.poff)
+      if (o >= 0) o += curp;
     cur += need;
+    curp += needp;
     chunk_size.back() = cur;
+    chunk_psize.back() = curp;
     chunk_of[ci] = (int)chunk_size.size() - 1;
     vinfo[ci] = vi;
   }
-  int64_t ws_elems = 0;
+  int64_t ws_elems = 0, vp_elems = 0;
   for (auto c : chunk_size) ws_elems = std::max(ws_elems, c);
+  for (auto c : chunk_psize) vp_elems = std::max(vp_elems, c);
   plan->V.reserve(std::max<int64_t>(1, ws_elems) * sizeof(double));
   plan->v_bytes = ws_elems * sizeof(double);
+
+  // plane arena (bf16 elements): [V planes of one chunk | psi planes | L-operator planes]
+  const int64_t psip_base = vp_elems;
+  std::vector<int64_t> psi_poff(lay.blocks.size());
+  int64_t arena = psip_base;
+  for (size_t bi = 0; bi < lay.blocks.size(); ++bi) {
+    const PsiBlk& pb = lay.blocks[bi];
+    psi_poff[bi] = arena;
+    arena += (int64_t)pb.cols * ((pb.rows + 7) / 8) * 8 * kPlaneParts;
+  }
+  const int64_t ap_base = arena;
+  std::map<std::pair<const double*, bool>, int64_t> a_planes;   // (block, transposed) -> arena offset
+  std::vector<SplitTask> a_tasks;
+  auto a_plane = [&](const Operand2& o, int M, int K) -> int64_t {
+    auto key = std::make_pair(o.p, o.trans);
+    auto it = a_planes.find(key);
+    if (it != a_planes.end()) return it->second;
+    SplitTask t;
+    t.src = tag_ptr(0, (uint64_t)o.p);
+    t.lds = o.ld;
+    t.kmap = nullptr;
+    t.dst = reinterpret_cast<uint16_t*>((uintptr_t)(arena * 2));   // arena byte offset, fixed below
+    t.rows = M;
+    t.kcols = K;
+    t.chunks = (K + 7) / 8;
+    t.trans = o.trans ? 1 : 0;
+    a_tasks.push_back(t);
+    a_planes[key] = arena;
+    const int64_t at = arena;
+    arena += (int64_t)M * t.chunks * 8 * kPlaneParts;
+    return at;
+  };
   double* V = static_cast<double*>(plan->V.p);
   const int nchunks = (int)chunk_size.size();
   plan->phase1.resize(nchunks);
@@ -368,7 +417,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
 
   std::vector<std::vector<GemmProblem>> p1(nchunks);
   // per chunk, per output psi block: list of segments
-  std::vector<std::map<int, GemmProblem>> p2(nchunks);
+  std::vector<std::map<int, GemmProblem>> p2(nchunks), p2s(nchunks);
   for (size_t ci = 0; ci < chans.size(); ++ci) {
     if (chunk_of[ci] < 0 || cgroups[ci].empty()) continue;
     const int ck = chunk_of[ci];
@@ -444,6 +493,30 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
             }
             gp.segs.push_back(sg);
             if (!o.ident) useful += 2.0 * ob.rows * (double)ob.cols * pb.rows;
+            // the same product on split planes: A rows of op(Lambda), B rows of V^T (or psi^T)
+            GSeg sq;
+            sq.alpha = sg.alpha;
+            sq.K = pb.rows;
+            sq.flags = o.ident ? kIdentA : 0;
+            sq.A = o.ident ? tag_ptr(3, 0) : tag_ptr(3, (uint64_t)(a_plane(o, ob.rows, pb.rows) * 2));
+            sq.lda = (pb.rows + 7) / 8;
+            if (ch.rkind == 1) {
+              sq.B = tag_ptr(3, (uint64_t)(psi_poff[bi] * 2));
+              sq.ldb = (pb.rows + 7) / 8;
+            } else {
+              const int64_t e = vi.poff[r2] + (int64_t)(pb.prow_in_stack / 8) * 8 * kPlaneParts;
+              sq.B = tag_ptr(3, (uint64_t)(e * 2));
+              sq.ldb = lay.stack_prows[pb.r] / 8;
+            }
+            auto& gq = p2s[ck][oit->second];
+            if (gq.segs.empty()) {
+              gq.C = gp.C;
+              gq.ldc = gp.ldc;
+              gq.M = gp.M;
+              gq.N = gp.N;
+              gq.beta = 1.0;
+            }
+            gq.segs.push_back(sq);
           }
         }
     }
@@ -507,22 +580,91 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     plan->diag_plan->build(v, true);
   }
   plan->nseg = 0;
-  plan->phase1b.resize(nchunks);
-  plan->phase2b.resize(nchunks);
+  plan->phase2s.resize(nchunks);
   for (int k = 0; k < nchunks; ++k) {
     plan->phase1[k] = std::make_unique<GemmPlan>();
     plan->phase1[k]->build(p1[k], true);
-    plan->phase1b[k] = std::make_unique<GemmPlan>();
-    plan->phase1b[k]->build(p1[k], false);
-    std::vector<GemmProblem> v;
+    std::vector<GemmProblem> v, vs;
     for (auto& kv : p2[k]) {
       plan->nseg += kv.second.segs.size();
       v.push_back(std::move(kv.second));
     }
+    for (auto& kv : p2s[k]) vs.push_back(std::move(kv.second));
     plan->phase2[k] = std::make_unique<GemmPlan>();
     plan->phase2[k]->build(v, true);
-    plan->phase2b[k] = std::make_unique<GemmPlan>();
-    plan->phase2b[k]->build(v, false);
+    plan->phase2s[k] = std::make_unique<GemmPlan>();
+    plan->phase2s[k]->build(vs, true, true, true);
+  }
+
+  // ---------------------------------------------------------------- split tasks
+  // padded-row maps of the right-sector stacks: plane column -> stack row or -1
+  std::vector<int64_t> kmap_off(nR, -1);
+  std::vector<int32_t> kmap;
+  for (int r = 0; r < nR; ++r) {
+    if (lay.stack_rows[r] == 0) continue;
+    kmap_off[r] = (int64_t)kmap.size();
+    kmap.resize(kmap.size() + lay.stack_prows[r], -1);
+  }
+  for (const auto& pb : lay.blocks)
+    for (int i = 0; i < pb.rows; ++i) kmap[kmap_off[pb.r] + pb.prow_in_stack + i] = pb.row_in_stack + i;
+  plan->kmaps.reserve(std::max<size_t>(1, kmap.size()) * sizeof(int32_t));
+  if (!kmap.empty())
+    BSD_HIP(hipMemcpy(plan->kmaps.p, kmap.data(), kmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  const int32_t* kmap_dev = static_cast<const int32_t*>(plan->kmaps.p);
+  plan->plane_bytes = (size_t)arena * 2;
+  plan->planes.reserve(std::max<size_t>(16, plan->plane_bytes));
+  uint16_t* ar = static_cast<uint16_t*>(plan->planes.p);
+  std::vector<SplitTask> tasks;
+  for (size_t bi = 0; bi < lay.blocks.size(); ++bi) {
+    const PsiBlk& pb = lay.blocks[bi];
+    SplitTask t;
+    t.src = tag_ptr(1, (uint64_t)(pb.off * sizeof(double)));
+    t.lds = pb.cols;
+    t.kmap = nullptr;
+    t.dst = ar + psi_poff[bi];
+    t.rows = pb.cols;
+    t.kcols = pb.rows;
+    t.chunks = (pb.rows + 7) / 8;
+    t.trans = 1;
+    tasks.push_back(t);
+  }
+  plan->n_split_psi = (int)tasks.size();
+  plan->split_v_first.assign(nchunks, 0);
+  plan->split_v_count.assign(nchunks, 0);
+  for (int k = 0; k < nchunks; ++k) {
+    plan->split_v_first[k] = (int)tasks.size();
+    for (size_t ci = 0; ci < chans.size(); ++ci) {
+      if (chunk_of[ci] != k || cgroups[ci].empty() || chans[ci].rkind != 0) continue;
+      const auto& vi = vinfo[ci];
+      for (int r2 = 0; r2 < nR; ++r2) {
+        if (vi.off[r2] < 0) continue;
+        const int r = vi.src[r2];
+        SplitTask t;
+        t.src = tag_ptr(0, (uint64_t)(V + vi.off[r2]));
+        t.lds = Rb->basis.dim[r2];
+        t.kmap = kmap_dev + kmap_off[r];
+        t.dst = ar + vi.poff[r2];
+        t.rows = Rb->basis.dim[r2];
+        t.kcols = lay.stack_prows[r];
+        t.chunks = lay.stack_prows[r] / 8;
+        t.trans = 1;
+        tasks.push_back(t);
+      }
+    }
+    plan->split_v_count[k] = (int)tasks.size() - plan->split_v_first[k];
+  }
+  plan->split_tasks.reserve(std::max<size_t>(1, tasks.size()) * sizeof(SplitTask));
+  if (!tasks.empty())
+    BSD_HIP(hipMemcpy(plan->split_tasks.p, tasks.data(), tasks.size() * sizeof(SplitTask), hipMemcpyHostToDevice));
+  // L-operator planes: split once here
+  if (!a_tasks.empty()) {
+    for (auto& t : a_tasks) t.dst = ar + (int64_t)((uintptr_t)t.dst / 2);
+    DevBuf dt;
+    dt.reserve(a_tasks.size() * sizeof(SplitTask));
+    BSD_HIP(hipMemcpyAsync(dt.p, a_tasks.data(), a_tasks.size() * sizeof(SplitTask), hipMemcpyHostToDevice, s));
+    GBases b0{{0, 0, 0, 0}};
+    launch_split_planes(static_cast<const SplitTask*>(dt.p), (int)a_tasks.size(), b0, s);
+    BSD_HIP(hipStreamSynchronize(s));
   }
   plan->useful_flops = useful;
   plan->nchannels = (int)chans.size();
@@ -530,9 +672,15 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   return plan;
 }
 
+static GBases hpsi_bases(const HpsiPlan& plan, const double* psi, double* out) {
+  return GBases{{0, (uint64_t)psi, (uint64_t)out, (uint64_t)plan.planes.p}};
+}
+
 int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision, int cap,
                  double* ms, double* flops, int* kind) {
-  // kind: 0 zero-fill, 10 + c phase-1 grouped GEMM with tile shape class c, 20 + c phase 2
+  // kind: 0 zero-fill, 1 / 2 split of psi / of the phase-1 output into bf16
+  // planes, 10 + c phase-1 grouped GEMM with tile shape class c, 20 + c phase 2,
+  // 10 + kShapes / 20 + kShapes the split-K reduction of phase 1 / phase 2
   std::vector<hipEvent_t> ev;
   std::vector<int> kinds;
   std::vector<double> fl;
@@ -542,21 +690,40 @@ int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream
     BSD_HIP(hipEventRecord(e, s));
     ev.push_back(e);
   };
-  GBases b{{0, (uint64_t)psi, (uint64_t)out, 0}};
+  const GBases b = hpsi_bases(plan, psi, out);
+  const SplitTask* tasks = static_cast<const SplitTask*>(plan.split_tasks.p);
   mark();
   zero_fill(out, plan.lay.n_elems, s);
   kinds.push_back(0);
   fl.push_back(0.0);
   mark();
+  if (precision != 0 && plan.n_split_psi > 0) {
+    launch_split_planes(tasks, plan.n_split_psi, b, s);
+    kinds.push_back(1);
+    fl.push_back(0.0);
+    mark();
+  }
   for (size_t k = 0; k < plan.phase1.size(); ++k) {
     for (int ph = 1; ph <= 2; ++ph) {
-      const GemmPlan& gp = precision == 0 ? (ph == 1 ? *plan.phase1[k] : *plan.phase2[k])
-                                          : (ph == 1 ? *plan.phase1b[k] : *plan.phase2b[k]);
+      if (ph == 2 && precision != 0 && plan.split_v_count[k] > 0) {
+        launch_split_planes(tasks + plan.split_v_first[k], plan.split_v_count[k], b, s);
+        kinds.push_back(2);
+        fl.push_back(0.0);
+        mark();
+      }
+      const GemmPlan& gp = ph == 1 ? *plan.phase1[k] : (precision == 0 ? *plan.phase2[k] : *plan.phase2s[k]);
+      const int prec = ph == 1 ? 0 : precision;
       for (int c = 0; c < kShapes; ++c) {
         if (gp.count[c] == 0) continue;
-        gp.launch_shape_class(c, b, s, precision);
+        gp.launch_shape_class(c, b, s, prec);
         kinds.push_back(10 * ph + c);
         fl.push_back(gp.shape_flops[c]);
+        mark();
+      }
+      if (gp.nreduce > 0) {
+        gp.launch_reduce(b, s);
+        kinds.push_back(10 * ph + kShapes);
+        fl.push_back(0.0);
         mark();
       }
     }
@@ -617,14 +784,16 @@ const double* hpsi_diagonal(HpsiPlan& plan, hipStream_t s) {
 
 void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision) {
   zero_fill(out, plan.lay.n_elems, s);
-  GBases b{{0, (uint64_t)psi, (uint64_t)out, 0}};
+  const GBases b = hpsi_bases(plan, psi, out);
+  const SplitTask* tasks = static_cast<const SplitTask*>(plan.split_tasks.p);
+  if (precision != 0) launch_split_planes(tasks, plan.n_split_psi, b, s);
   for (size_t k = 0; k < plan.phase1.size(); ++k) {
+    plan.phase1[k]->launch(b, s, 0);
     if (precision == 0) {
-      plan.phase1[k]->launch(b, s, 0);
       plan.phase2[k]->launch(b, s, 0);
     } else {
-      plan.phase1b[k]->launch(b, s, precision);
-      plan.phase2b[k]->launch(b, s, precision);
+      launch_split_planes(tasks + plan.split_v_first[k], plan.split_v_count[k], b, s);
+      plan.phase2s[k]->launch(b, s, precision);
     }
   }
 }

@@ -9,6 +9,7 @@ struct PsiBlk {
   int rows, cols;
   int64_t off;          // element offset
   int row_in_stack;     // row offset inside the right sector's stack
+  int prow_in_stack;    // the same in the stack padded to multiples of 8 rows
 };
 
 // psi is stored grouped by right sector: for each right sector r, the blocks
@@ -19,6 +20,7 @@ struct PsiLayout {
   std::map<std::tuple<int, int, int>, int> index;
   std::vector<int64_t> stack_off;
   std::vector<int> stack_rows;
+  std::vector<int> stack_prows;   // padded stack rows (multiple of 8)
   int64_t n_elems = 0;
 };
 
@@ -45,7 +47,13 @@ struct HpsiPlan {
   DevBuf agg, V;
   size_t agg_bytes = 0, v_bytes = 0;
   std::vector<std::unique_ptr<GemmPlan>> phase1, phase2;      // float64 tile lists
-  std::vector<std::unique_ptr<GemmPlan>> phase1b, phase2b;    // split-bf16 tile lists
+  // split precision: phase 1 runs in float64, its output and psi are cut into
+  // bf16 planes (arena addressed through pointer tag 3), phase 2 on the planes
+  std::vector<std::unique_ptr<GemmPlan>> phase2s;
+  DevBuf planes, kmaps, split_tasks;
+  size_t plane_bytes = 0;
+  int n_split_psi = 0;                   // tasks [0, n_split_psi) split psi
+  std::vector<int> split_v_first, split_v_count;   // per chunk: tasks splitting V
   std::unique_ptr<GemmPlan> diag_plan;   // diagonal of H_eff (rank-1 sector products)
   DevBuf ones, diag, dav_work;
   bool diag_ready = false;

@@ -245,11 +245,25 @@ struct GSeg {
   int32_t K, flags;
   double alpha;
 };
+// One unit of work of a grouped-GEMM launch: the tile at (m0, n0) of an M x N
+// problem over the K-segments seg0 .. seg0 + nseg - 1.  C points at the tile's
+// own origin: inside the problem's output, or, for one part of a split-K tile,
+// at a dense workspace slot (ldc = tile width, beta = 0) that a reduction adds
+// into the output afterwards.
 struct GTile {
   uint64_t C;
   int64_t ldc;
   int32_t M, N, m0, n0;
   int32_t seg0, nseg;
+  double beta;
+};
+// Fixed-order sum of the split-K parts of one tile: C = beta C + sum_p part_p.
+struct GReduce {
+  uint64_t C;
+  int64_t ldc;
+  const double* parts;
+  int32_t rows, cols, nparts, ldp;
+  int64_t part_stride;
   double beta;
 };
 struct GBases {
@@ -270,17 +284,45 @@ struct GemmProblem {
 // (workgroup tiles staged through LDS), 4 16x16 and 5 32x32 (one wave each,
 // float64 only).
 constexpr int kShapes = 6;
+// Split-bf16 operand planes.  A float64 matrix X (rows x K) is stored once as
+// bf16 parts X ~ h + m + l (h = bf16(X), m = bf16(X - h), l = bf16(X - h - m)),
+// laid out for the MFMA operand fetch: each row is cut into ceil(K / 8) chunks
+// of 8 consecutive K values and a chunk keeps its three parts side by side
+// (48 bytes), so element (i, k, part p) sits at
+//   ((i * chunks + k / 8) * 3 + p) * 8 + k % 8.
+// Values past K (and columns that kmap sends to -1) are zero.
+constexpr int kPlaneParts = 3;
+struct SplitTask {
+  uint64_t src;         // tagged float64 source
+  int64_t lds;          // source leading dimension
+  const int32_t* kmap;  // optional: plane column -> source column (-1 = zero)
+  uint16_t* dst;
+  int32_t rows, kcols;  // plane rows; plane columns (source K, or kmap length)
+  int32_t chunks;       // chunks per plane row (>= ceil(kcols / 8))
+  int32_t trans;        // source element (i, k) at src[k * lds + i] (else src[i * lds + k])
+};
+void launch_split_planes(const SplitTask* tasks, int n, const GBases& b, hipStream_t s);
+
 struct GemmPlan {
   int first[kShapes] = {0, 0, 0, 0, 0, 0}, count[kShapes] = {0, 0, 0, 0, 0, 0};
   bool wave = false;
+  // planes: the segments' A and B point at split-bf16 planes (A rows of op(A),
+  // B rows of op(B)^T, lda / ldb in chunks); launched only at split precision
+  bool planes = false;
   DevBuf tiles, segs;
+  // split-K: parts of long tiles write workspace slots, summed by one reduction
+  DevBuf parts, reduces;
+  int nreduce = 0;
   double flops = 0.0;                       // useful flops (2 M N K over non-identity segments)
   double shape_flops[kShapes] = {0, 0, 0, 0, 0, 0};
-  // wave_tiles: small problems get wave tiles (the list is then float64 only)
-  void build(const std::vector<GemmProblem>& probs, bool wave_tiles = true);
+  // wave_tiles: small problems get wave tiles (the list is then float64 only);
+  // split_k: cut long tiles into parts so that every launch fills the device
+  void build(const std::vector<GemmProblem>& probs, bool wave_tiles = true, bool split_k = true,
+             bool plane_operands = false);
   // precision: 0 float64 MFMA, 1 split-bf16 (3 products), 2 split-bf16 (6 products)
   void launch(const GBases& bases, hipStream_t s, int precision = 0) const;
   void launch_shape_class(int c, const GBases& bases, hipStream_t s, int precision = 0) const;
+  void launch_reduce(const GBases& bases, hipStream_t s) const;
 };
 
 struct AggTerm {
@@ -300,6 +342,9 @@ void launch_aggregate(const AggTask* tasks_dev, const AggTerm* terms_dev, int nt
                       hipStream_t s);
 void launch_grouped_gemm(const GTile* tiles, int ntiles, int shape, const GSeg* segs,
                          const GBases& b, hipStream_t s, int precision = 0);
+void launch_split_reduce(const GReduce* red, int n, const GBases& b, hipStream_t s);
+void launch_planes_gemm(const GTile* tiles, int ntiles, int shape, const GSeg* segs, const GBases& b,
+                        hipStream_t s, int precision);
 
 // ---------------------------------------------------------------- serializer
 struct FamilyView {

@@ -1,0 +1,284 @@
+// Split-bf16 block products on pre-split operand planes.
+//
+// The float64 operands of the block GEMMs are cut once into three bf16 parts
+// (x ~ h + m + l) and stored as planes whose layout is exactly the per-lane
+// operand of v_mfma_f32_16x16x32_bf16 (8 consecutive K values of one row per
+// lane, 16 bytes per part).  Splitting once means the product kernel only
+// streams bf16 chunks and runs MFMAs; the L-operator blocks are split when the
+// product is prepared, psi and the phase-1 intermediates once per product.
+//
+// Products kept: h h + h m + m h (3 MFMAs, float32 accuracy of the dominant
+// terms) or additionally h l + m m + l h (6 MFMAs).  Every K-segment is summed
+// in float32 by the MFMAs and then added, times its coefficient alpha, into
+// float64 accumulators.
+#include "devutil.h"
+
+namespace bsd {
+
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split3(double x, unsigned short& h, unsigned short& m, unsigned short& l) {
+  h = bf16_rne((float)x);
+  const double r1 = x - bf16_to_double(h);
+  m = bf16_rne((float)r1);
+  const double r2 = r1 - bf16_to_double(m);
+  l = bf16_rne((float)r2);
+}
+
+// one workgroup per task; each thread writes whole chunks (3 x 16 bytes)
+__global__ void __launch_bounds__(256)
+split_planes_kernel(const SplitTask* __restrict__ tasks, GBases bases) {
+  const SplitTask t = tasks[blockIdx.x];
+  const double* src = resolve(t.src, bases);
+  const int n = t.rows * t.chunks;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    // consecutive threads read consecutive source addresses
+    int i, c;
+    if (t.trans) {
+      i = e % t.rows;
+      c = e / t.rows;
+    } else {
+      c = e % t.chunks;
+      i = e / t.chunks;
+    }
+    u32x4_t w[kPlaneParts];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      unsigned short p[kPlaneParts][2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int k = 8 * c + 2 * h + q;
+        double x = 0.0;
+        if (k < t.kcols) {
+          const int sk = t.kmap ? t.kmap[k] : k;
+          if (sk >= 0) x = t.trans ? src[(int64_t)sk * t.lds + i] : src[(int64_t)i * t.lds + sk];
+        }
+        split3(x, p[0][q], p[1][q], p[2][q]);
+      }
+#pragma unroll
+      for (int pl = 0; pl < kPlaneParts; ++pl) w[pl][h] = (unsigned int)p[pl][0] | ((unsigned int)p[pl][1] << 16);
+    }
+    u32x4_t* d = reinterpret_cast<u32x4_t*>(t.dst + ((int64_t)i * t.chunks + c) * (kPlaneParts * 8));
+#pragma unroll
+    for (int pl = 0; pl < kPlaneParts; ++pl) d[pl] = w[pl];
+  }
+}
+
+void launch_split_planes(const SplitTask* tasks, int n, const GBases& b, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(split_planes_kernel, dim3(n), dim3(256), 0, s, tasks, b);
+  BSD_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- wave tiles on planes
+// Every wave owns one TW x TW output tile.  In a pass over 32 values of K the
+// lane (r, q) (r = lane % 16, q = lane / 16) loads chunk 4 pass + q of its A
+// rows and of its B columns; the identity operand is generated in registers.
+struct PSeg {
+  const uint16_t* A;
+  const uint16_t* B;
+  int64_t lda, ldb;  // in chunks
+  int K, flags;
+  double alpha;
+};
+
+__device__ __forceinline__ PSeg load_pseg(const GSeg* __restrict__ segs, int idx, const GBases& bases) {
+  const GSeg g = segs[idx];
+  PSeg w;
+  w.A = reinterpret_cast<const uint16_t*>(resolve((uint64_t)uni64((int64_t)g.A), bases));
+  w.B = reinterpret_cast<const uint16_t*>(resolve((uint64_t)uni64((int64_t)g.B), bases));
+  w.lda = uni64(g.lda);
+  w.ldb = uni64(g.ldb);
+  w.K = uni(g.K);
+  w.flags = uni(g.flags);
+  w.alpha = unid(g.alpha);
+  return w;
+}
+
+template <int NI, int NPL>
+__device__ __forceinline__ void load_ppass(const PSeg& sg, int pass, const bool* rowok, const int* gi,
+                                           const bool* colok, const int* gj, int q, u32x4_t (&a)[NI][NPL],
+                                           u32x4_t (&b)[NI][NPL]) {
+  const int c = 4 * pass + q;
+  const bool cok = 8 * c < sg.K;
+  const bool ia = sg.flags & kIdentA;
+  const u32x4_t zero = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    if (ia) {
+      // alpha I: the h part is 1.0 (bf16 0x3F80) where row == k
+      u32x4_t h = zero;
+      const int d = gi[i] - 8 * c;
+      if (rowok[i] && cok && d >= 0 && d < 8) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) h[w] = (d >> 1) == w ? (0x3F80u << (16 * (d & 1))) : 0u;
+      }
+      a[i][0] = h;
+#pragma unroll
+      for (int pl = 1; pl < NPL; ++pl) a[i][pl] = zero;
+    } else if (rowok[i] && cok) {
+      const u32x4_t* p = reinterpret_cast<const u32x4_t*>(sg.A + ((int64_t)gi[i] * sg.lda + c) * (kPlaneParts * 8));
+#pragma unroll
+      for (int pl = 0; pl < NPL; ++pl) a[i][pl] = p[pl];
+    } else {
+#pragma unroll
+      for (int pl = 0; pl < NPL; ++pl) a[i][pl] = zero;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NI; ++j) {
+    if (colok[j] && cok) {
+      const u32x4_t* p = reinterpret_cast<const u32x4_t*>(sg.B + ((int64_t)gj[j] * sg.ldb + c) * (kPlaneParts * 8));
+#pragma unroll
+      for (int pl = 0; pl < NPL; ++pl) b[j][pl] = p[pl];
+    } else {
+#pragma unroll
+      for (int pl = 0; pl < NPL; ++pl) b[j][pl] = zero;
+    }
+  }
+}
+
+__device__ __forceinline__ float4_t mfma_bf16(u32x4_t a, u32x4_t b, float4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a), __builtin_bit_cast(bf16x8_t, b), c,
+                                                 0, 0, 0);
+}
+
+// smallest products first; the identity has no m and l parts
+template <int NI, int NPL, int NPROD>
+__device__ __forceinline__ void planes_mfma(const u32x4_t (&a)[NI][NPL], const u32x4_t (&b)[NI][NPL],
+                                            float4_t (&t)[NI][NI], bool ident) {
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      float4_t c = t[i][j];
+      if (NPROD == 6) {
+        if (!ident) {
+          c = mfma_bf16(a[i][NPL - 1], b[j][0], c);
+          c = mfma_bf16(a[i][1], b[j][1], c);
+        }
+        c = mfma_bf16(a[i][0], b[j][NPL - 1], c);
+      }
+      if (!ident) c = mfma_bf16(a[i][1], b[j][0], c);
+      c = mfma_bf16(a[i][0], b[j][1], c);
+      c = mfma_bf16(a[i][0], b[j][0], c);
+      t[i][j] = c;
+    }
+}
+
+template <int TW, int NPROD>
+__global__ void __launch_bounds__(256)
+wave_planes_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __restrict__ segs, GBases bases) {
+  constexpr int NI = TW / 16;
+  constexpr int NPL = NPROD == 6 ? 3 : 2;  // parts read per operand
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int ti = uni(blockIdx.x * 4 + wave);
+  if (ti >= ntiles) return;
+  const GTile tile = tiles[ti];
+  const int M = uni(tile.M), N = uni(tile.N), m0 = uni(tile.m0), n0 = uni(tile.n0);
+  const int seg0 = uni(tile.seg0), nseg = uni(tile.nseg);
+  const int mt = min(TW, M - m0);
+  const int nt = min(TW, N - n0);
+  const int r16 = lane & 15, q = lane >> 4;
+  bool rowok[NI], colok[NI];
+  int gi[NI], gj[NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    rowok[i] = i * 16 + r16 < mt;
+    gi[i] = m0 + i * 16 + r16;
+    colok[i] = i * 16 + r16 < nt;
+    gj[i] = n0 + i * 16 + r16;
+  }
+  float4_t t[NI][NI];
+  double4_t acc[NI][NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) {
+      t[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+      acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    }
+
+  // software pipeline over the flattened (segment, pass) sequence
+  if (nseg > 0) {
+    int si = 0, pass = 0;
+    PSeg cur = load_pseg(segs, seg0, bases);
+    int cur_np = (cur.K + 31) / 32;
+    u32x4_t a[NI][NPL], b[NI][NPL], an[NI][NPL], bn[NI][NPL];
+    load_ppass<NI, NPL>(cur, 0, rowok, gi, colok, gj, q, a, b);
+    while (true) {
+      int nsi = si, npass = pass + 1;
+      PSeg nxt = cur;
+      bool more = true;
+      if (npass >= cur_np) {
+        nsi = si + 1;
+        npass = 0;
+        if (nsi < nseg) nxt = load_pseg(segs, seg0 + nsi, bases);
+        else more = false;
+      }
+      if (more) load_ppass<NI, NPL>(nxt, npass, rowok, gi, colok, gj, q, an, bn);
+      planes_mfma<NI, NPL, NPROD>(a, b, t, cur.flags & kIdentA);
+      if (npass == 0) {
+        // end of the current segment: scale by its alpha into float64
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+          for (int j = 0; j < NI; ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[i][j][v] += cur.alpha * (double)t[i][j][v];
+            t[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+          }
+      }
+      if (!more) break;
+      if (npass == 0) {
+        cur = nxt;
+        cur_np = (cur.K + 31) / 32;
+      }
+      si = nsi;
+      pass = npass;
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int pl = 0; pl < NPL; ++pl) {
+          a[i][pl] = an[i][pl];
+          b[i][pl] = bn[i][pl];
+        }
+    }
+  }
+  double* C = const_cast<double*>(resolve(tile.C, bases));
+  const double beta = tile.beta;
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        // bf16 16x16x32 output: accumulator register v of lane l holds row 4 (l / 16) + v
+        const int r = i * 16 + 4 * q + v;
+        const int c = j * 16 + r16;
+        if (r < mt && c < nt) {
+          double* p = C + (int64_t)r * tile.ldc + c;
+          double x = acc[i][j][v];
+          if (beta != 0.0) x += beta * (*p);
+          *p = x;
+        }
+      }
+}
+
+void launch_planes_gemm(const GTile* tiles, int ntiles, int shape, const GSeg* segs, const GBases& b,
+                        hipStream_t s, int precision) {
+  if (ntiles <= 0) return;
+  BSD_CHECK(shape == 4 || shape == 5, 1, "plane operands use wave tiles only");
+  BSD_CHECK(precision == 1 || precision == 2, 1, "plane operands are for split precision only");
+  const dim3 grid((ntiles + 3) / 4), block(256);
+  if (shape == 4) {
+    if (precision == 1) hipLaunchKernelGGL((wave_planes_kernel<16, 3>), grid, block, 0, s, tiles, ntiles, segs, b);
+    else hipLaunchKernelGGL((wave_planes_kernel<16, 6>), grid, block, 0, s, tiles, ntiles, segs, b);
+  } else {
+    if (precision == 1) hipLaunchKernelGGL((wave_planes_kernel<32, 3>), grid, block, 0, s, tiles, ntiles, segs, b);
+    else hipLaunchKernelGGL((wave_planes_kernel<32, 6>), grid, block, 0, s, tiles, ntiles, segs, b);
+  }
+  BSD_HIP(hipGetLastError());
+}
+
+}  // namespace bsd
