@@ -151,11 +151,11 @@ def main():
                 a[0] += t
                 a[1] += f
                 a[2] += 1
-        names = {0: "zero_fill_kernel", 1: "split_planes_kernel psi", 2: "split_planes_kernel V"}
+        names = {0: "zero_fill_kernel", 1: "split_planes_kernel psi"}
         for ph in (1, 2):
             for c, sh in shapes.items():
-                if c >= 4 and ph == 2 and prec:
-                    names[10 * ph + c] = f"wave_planes_kernel{sh[:-1]}, {3 * prec}> phase {ph}"
+                if c >= 4 and prec:
+                    names[10 * ph + c] = f"wave_planes_kernel{sh[:-1]}, {3 * prec}, {2 - ph}> phase {ph}"
                 elif c >= 4:
                     names[10 * ph + c] = f"wave_gemm_kernel{sh} phase {ph}"
                 else:

@@ -10,6 +10,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch first: it ships its own HIP runtime under the same soname as the one the
+# library is linked against, and whichever loads first serves the process.
+# Loading torch's keeps a single runtime that both torch and the library use.
+import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libbsdmrg.so")

@@ -472,7 +472,9 @@ void launch_split_reduce(const GReduce* red, int n, const GBases& b, hipStream_t
   BSD_HIP(hipGetLastError());
 }
 
-void GemmPlan::build(const std::vector<GemmProblem>& probs, bool wave_tiles, bool split_k, bool plane_operands) {
+void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts& opts) {
+  const bool wave_tiles = opts.wave_tiles, plane_operands = opts.plane_operands || opts.plane_output;
+  const bool split_k = opts.split_k && !opts.plane_output;
   // tile shape classes and the waves one tile of each class occupies
   const int TMs[kShapes] = {64, 32, 32, 64, 16, 32}, TNs[kShapes] = {64, 32, 64, 32, 16, 32};
   const int waves_per_tile[kShapes] = {4, 1, 2, 2, 1, 1};
@@ -524,7 +526,10 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, bool wave_tiles, boo
     for (int m0 = 0; m0 < p.M; m0 += TMs[cls])
       for (int n0 = 0; n0 < p.N; n0 += TNs[cls]) {
         GTile x;
-        x.C = p.C + (uint64_t)(((int64_t)m0 * p.ldc + n0) * (int64_t)sizeof(double));
+        // tile origin: element (m0, n0) of C, or of the planes of C^T (chunk m0 / 8 of row n0)
+        x.C = opts.plane_output
+                  ? p.C + (uint64_t)((((int64_t)n0 * p.ldc + m0 / 8) * kPlaneParts * 8) * (int64_t)sizeof(uint16_t))
+                  : p.C + (uint64_t)(((int64_t)m0 * p.ldc + n0) * (int64_t)sizeof(double));
         x.ldc = p.ldc;
         x.M = p.M;
         x.N = p.N;
@@ -538,6 +543,7 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, bool wave_tiles, boo
   }
   wave = wave_tiles || plane_operands;
   planes = plane_operands;
+  planes_out = opts.plane_output;
   // split long tiles into parts of about equal work: each part accumulates its
   // own contiguous run of segments into a workspace slot, and one reduction per
   // split tile adds the parts in a fixed order (deterministic results)
@@ -623,7 +629,7 @@ void GemmPlan::launch_shape_class(int c, const GBases& bases, hipStream_t s, int
   if (planes) {
     BSD_CHECK(precision != 0, 1, "plane-operand tile list launched at float64 precision");
     launch_planes_gemm(static_cast<const GTile*>(tiles.p) + first[c], count[c], c,
-                       static_cast<const GSeg*>(segs.p), bases, s, precision);
+                       static_cast<const GSeg*>(segs.p), bases, s, precision, planes_out);
     return;
   }
   BSD_CHECK(!(wave && count[4] + count[5] > 0 && precision != 0), 1, "float64 tile list launched at split precision");

@@ -387,26 +387,34 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     psi_poff[bi] = arena;
     arena += (int64_t)pb.cols * ((pb.rows + 7) / 8) * 8 * kPlaneParts;
   }
-  const int64_t ap_base = arena;
-  std::map<std::pair<const double*, bool>, int64_t> a_planes;   // (block, transposed) -> arena offset
-  std::vector<SplitTask> a_tasks;
-  auto a_plane = [&](const Operand2& o, int M, int K) -> int64_t {
-    auto key = std::make_pair(o.p, o.trans);
-    auto it = a_planes.find(key);
-    if (it != a_planes.end()) return it->second;
+  // psi row planes per right-sector stack, rows padded to the 8-row block starts
+  std::vector<int64_t> psir_off(nR, -1);
+  for (int r = 0; r < nR; ++r) {
+    if (lay.stack_rows[r] == 0) continue;
+    psir_off[r] = arena;
+    arena += (int64_t)lay.stack_prows[r] * ((Rb->basis.dim[r] + 7) / 8) * 8 * kPlaneParts;
+  }
+  // operator planes (left and right blocks), split once when the plan is built
+  std::map<std::pair<const double*, bool>, int64_t> op_planes;   // (block, transposed) -> arena offset
+  std::vector<SplitTask> op_tasks;
+  auto op_plane = [&](const double* p, int64_t ld, bool trans, int rows, int K) -> int64_t {
+    auto key = std::make_pair(p, trans);
+    auto it = op_planes.find(key);
+    if (it != op_planes.end()) return it->second;
     SplitTask t;
-    t.src = tag_ptr(0, (uint64_t)o.p);
-    t.lds = o.ld;
+    t.src = tag_ptr(0, (uint64_t)p);
+    t.lds = ld;
     t.kmap = nullptr;
+    t.rmap = nullptr;
     t.dst = reinterpret_cast<uint16_t*>((uintptr_t)(arena * 2));   // arena byte offset, fixed below
-    t.rows = M;
+    t.rows = rows;
     t.kcols = K;
     t.chunks = (K + 7) / 8;
-    t.trans = o.trans ? 1 : 0;
-    a_tasks.push_back(t);
-    a_planes[key] = arena;
+    t.trans = trans ? 1 : 0;
+    op_tasks.push_back(t);
+    op_planes[key] = arena;
     const int64_t at = arena;
-    arena += (int64_t)M * t.chunks * 8 * kPlaneParts;
+    arena += (int64_t)rows * t.chunks * 8 * kPlaneParts;
     return at;
   };
   double* V = static_cast<double*>(plan->V.p);
@@ -415,7 +423,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   plan->phase2.resize(nchunks);
   double useful = 0.0;
 
-  std::vector<std::vector<GemmProblem>> p1(nchunks);
+  std::vector<std::vector<GemmProblem>> p1(nchunks), p1s(nchunks);
   // per chunk, per output psi block: list of segments
   std::vector<std::map<int, GemmProblem>> p2(nchunks), p2s(nchunks);
   for (size_t ci = 0; ci < chans.size(); ++ci) {
@@ -446,6 +454,24 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
         gp.segs.push_back(sg);
         useful += 2.0 * gp.M * (double)gp.N * sg.K;
         p1[ck].push_back(std::move(gp));
+        // split precision: psi row planes times planes of R_b, stored as the
+        // planes of V^T (rows r', K = padded stack rows) that phase 2 reads
+        GemmProblem gs;
+        gs.C = tag_ptr(3, (uint64_t)(vi.poff[r2] * 2));
+        gs.ldc = lay.stack_prows[r] / 8;
+        gs.M = lay.stack_prows[r];
+        gs.N = Rb->basis.dim[r2];
+        gs.beta = 0.0;
+        GSeg sq;
+        sq.A = tag_ptr(3, (uint64_t)(psir_off[r] * 2));
+        sq.lda = (Rb->basis.dim[r] + 7) / 8;
+        sq.B = tag_ptr(3, (uint64_t)(op_plane(p, ld, ch.rtrans, Rb->basis.dim[r2], Rb->basis.dim[r]) * 2));
+        sq.ldb = (Rb->basis.dim[r] + 7) / 8;
+        sq.K = Rb->basis.dim[r];
+        sq.flags = 0;
+        sq.alpha = 1.0;
+        gs.segs.push_back(sq);
+        p1s[ck].push_back(std::move(gs));
       }
     }
     const int rpar = ch.rdq.parity();
@@ -498,7 +524,8 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
             sq.alpha = sg.alpha;
             sq.K = pb.rows;
             sq.flags = o.ident ? kIdentA : 0;
-            sq.A = o.ident ? tag_ptr(3, 0) : tag_ptr(3, (uint64_t)(a_plane(o, ob.rows, pb.rows) * 2));
+            sq.A = o.ident ? tag_ptr(3, 0)
+                           : tag_ptr(3, (uint64_t)(op_plane(o.p, o.ld, o.trans, ob.rows, pb.rows) * 2));
             sq.lda = (pb.rows + 7) / 8;
             if (ch.rkind == 1) {
               sq.B = tag_ptr(3, (uint64_t)(psi_poff[bi] * 2));
@@ -580,10 +607,15 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     plan->diag_plan->build(v, true);
   }
   plan->nseg = 0;
+  plan->phase1s.resize(nchunks);
   plan->phase2s.resize(nchunks);
   for (int k = 0; k < nchunks; ++k) {
     plan->phase1[k] = std::make_unique<GemmPlan>();
     plan->phase1[k]->build(p1[k], true);
+    GemmBuildOpts o1;
+    o1.plane_output = true;
+    plan->phase1s[k] = std::make_unique<GemmPlan>();
+    plan->phase1s[k]->build(p1s[k], o1);
     std::vector<GemmProblem> v, vs;
     for (auto& kv : p2[k]) {
       plan->nseg += kv.second.segs.size();
@@ -592,8 +624,10 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     for (auto& kv : p2s[k]) vs.push_back(std::move(kv.second));
     plan->phase2[k] = std::make_unique<GemmPlan>();
     plan->phase2[k]->build(v, true);
+    GemmBuildOpts o2;
+    o2.plane_operands = true;
     plan->phase2s[k] = std::make_unique<GemmPlan>();
-    plan->phase2s[k]->build(vs, true, true, true);
+    plan->phase2s[k]->build(vs, o2);
   }
 
   // ---------------------------------------------------------------- split tasks
@@ -621,6 +655,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     t.src = tag_ptr(1, (uint64_t)(pb.off * sizeof(double)));
     t.lds = pb.cols;
     t.kmap = nullptr;
+    t.rmap = nullptr;
     t.dst = ar + psi_poff[bi];
     t.rows = pb.cols;
     t.kcols = pb.rows;
@@ -628,42 +663,32 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     t.trans = 1;
     tasks.push_back(t);
   }
-  plan->n_split_psi = (int)tasks.size();
-  plan->split_v_first.assign(nchunks, 0);
-  plan->split_v_count.assign(nchunks, 0);
-  for (int k = 0; k < nchunks; ++k) {
-    plan->split_v_first[k] = (int)tasks.size();
-    for (size_t ci = 0; ci < chans.size(); ++ci) {
-      if (chunk_of[ci] != k || cgroups[ci].empty() || chans[ci].rkind != 0) continue;
-      const auto& vi = vinfo[ci];
-      for (int r2 = 0; r2 < nR; ++r2) {
-        if (vi.off[r2] < 0) continue;
-        const int r = vi.src[r2];
-        SplitTask t;
-        t.src = tag_ptr(0, (uint64_t)(V + vi.off[r2]));
-        t.lds = Rb->basis.dim[r2];
-        t.kmap = kmap_dev + kmap_off[r];
-        t.dst = ar + vi.poff[r2];
-        t.rows = Rb->basis.dim[r2];
-        t.kcols = lay.stack_prows[r];
-        t.chunks = lay.stack_prows[r] / 8;
-        t.trans = 1;
-        tasks.push_back(t);
-      }
-    }
-    plan->split_v_count[k] = (int)tasks.size() - plan->split_v_first[k];
+  for (int r = 0; r < nR; ++r) {
+    if (lay.stack_rows[r] == 0) continue;
+    SplitTask t;
+    t.src = tag_ptr(1, (uint64_t)(lay.stack_off[r] * sizeof(double)));
+    t.lds = Rb->basis.dim[r];
+    t.kmap = nullptr;
+    t.rmap = kmap_dev + kmap_off[r];
+    t.dst = ar + psir_off[r];
+    t.rows = lay.stack_prows[r];
+    t.kcols = Rb->basis.dim[r];
+    t.chunks = (Rb->basis.dim[r] + 7) / 8;
+    t.trans = 0;
+    tasks.push_back(t);
   }
+  plan->n_split_psi = (int)tasks.size();
   plan->split_tasks.reserve(std::max<size_t>(1, tasks.size()) * sizeof(SplitTask));
   if (!tasks.empty())
     BSD_HIP(hipMemcpy(plan->split_tasks.p, tasks.data(), tasks.size() * sizeof(SplitTask), hipMemcpyHostToDevice));
-  // L-operator planes: split once here
-  if (!a_tasks.empty()) {
-    for (auto& t : a_tasks) t.dst = ar + (int64_t)((uintptr_t)t.dst / 2);
+  // operator planes: split once here
+  if (!op_tasks.empty()) {
+    for (auto& t : op_tasks) t.dst = ar + (int64_t)((uintptr_t)t.dst / 2);
     DevBuf dt;
-    dt.reserve(a_tasks.size() * sizeof(SplitTask));
-    BSD_HIP(hipMemcpyAsync(dt.p, a_tasks.data(), a_tasks.size() * sizeof(SplitTask), hipMemcpyHostToDevice, s));
+    dt.reserve(op_tasks.size() * sizeof(SplitTask));
+    BSD_HIP(hipMemcpyAsync(dt.p, op_tasks.data(), op_tasks.size() * sizeof(SplitTask), hipMemcpyHostToDevice, s));
     GBases b0{{0, 0, 0, 0}};
-    launch_split_planes(static_cast<const SplitTask*>(dt.p), (int)a_tasks.size(), b0, s);
+    launch_split_planes(static_cast<const SplitTask*>(dt.p), (int)op_tasks.size(), b0, s);
     BSD_HIP(hipStreamSynchronize(s));
   }
   plan->useful_flops = useful;
@@ -678,8 +703,7 @@ static GBases hpsi_bases(const HpsiPlan& plan, const double* psi, double* out) {
 
 int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision, int cap,
                  double* ms, double* flops, int* kind) {
-  // kind: 0 zero-fill, 1 / 2 split of psi / of the phase-1 output into bf16
-  // planes, 10 + c phase-1 grouped GEMM with tile shape class c, 20 + c phase 2,
+  // kind: 0 zero-fill, 1 split of psi into bf16 planes, 10 + c phase-1 grouped GEMM with tile shape class c, 20 + c phase 2,
   // 10 + kShapes / 20 + kShapes the split-K reduction of phase 1 / phase 2
   std::vector<hipEvent_t> ev;
   std::vector<int> kinds;
@@ -705,14 +729,9 @@ int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream
   }
   for (size_t k = 0; k < plan.phase1.size(); ++k) {
     for (int ph = 1; ph <= 2; ++ph) {
-      if (ph == 2 && precision != 0 && plan.split_v_count[k] > 0) {
-        launch_split_planes(tasks + plan.split_v_first[k], plan.split_v_count[k], b, s);
-        kinds.push_back(2);
-        fl.push_back(0.0);
-        mark();
-      }
-      const GemmPlan& gp = ph == 1 ? *plan.phase1[k] : (precision == 0 ? *plan.phase2[k] : *plan.phase2s[k]);
-      const int prec = ph == 1 ? 0 : precision;
+      const GemmPlan& gp = precision == 0 ? (ph == 1 ? *plan.phase1[k] : *plan.phase2[k])
+                                          : (ph == 1 ? *plan.phase1s[k] : *plan.phase2s[k]);
+      const int prec = precision;
       for (int c = 0; c < kShapes; ++c) {
         if (gp.count[c] == 0) continue;
         gp.launch_shape_class(c, b, s, prec);
@@ -788,11 +807,11 @@ void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t 
   const SplitTask* tasks = static_cast<const SplitTask*>(plan.split_tasks.p);
   if (precision != 0) launch_split_planes(tasks, plan.n_split_psi, b, s);
   for (size_t k = 0; k < plan.phase1.size(); ++k) {
-    plan.phase1[k]->launch(b, s, 0);
     if (precision == 0) {
+      plan.phase1[k]->launch(b, s, 0);
       plan.phase2[k]->launch(b, s, 0);
     } else {
-      launch_split_planes(tasks + plan.split_v_first[k], plan.split_v_count[k], b, s);
+      plan.phase1s[k]->launch(b, s, precision);
       plan.phase2s[k]->launch(b, s, precision);
     }
   }

@@ -47,13 +47,13 @@ struct HpsiPlan {
   DevBuf agg, V;
   size_t agg_bytes = 0, v_bytes = 0;
   std::vector<std::unique_ptr<GemmPlan>> phase1, phase2;      // float64 tile lists
-  // split precision: phase 1 runs in float64, its output and psi are cut into
-  // bf16 planes (arena addressed through pointer tag 3), phase 2 on the planes
-  std::vector<std::unique_ptr<GemmPlan>> phase2s;
+  // split precision: psi is cut into bf16 planes, phase 1 multiplies them with
+  // the planes of the right operators and stores V^T as planes, phase 2 reads
+  // those and the planes of the left operators (arena addressed through tag 3)
+  std::vector<std::unique_ptr<GemmPlan>> phase1s, phase2s;
   DevBuf planes, kmaps, split_tasks;
   size_t plane_bytes = 0;
-  int n_split_psi = 0;                   // tasks [0, n_split_psi) split psi
-  std::vector<int> split_v_first, split_v_count;   // per chunk: tasks splitting V
+  int n_split_psi = 0;                   // split tasks for psi (run first in every product)
   std::unique_ptr<GemmPlan> diag_plan;   // diagonal of H_eff (rank-1 sector products)
   DevBuf ones, diag, dav_work;
   bool diag_ready = false;

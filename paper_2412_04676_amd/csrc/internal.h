@@ -296,6 +296,7 @@ struct SplitTask {
   uint64_t src;         // tagged float64 source
   int64_t lds;          // source leading dimension
   const int32_t* kmap;  // optional: plane column -> source column (-1 = zero)
+  const int32_t* rmap;  // optional: plane row -> source row (-1 = zero row)
   uint16_t* dst;
   int32_t rows, kcols;  // plane rows; plane columns (source K, or kmap length)
   int32_t chunks;       // chunks per plane row (>= ceil(kcols / 8))
@@ -303,12 +304,21 @@ struct SplitTask {
 };
 void launch_split_planes(const SplitTask* tasks, int n, const GBases& b, hipStream_t s);
 
+struct GemmBuildOpts {
+  bool wave_tiles = true;      // blocks up to 64 x 64 get wave tiles (float64 lists)
+  bool split_k = true;         // cut long tiles so that every launch fills the device
+  bool plane_operands = false; // A and B are split-bf16 planes (wave tiles for every size)
+  bool plane_output = false;   // C is written as split-bf16 planes of C^T (M a multiple of 8)
+};
+
 struct GemmPlan {
   int first[kShapes] = {0, 0, 0, 0, 0, 0}, count[kShapes] = {0, 0, 0, 0, 0, 0};
   bool wave = false;
   // planes: the segments' A and B point at split-bf16 planes (A rows of op(A),
-  // B rows of op(B)^T, lda / ldb in chunks); launched only at split precision
-  bool planes = false;
+  // B rows of op(B)^T, lda / ldb in chunks); launched only at split precision.
+  // planes_out: the result is stored as planes of C^T (row n of C^T = column n
+  // of C, ldc in chunks), the operand layout of a following planes product.
+  bool planes = false, planes_out = false;
   DevBuf tiles, segs;
   // split-K: parts of long tiles write workspace slots, summed by one reduction
   DevBuf parts, reduces;
@@ -317,8 +327,12 @@ struct GemmPlan {
   double shape_flops[kShapes] = {0, 0, 0, 0, 0, 0};
   // wave_tiles: small problems get wave tiles (the list is then float64 only);
   // split_k: cut long tiles into parts so that every launch fills the device
-  void build(const std::vector<GemmProblem>& probs, bool wave_tiles = true, bool split_k = true,
-             bool plane_operands = false);
+  void build(const std::vector<GemmProblem>& probs, const GemmBuildOpts& opts);
+  void build(const std::vector<GemmProblem>& probs, bool wave_tiles = true) {
+    GemmBuildOpts o;
+    o.wave_tiles = wave_tiles;
+    build(probs, o);
+  }
   // precision: 0 float64 MFMA, 1 split-bf16 (3 products), 2 split-bf16 (6 products)
   void launch(const GBases& bases, hipStream_t s, int precision = 0) const;
   void launch_shape_class(int c, const GBases& bases, hipStream_t s, int precision = 0) const;
@@ -344,7 +358,7 @@ void launch_grouped_gemm(const GTile* tiles, int ntiles, int shape, const GSeg* 
                          const GBases& b, hipStream_t s, int precision = 0);
 void launch_split_reduce(const GReduce* red, int n, const GBases& b, hipStream_t s);
 void launch_planes_gemm(const GTile* tiles, int ntiles, int shape, const GSeg* segs, const GBases& b,
-                        hipStream_t s, int precision);
+                        hipStream_t s, int precision, bool planes_out);
 
 // ---------------------------------------------------------------- serializer
 struct FamilyView {

@@ -41,6 +41,7 @@ split_planes_kernel(const SplitTask* __restrict__ tasks, GBases bases) {
       c = e % t.chunks;
       i = e / t.chunks;
     }
+    const int si = t.rmap ? t.rmap[i] : i;
     u32x4_t w[kPlaneParts];
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
@@ -49,9 +50,9 @@ split_planes_kernel(const SplitTask* __restrict__ tasks, GBases bases) {
       for (int q = 0; q < 2; ++q) {
         const int k = 8 * c + 2 * h + q;
         double x = 0.0;
-        if (k < t.kcols) {
+        if (k < t.kcols && si >= 0) {
           const int sk = t.kmap ? t.kmap[k] : k;
-          if (sk >= 0) x = t.trans ? src[(int64_t)sk * t.lds + i] : src[(int64_t)i * t.lds + sk];
+          if (sk >= 0) x = t.trans ? src[(int64_t)sk * t.lds + si] : src[(int64_t)si * t.lds + sk];
         }
         split3(x, p[0][q], p[1][q], p[2][q]);
       }
@@ -166,7 +167,10 @@ __device__ __forceinline__ void planes_mfma(const u32x4_t (&a)[NI][NPL], const u
     }
 }
 
-template <int TW, int NPROD>
+// OUTP 0: C is float64 (C = beta C + result).  OUTP 1: the result is split and
+// stored as planes of C^T: element (r, c) goes to row c, K index r; the four
+// rows 4 (lane / 16) + v a lane holds are four consecutive K values of one chunk.
+template <int TW, int NPROD, int OUTP>
 __global__ void __launch_bounds__(256)
 wave_planes_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __restrict__ segs, GBases bases) {
   constexpr int NI = TW / 16;
@@ -245,6 +249,28 @@ wave_planes_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __re
         }
     }
   }
+  if (OUTP == 1) {
+    // rows come in groups of 4 inside one chunk; mt is a multiple of 8
+    uint16_t* P = reinterpret_cast<uint16_t*>(const_cast<double*>(resolve(tile.C, bases)));
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        const int r = i * 16 + 4 * q;
+        const int c = j * 16 + r16;
+        if (r < mt && c < nt) {
+          unsigned short h[4], m[4], l[4];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) split3(acc[i][j][v], h[v], m[v], l[v]);
+          uint16_t* d = P + ((int64_t)c * tile.ldc + (r >> 3)) * (kPlaneParts * 8) + (r & 7);
+          typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+          *reinterpret_cast<u32x2_t*>(d) = u32x2_t{h[0] | ((unsigned)h[1] << 16), h[2] | ((unsigned)h[3] << 16)};
+          *reinterpret_cast<u32x2_t*>(d + 8) = u32x2_t{m[0] | ((unsigned)m[1] << 16), m[2] | ((unsigned)m[3] << 16)};
+          *reinterpret_cast<u32x2_t*>(d + 16) = u32x2_t{l[0] | ((unsigned)l[1] << 16), l[2] | ((unsigned)l[3] << 16)};
+        }
+      }
+    return;
+  }
   double* C = const_cast<double*>(resolve(tile.C, bases));
   const double beta = tile.beta;
 #pragma unroll
@@ -265,18 +291,27 @@ wave_planes_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __re
       }
 }
 
+template <int TW, int OUTP>
+static void launch_planes_tw(const GTile* tiles, int ntiles, const GSeg* segs, const GBases& b, hipStream_t s,
+                             int precision) {
+  const dim3 grid((ntiles + 3) / 4), block(256);
+  if (precision == 1)
+    hipLaunchKernelGGL((wave_planes_kernel<TW, 3, OUTP>), grid, block, 0, s, tiles, ntiles, segs, b);
+  else
+    hipLaunchKernelGGL((wave_planes_kernel<TW, 6, OUTP>), grid, block, 0, s, tiles, ntiles, segs, b);
+}
+
 void launch_planes_gemm(const GTile* tiles, int ntiles, int shape, const GSeg* segs, const GBases& b,
-                        hipStream_t s, int precision) {
+                        hipStream_t s, int precision, bool planes_out) {
   if (ntiles <= 0) return;
   BSD_CHECK(shape == 4 || shape == 5, 1, "plane operands use wave tiles only");
   BSD_CHECK(precision == 1 || precision == 2, 1, "plane operands are for split precision only");
-  const dim3 grid((ntiles + 3) / 4), block(256);
   if (shape == 4) {
-    if (precision == 1) hipLaunchKernelGGL((wave_planes_kernel<16, 3>), grid, block, 0, s, tiles, ntiles, segs, b);
-    else hipLaunchKernelGGL((wave_planes_kernel<16, 6>), grid, block, 0, s, tiles, ntiles, segs, b);
+    if (planes_out) launch_planes_tw<16, 1>(tiles, ntiles, segs, b, s, precision);
+    else launch_planes_tw<16, 0>(tiles, ntiles, segs, b, s, precision);
   } else {
-    if (precision == 1) hipLaunchKernelGGL((wave_planes_kernel<32, 3>), grid, block, 0, s, tiles, ntiles, segs, b);
-    else hipLaunchKernelGGL((wave_planes_kernel<32, 6>), grid, block, 0, s, tiles, ntiles, segs, b);
+    if (planes_out) launch_planes_tw<32, 1>(tiles, ntiles, segs, b, s, precision);
+    else launch_planes_tw<32, 0>(tiles, ntiles, segs, b, s, precision);
   }
   BSD_HIP(hipGetLastError());
 }

@@ -2,6 +2,8 @@
 and the two-site effective-Hamiltonian product against the dense definition
 P^T H P psi and against the block-sparse oracle (float64, relative 2-norm
 error <= 1e-10)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -180,3 +182,23 @@ def test_graph_replays_equal_eager_product():
         torch.cuda.synchronize()
         assert torch.equal(y, ref), k
     B.bsdmrg_destroy(ctx)
+
+
+def test_library_before_torch_keeps_one_hip_runtime():
+    # a process that calls the library before touching torch must still be able
+    # to use torch on the GPU afterwards (one HIP runtime per process)
+    import subprocess
+    import sys
+    code = ("import sys\n"
+            "sys.path[:0] = ['.', 'tests']\n"
+            "from paper_2412_04676_amd import bsdmrg as B\n"
+            "from gpu_helpers import build_system\n"
+            "ctx = build_system(6, 3, 3, 20, 2)[0]\n"
+            "B.bsdmrg_destroy(ctx)\n"
+            "import torch\n"
+            "x = torch.ones(4, device='cuda')\n"
+            "assert float(x.sum()) == 4.0\n"
+            "print('ok')\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=100)
+    assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
