@@ -92,6 +92,29 @@ def cpu_baseline(L, na, nb, D, site, useful_flops, budget_s=20.0):
                       "same useful flops per product as the GPU figure"}
 
 
+def measured_traffic(kernel_label):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain-copy calibration), or
+    None when the summary covers another kernel or its source has changed since."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "*_traffic.txt")):
+        kv = {}
+        with open(path) as f:
+            for line in f:
+                if "=" in line and not line.startswith("#"):
+                    k, v = line.strip().split("=", 1)
+                    kv[k] = v
+        if not kernel_label.startswith(kv.get("kernel", "\0")):
+            continue
+        src = os.path.join(os.path.dirname(os.path.abspath(__file__)), kv["source"])
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] != kv["source_sha256_16"]:
+                return None
+        return int(kv["bytes_per_launch"])
+    return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,11 +169,12 @@ def main():
         # dominant kernel: per-launch HIP events on the library's stream
         kinds = {}
         for _ in range(5):
-            for k, t, f in B.bsdmrg_hpsi_profile(ctx, site, x, y, prec, stream):
-                a = kinds.setdefault(k, [0.0, 0.0, 0])
+            for k, t, f, nb in B.bsdmrg_hpsi_profile(ctx, site, x, y, prec, stream):
+                a = kinds.setdefault(k, [0.0, 0.0, 0, 0.0])
                 a[0] += t
                 a[1] += f
                 a[2] += 1
+                a[3] += nb
         names = {0: "zero_fill_kernel", 1: "split_planes_kernel psi"}
         for ph in (1, 2):
             for c, sh in shapes.items():
@@ -165,7 +189,8 @@ def main():
         per = {names[k]: v[0] / v[2] for k, v in sorted(kinds.items())}
         log(f"bench: precision {prec}: H.psi {ms_:.3f} ms, {info['flops'] / (ms_ * 1e-3) / 1e12:.2f} TFLOP/s; "
             + ", ".join(f"{n}: {t:.3f} ms" for n, t in per.items()))
-        return ms_, out_, names[dom], kinds[dom][0] / kinds[dom][2], kinds[dom][1] / kinds[dom][2], per
+        n_dom = kinds[dom][2]
+        return (ms_, out_, names[dom], kinds[dom][0] / n_dom, kinds[dom][1] / n_dom, per, kinds[dom][3] / n_dom)
 
     res = {p: time_precision(p) for p in (B.FP64, B.BF16X3, B.BF16X6)}
     ref = res[B.FP64][1]
@@ -181,13 +206,28 @@ def main():
     # float64 product whose energy (Rayleigh quotient) moves by at most 1e-6 Eh
     ok = [p for p in res if errs[p] <= 1e-6 and de_rq[p] <= 1e-6]
     chosen = min(ok, key=lambda p: res[p][0])
-    ms, _, dname, t_dom, f_dom, per_launch = res[chosen]
+    ms, _, dname, t_dom, f_dom, per_launch, b_dom = res[chosen]
     tflops = info["flops"] / (ms * 1e-3) / 1e12
-    # algorithmic flops of the dominant kernel: the split-bf16 x6 product issues 6
-    # bf16 MFMA products per float64 multiply-add
-    mult = 6.0 if chosen == B.BF16X6 else 1.0
-    peak = BF16_MFMA_PEAK_TFLOPS if chosen == B.BF16X6 else FP64_MFMA_PEAK_TFLOPS
-    ach = mult * f_dom / (t_dom * 1e-3) / 1e12
+    # algorithmic flops of the dominant kernel: the split-bf16 products issue 3 or
+    # 6 bf16 MFMA products per float64 multiply-add
+    mult = {B.FP64: 1.0, B.BF16X3: 3.0, B.BF16X6: 6.0}[chosen]
+    peak_f = FP64_MFMA_PEAK_TFLOPS if chosen == B.FP64 else BF16_MFMA_PEAK_TFLOPS
+    ach_f = mult * f_dom / (t_dom * 1e-3) / 1e12
+    ach_b = b_dom / (t_dom * 1e-3) / 1e9
+    # the roof that bounds the kernel at its algorithmic intensity
+    intensity = mult * f_dom / b_dom
+    ridge = peak_f * 1e12 / (HBM_PEAK_GBS * 1e9)
+    traffic = measured_traffic(dname)
+    if intensity < ridge:
+        roof = {"bound": "hbm", "achieved": ach_b, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_b / HBM_PEAK_GBS}
+    else:
+        roof = {"bound": "mfma", "achieved": ach_f, "peak": peak_f, "unit": "TFLOP/s", "frac": ach_f / peak_f}
+    roof.update({"traffic": traffic, "kernel": dname, "kernel_ms": t_dom, "kernel_useful_flops": f_dom,
+                 "algorithmic_flops_per_useful_flop": mult, "algorithmic_bytes": b_dom,
+                 "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
+                 "mfma_tflops": ach_f, "mfma_peak": peak_f, "mfma_frac": ach_f / peak_f,
+                 "hbm_GBps": ach_b, "hbm_frac": ach_b / HBM_PEAK_GBS,
+                 "traffic_GBps": traffic / (t_dom * 1e-3) / 1e9 if traffic else None})
 
     # serializer and offload of the left environment block
     nbytes = B.bsdmrg_serialized_size(ctx, B.LEFT, site)
@@ -280,10 +320,7 @@ def main():
                               "d_rayleigh_Eh": de_rq[p], "per_launch_ms": res[p][5]}
                        for name, p in (("fp64", B.FP64), ("bf16x3", B.BF16X3), ("bf16x6", B.BF16X6))},
         "speedup_bf16x6_vs_fp64": res[B.FP64][0] / res[B.BF16X6][0],
-        "roofline": {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s",
-                     "frac": ach / peak, "traffic": None,
-                     "kernel": dname, "kernel_ms": t_dom, "kernel_useful_flops": f_dom,
-                     "algorithmic_flops_per_useful_flop": mult},
+        "roofline": roof,
         "site_step": {"davidson_iters": it_dav, "davidson_ms": t_dav * 1e3, "energy": e_dav,
                       "residual": r_dav, "truncate_ms": t_tr * 1e3, "kept": kept, "trunc_err": err_tr,
                       "renormalize_ms": t_ren * 1e3},

@@ -169,15 +169,17 @@ int bsdmrg_hpsi_info(bsdmrg_ctx* ctx, int site, int precision, double* flops, in
 
 /* One product as bsdmrg_hpsi with a HIP event between consecutive kernel
  * launches (synchronizing).  For launch i (i < cap) it returns the elapsed
- * milliseconds ms[i], the algorithmic flops flops[i] of that launch and its kind
+ * milliseconds ms[i], the algorithmic flops flops[i] of that launch, its
+ * algorithmic HBM bytes bytes[i] (every distinct operand block read once plus
+ * the output; bytes may be NULL) and its kind
  * kind[i] (0 output zero-fill; 10 + c phase-1 and 20 + c phase-2 grouped GEMM
  * with tile shape class c: 0 64x64, 1 32x32, 2 32x64, 3 64x32 workgroup tiles,
  * 4 16x16 and 5 32x32 wave tiles; 16 and 26 the reduction that sums the
  * split-K parts of phase 1 and phase 2).  Launches with no tiles are skipped.
  * *n_launches receives the number of launches. */
 int bsdmrg_hpsi_profile(bsdmrg_ctx* ctx, int site, const double* psi_dev, double* out_dev, int precision,
-                        bsdmrg_stream_t stream, int cap, double* ms, double* flops, int* kind,
-                        int* n_launches);
+                        bsdmrg_stream_t stream, int cap, double* ms, double* flops, double* bytes,
+                        int* kind, int* n_launches);
 
 /* Copy one renormalized block operator to the host (synchronizing).  kind is
  * one of 'H','c','A','B','S','P','Q' with spin-orbital indices p, q (-1 if

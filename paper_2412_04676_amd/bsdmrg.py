@@ -64,7 +64,7 @@ _SIGS = {
     "bsdmrg_hpsi": ([c_vp, c_int, c_vp, c_vp, c_int, c_vp], c_int),
     "bsdmrg_hpsi_info": ([c_vp, c_int, c_int, ctypes.POINTER(ctypes.c_double), c_i64p, c_i64p,
                           c_i64p, c_i64p], c_int),
-    "bsdmrg_hpsi_profile": ([c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_int, c_vp, c_vp, c_vp,
+    "bsdmrg_hpsi_profile": ([c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_int, c_vp, c_vp, c_vp, c_vp,
                              ctypes.POINTER(c_int)], c_int),
     "bsdmrg_davidson": ([c_vp, c_int, c_vp, c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_int),
                          ctypes.POINTER(ctypes.c_double), c_vp, c_int, c_vp], c_int),
@@ -198,14 +198,15 @@ def bsdmrg_hpsi_info(ctx, site, precision=FP64):
 
 
 def bsdmrg_hpsi_profile(ctx, site, psi_dev, out_dev, precision=FP64, stream=None, cap=256):
-    """Returns a list of (kind, ms, flops) per kernel launch of one product."""
+    """Returns a list of (kind, ms, flops, bytes) per kernel launch of one product."""
     ms = np.zeros(cap)
     fl = np.zeros(cap)
+    by = np.zeros(cap)
     kd = np.zeros(cap, dtype=np.int32)
     n = c_int()
     _check(_lib.bsdmrg_hpsi_profile(ctx, site, _ptr(psi_dev), _ptr(out_dev), precision, _stream(stream), cap,
-                                    _ptr(ms), _ptr(fl), _ptr(kd), ctypes.byref(n)))
-    return [(int(kd[i]), float(ms[i]), float(fl[i])) for i in range(min(n.value, cap))]
+                                    _ptr(ms), _ptr(fl), _ptr(by), _ptr(kd), ctypes.byref(n)))
+    return [(int(kd[i]), float(ms[i]), float(fl[i]), float(by[i])) for i in range(min(n.value, cap))]
 
 
 class DavOpts(ctypes.Structure):

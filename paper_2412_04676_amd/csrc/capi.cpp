@@ -366,14 +366,15 @@ int bsdmrg_hpsi(bsdmrg_ctx* ctx, int site, const double* psi, double* out, int p
 }
 
 int bsdmrg_hpsi_profile(bsdmrg_ctx* ctx, int site, const double* psi, double* out, int precision,
-                        bsdmrg_stream_t stream, int cap, double* ms, double* flops, int* kind, int* n) {
+                        bsdmrg_stream_t stream, int cap, double* ms, double* flops, double* bytes, int* kind,
+                        int* n) {
   return guard([&] {
     BSD_CHECK(ctx && psi && out && n && (cap <= 0 || (ms && flops && kind)), BSDMRG_EINVAL, "NULL argument");
     HpsiPlan* p = get_plan(ctx->c, site, precision, 0, S(stream), false);
     Block* Lb = get_block(ctx->c, true, site);
     Block* Rb = get_block(ctx->c, false, site + 2);
     BSD_CHECK(Lb && Rb && Lb->resident && Rb->resident, BSDMRG_EBUSY, "environment blocks not resident");
-    *n = profile_hpsi(*p, psi, out, S(stream), precision, cap, ms, flops, kind);
+    *n = profile_hpsi(*p, psi, out, S(stream), precision, cap, ms, flops, bytes, kind);
   });
 }
 

@@ -10,6 +10,7 @@
 #include "devutil.h"
 
 #include <algorithm>
+#include <set>
 
 namespace bsd {
 
@@ -489,7 +490,8 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
   std::vector<GSeg> sg;
   std::vector<double> segwork;
   flops = 0.0;
-  for (int c = 0; c < kShapes; ++c) shape_flops[c] = 0.0;
+  for (int c = 0; c < kShapes; ++c) shape_flops[c] = shape_in_elems[c] = shape_out_bytes[c] = 0.0;
+  std::set<uint64_t> seen_a[kShapes], seen_b[kShapes];
   for (const auto& p : probs) {
     if (p.M <= 0 || p.N <= 0) continue;
     int seg0 = (int)sg.size();
@@ -516,12 +518,17 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
       sg.push_back(s);
       segwork.push_back(s.K + 16.0);
       ktot += s.K + 16.0;
+      const double kk = plane_operands ? (s.K + 7) / 8 * 8.0 : (double)s.K;
       if (!(s.flags & kIdentA)) {
         double f = 2.0 * p.M * (double)p.N * s.K;
         flops += f;
         shape_flops[cls] += f;
+        if (seen_a[cls].insert(s.A).second) shape_in_elems[cls] += p.M * kk;
       }
+      if (seen_b[cls].insert(s.B).second) shape_in_elems[cls] += p.N * kk;
     }
+    shape_out_bytes[cls] += opts.plane_output ? (double)p.M * p.N * 2.0 * kPlaneParts
+                                              : (double)p.M * p.N * sizeof(double) * (p.beta != 0.0 ? 2 : 1);
     int nseg = (int)sg.size() - seg0;
     for (int m0 = 0; m0 < p.M; m0 += TMs[cls])
       for (int n0 = 0; n0 < p.N; n0 += TNs[cls]) {

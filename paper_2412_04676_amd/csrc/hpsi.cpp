@@ -702,12 +702,12 @@ static GBases hpsi_bases(const HpsiPlan& plan, const double* psi, double* out) {
 }
 
 int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision, int cap,
-                 double* ms, double* flops, int* kind) {
+                 double* ms, double* flops, double* bytes, int* kind) {
   // kind: 0 zero-fill, 1 split of psi into bf16 planes, 10 + c phase-1 grouped GEMM with tile shape class c, 20 + c phase 2,
   // 10 + kShapes / 20 + kShapes the split-K reduction of phase 1 / phase 2
   std::vector<hipEvent_t> ev;
   std::vector<int> kinds;
-  std::vector<double> fl;
+  std::vector<double> fl, by;
   auto mark = [&]() {
     hipEvent_t e;
     BSD_HIP(hipEventCreate(&e));
@@ -720,11 +720,13 @@ int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream
   zero_fill(out, plan.lay.n_elems, s);
   kinds.push_back(0);
   fl.push_back(0.0);
+  by.push_back(8.0 * plan.lay.n_elems);
   mark();
   if (precision != 0 && plan.n_split_psi > 0) {
     launch_split_planes(tasks, plan.n_split_psi, b, s);
     kinds.push_back(1);
     fl.push_back(0.0);
+    by.push_back(plan.lay.n_elems * (8.0 + 2.0 * 2 * kPlaneParts));   // psi read, two plane copies written
     mark();
   }
   for (size_t k = 0; k < plan.phase1.size(); ++k) {
@@ -737,12 +739,14 @@ int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream
         gp.launch_shape_class(c, b, s, prec);
         kinds.push_back(10 * ph + c);
         fl.push_back(gp.shape_flops[c]);
+        by.push_back(gp.algo_bytes(c, prec));
         mark();
       }
       if (gp.nreduce > 0) {
         gp.launch_reduce(b, s);
         kinds.push_back(10 * ph + kShapes);
         fl.push_back(0.0);
+        by.push_back(0.0);
         mark();
       }
     }
@@ -754,6 +758,7 @@ int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream
     BSD_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
     ms[i] = t;
     flops[i] = fl[i];
+    if (bytes) bytes[i] = by[i];
     kind[i] = kinds[i];
   }
   for (auto e : ev) (void)hipEventDestroy(e);

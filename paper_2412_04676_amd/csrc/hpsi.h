@@ -70,7 +70,7 @@ void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t 
 // this (psi, out, precision); kernels only, no memset nodes)
 void run_hpsi_graph(HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision = 0);
 int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision, int cap,
-                 double* ms, double* flops, int* kind);
+                 double* ms, double* flops, double* bytes, int* kind);
 void zero_fill(double* p, int64_t n, hipStream_t s);
 // diagonal of H_eff into the plan's own buffer (computed once per plan)
 const double* hpsi_diagonal(HpsiPlan& plan, hipStream_t s);

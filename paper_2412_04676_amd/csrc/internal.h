@@ -325,6 +325,13 @@ struct GemmPlan {
   int nreduce = 0;
   double flops = 0.0;                       // useful flops (2 M N K over non-identity segments)
   double shape_flops[kShapes] = {0, 0, 0, 0, 0, 0};
+  // algorithmic HBM traffic per shape class: distinct operand blocks read once
+  // (float64 values, or values per bf16 part for plane operands) and the output
+  double shape_in_elems[kShapes] = {0, 0, 0, 0, 0, 0}, shape_out_bytes[kShapes] = {0, 0, 0, 0, 0, 0};
+  double algo_bytes(int c, int precision) const {
+    const double per = planes ? 2.0 * (precision == 1 ? 2 : kPlaneParts) : 8.0;
+    return shape_in_elems[c] * per + shape_out_bytes[c];
+  }
   // wave_tiles: small problems get wave tiles (the list is then float64 only);
   // split_k: cut long tiles into parts so that every launch fills the device
   void build(const std::vector<GemmProblem>& probs, const GemmBuildOpts& opts);

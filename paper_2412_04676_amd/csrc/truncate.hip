@@ -17,7 +17,15 @@
 namespace bsd {
 
 // One workgroup per sector.  G (m x m, ld m, m even) is overwritten by its
-// eigenvalues on the diagonal, V (m x m) receives the eigenvectors as columns.
+// eigenvalues on the diagonal, V (m x m) receives the eigenvectors as rows.
+//
+// Cyclic parallel Jacobi: a sweep is m - 1 rounds of the round-robin pairing,
+// each round rotates m / 2 disjoint index pairs (p, q) at once.  With the
+// rotations R_k fixed, the update R^T A R of the symmetric matrix splits into
+// independent 2 x 2 blocks, one per pair of pairs (k1, k2), so a round is one
+// pass after the rotation angles: a wave takes the two rows (p1, q1) of pair
+// k1 and its lanes the column pairs k2 (accesses stay inside two rows), and
+// the eigenvector rows p, q rotate with lanes along the row.  No divisions.
 __global__ void __launch_bounds__(1024)
 jacobi_kernel(const int64_t* __restrict__ goff, const int* __restrict__ dims, double* __restrict__ G,
               double* __restrict__ V, int max_sweeps) {
@@ -26,35 +34,37 @@ jacobi_kernel(const int64_t* __restrict__ goff, const int* __restrict__ dims, do
   double* Z = V + goff[blockIdx.x];
   __shared__ double cs[512], sn[512];
   __shared__ int pp[512], qq[512];
-  __shared__ double red[1024];
+  __shared__ double red[2][32];
   const int t = threadIdx.x, nt = blockDim.x;
-  for (int64_t e = t; e < (int64_t)m * m; e += nt) Z[e] = ((e / m) == (e % m)) ? 1.0 : 0.0;
+  const int wave = t >> 6, lane = t & 63, nw = nt >> 6;
+  for (int i = wave; i < m; i += nw)
+    for (int j = lane; j < m; j += 64) Z[(int64_t)i * m + j] = i == j ? 1.0 : 0.0;
   __syncthreads();
   if (m < 2) return;
   const int half = m / 2;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     // convergence: off-diagonal norm against the diagonal norm
     double o = 0.0, d = 0.0;
-    for (int64_t e = t; e < (int64_t)m * m; e += nt) {
-      const double v = A[e];
-      if ((e / m) == (e % m)) d += v * v;
-      else o += v * v;
+    for (int i = wave; i < m; i += nw)
+      for (int j = lane; j < m; j += 64) {
+        const double v = A[(int64_t)i * m + j];
+        if (i == j) d += v * v;
+        else o += v * v;
+      }
+    for (int w = 32; w > 0; w >>= 1) {
+      o += __shfl_xor(o, w);
+      d += __shfl_xor(d, w);
     }
-    red[t] = o;
-    __syncthreads();
-    for (int s = nt / 2; s > 0; s >>= 1) {
-      if (t < s) red[t] += red[t + s];
-      __syncthreads();
+    if (lane == 0) {
+      red[0][wave] = o;
+      red[1][wave] = d;
     }
-    const double off = red[0];
     __syncthreads();
-    red[t] = d;
-    __syncthreads();
-    for (int s = nt / 2; s > 0; s >>= 1) {
-      if (t < s) red[t] += red[t + s];
-      __syncthreads();
+    double off = 0.0, dia = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      off += red[0][w];
+      dia += red[1][w];
     }
-    const double dia = red[0];
     __syncthreads();
     if (off <= 1e-32 * dia || off == 0.0) break;
     for (int r = 0; r < m - 1; ++r) {
@@ -64,11 +74,13 @@ jacobi_kernel(const int64_t* __restrict__ goff, const int* __restrict__ dims, do
           p = r;
           q = m - 1;
         } else {
-          p = (r + k) % (m - 1);
-          q = (r - k + (m - 1)) % (m - 1);
+          p = r + k;
+          if (p >= m - 1) p -= m - 1;
+          q = r - k;
+          if (q < 0) q += m - 1;
         }
         if (p > q) {
-          int x = p;
+          const int x = p;
           p = q;
           q = x;
         }
@@ -86,29 +98,37 @@ jacobi_kernel(const int64_t* __restrict__ goff, const int* __restrict__ dims, do
         qq[k] = q;
       }
       __syncthreads();
-      // rows p, q
-      for (int64_t e = t; e < (int64_t)half * m; e += nt) {
-        const int k = (int)(e / m), j = (int)(e % m);
-        const double c = cs[k], s = sn[k];
-        if (s == 0.0) continue;
-        const int p = pp[k], q = qq[k];
-        const double ap = A[(int64_t)p * m + j], aq = A[(int64_t)q * m + j];
-        A[(int64_t)p * m + j] = c * ap - s * aq;
-        A[(int64_t)q * m + j] = s * ap + c * aq;
+      // blocks (k1, k2): B' = R1^T B R2 with R = [[c, s], [-s, c]] on (p, q)
+      for (int k1 = wave; k1 < half; k1 += nw) {
+        const double c1 = cs[k1], s1 = sn[k1];
+        const int p1 = pp[k1], q1 = qq[k1];
+        double* rp = A + (int64_t)p1 * m;
+        double* rq = A + (int64_t)q1 * m;
+        for (int k2 = lane; k2 < half; k2 += 64) {
+          const double c2 = cs[k2], s2 = sn[k2];
+          if (s1 == 0.0 && s2 == 0.0) continue;
+          const int p2 = pp[k2], q2 = qq[k2];
+          const double b00 = rp[p2], b01 = rp[q2], b10 = rq[p2], b11 = rq[q2];
+          const double t00 = c1 * b00 - s1 * b10, t01 = c1 * b01 - s1 * b11;
+          const double t10 = s1 * b00 + c1 * b10, t11 = s1 * b01 + c1 * b11;
+          const bool diag = k1 == k2;   // the rotated pair itself is diagonalized
+          rp[p2] = c2 * t00 - s2 * t01;
+          rp[q2] = diag ? 0.0 : s2 * t00 + c2 * t01;
+          rq[p2] = diag ? 0.0 : c2 * t10 - s2 * t11;
+          rq[q2] = s2 * t10 + c2 * t11;
+        }
       }
-      __syncthreads();
-      // columns p, q and eigenvectors
-      for (int64_t e = t; e < (int64_t)half * m; e += nt) {
-        const int k = (int)(e / m), j = (int)(e % m);
+      // eigenvector rows p, q
+      for (int k = wave; k < half; k += nw) {
         const double c = cs[k], s = sn[k];
         if (s == 0.0) continue;
-        const int p = pp[k], q = qq[k];
-        const double ap = A[(int64_t)j * m + p], aq = A[(int64_t)j * m + q];
-        A[(int64_t)j * m + p] = c * ap - s * aq;
-        A[(int64_t)j * m + q] = s * ap + c * aq;
-        const double zp = Z[(int64_t)j * m + p], zq = Z[(int64_t)j * m + q];
-        Z[(int64_t)j * m + p] = c * zp - s * zq;
-        Z[(int64_t)j * m + q] = s * zp + c * zq;
+        double* zp = Z + (int64_t)pp[k] * m;
+        double* zq = Z + (int64_t)qq[k] * m;
+        for (int i = lane; i < m; i += 64) {
+          const double a = zp[i], b = zq[i];
+          zp[i] = c * a - s * b;
+          zq[i] = s * a + c * b;
+        }
       }
       __syncthreads();
     }
@@ -306,14 +326,14 @@ TruncResult truncate_psi(Ctx& ctx, const HpsiPlan& plan, const double* psi, int 
         tb.data.resize((size_t)d * kc.size());
         for (int i = 0; i < d; ++i)
           for (size_t j = 0; j < kc.size(); ++j)
-            tb.data[i * kc.size() + j] = Vh[x.goff + (int64_t)(offs[a] + i) * x.m + kc[j]];
+            tb.data[i * kc.size() + j] = Vh[x.goff + (int64_t)kc[j] * x.m + offs[a] + i];
       } else {
         tb.ql = x.qm;   // left bond label of site+1 is the middle sector
         tb.rows = (int)kc.size();
         tb.cols = d;
         tb.data.resize((size_t)d * kc.size());
         for (size_t j = 0; j < kc.size(); ++j)
-          for (int i = 0; i < d; ++i) tb.data[j * d + i] = Vh[x.goff + (int64_t)(offs[a] + i) * x.m + kc[j]];
+          for (int i = 0; i < d; ++i) tb.data[j * d + i] = Vh[x.goff + (int64_t)kc[j] * x.m + offs[a] + i];
       }
       res.blocks.push_back(std::move(tb));
     }
