@@ -8,7 +8,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libbsdmrg.so")
 SOURCES = ["algebra.cpp", "blocks.cpp", "hpsi.cpp", "capi.cpp", "gemm.hip", "planes.hip", "serializer.hip", "davidson.hip", "truncate.hip"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wno-unused-result", "-I" + os.path.join(os.path.dirname(HERE), "include")]
 
 

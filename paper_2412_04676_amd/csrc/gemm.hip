@@ -533,9 +533,10 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
     for (int m0 = 0; m0 < p.M; m0 += TMs[cls])
       for (int n0 = 0; n0 < p.N; n0 += TNs[cls]) {
         GTile x;
-        // tile origin: element (m0, n0) of C, or of the planes of C^T (chunk m0 / 8 of row n0)
+        // tile origin: element (m0, n0) of C, or of the planes of C^T (row n0, chunk m0 / 8;
+        // n0 is a multiple of 8, so the tile's rows start a row group)
         x.C = opts.plane_output
-                  ? p.C + (uint64_t)((((int64_t)n0 * p.ldc + m0 / 8) * kPlaneParts * 8) * (int64_t)sizeof(uint16_t))
+                  ? p.C + (uint64_t)(plane_off(n0, m0 / 8, 0, p.ldc) * (int64_t)sizeof(uint16_t))
                   : p.C + (uint64_t)(((int64_t)m0 * p.ldc + n0) * (int64_t)sizeof(double));
         x.ldc = p.ldc;
         x.M = p.M;
@@ -615,6 +616,36 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
       all.push_back(u.first.t);
       slot.push_back(u.second);
     }
+  }
+  if (plane_operands) {
+    // one step per pass of 32 K values; split-K cuts above fall on segment
+    // boundaries, so every unit starts fresh and ends with a flush
+    BSD_CHECK(slot.size() == all.size(), 1, "tile bookkeeping");
+    std::vector<GSeg> steps;
+    std::vector<int> first_step(sg.size() + 1);
+    for (size_t si = 0; si < sg.size(); ++si) {
+      first_step[si] = (int)steps.size();
+      const GSeg& g = sg[si];
+      BSD_CHECK((g.A >> kTagShift) == 0 && (g.B >> kTagShift) == 0, 1, "plane operands must be absolute addresses");
+      const int npass = (g.K + 31) / 32;
+      for (int p = 0; p < npass; ++p) {
+        GSeg x = g;
+        x.K = g.K - 32 * p;
+        x.flags = (g.flags & kIdentA) | (p == 0 ? kStepFresh : 0) | (p == npass - 1 ? kStepEnd : 0) |
+                  (p << kStepPassShift);
+        const uint64_t adv = (uint64_t)p * 4 * kPlaneParts * 64 * sizeof(uint16_t);
+        if (!(g.flags & kIdentA)) x.A += adv;
+        x.B += adv;
+        steps.push_back(x);
+      }
+    }
+    first_step[sg.size()] = (int)steps.size();
+    for (auto& x : all) {
+      const int a = first_step[x.seg0], b = first_step[x.seg0 + x.nseg];
+      x.seg0 = a;
+      x.nseg = b - a;
+    }
+    sg.swap(steps);
   }
   if (ws_elems > 0) parts.reserve(ws_elems * sizeof(double));
   double* ws = static_cast<double*>(parts.p);

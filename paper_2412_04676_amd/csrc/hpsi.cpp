@@ -345,7 +345,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
         vi.poff[r2] = needp;
         vi.src[r2] = r;
         need += ((int64_t)lay.stack_rows[r] * Rb->basis.dim[r2] + 1) / 2 * 2;
-        needp += (int64_t)Rb->basis.dim[r2] * lay.stack_prows[r] * kPlaneParts;
+        needp += plane_elems(Rb->basis.dim[r2], lay.stack_prows[r] / 8);
       }
       if (need == 0) {
         cgroups[ci].clear();
@@ -385,14 +385,14 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   for (size_t bi = 0; bi < lay.blocks.size(); ++bi) {
     const PsiBlk& pb = lay.blocks[bi];
     psi_poff[bi] = arena;
-    arena += (int64_t)pb.cols * ((pb.rows + 7) / 8) * 8 * kPlaneParts;
+    arena += plane_elems(pb.cols, (pb.rows + 7) / 8);
   }
   // psi row planes per right-sector stack, rows padded to the 8-row block starts
   std::vector<int64_t> psir_off(nR, -1);
   for (int r = 0; r < nR; ++r) {
     if (lay.stack_rows[r] == 0) continue;
     psir_off[r] = arena;
-    arena += (int64_t)lay.stack_prows[r] * ((Rb->basis.dim[r] + 7) / 8) * 8 * kPlaneParts;
+    arena += plane_elems(lay.stack_prows[r], (Rb->basis.dim[r] + 7) / 8);
   }
   // operator planes (left and right blocks), split once when the plan is built
   std::map<std::pair<const double*, bool>, int64_t> op_planes;   // (block, transposed) -> arena offset
@@ -414,7 +414,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     op_tasks.push_back(t);
     op_planes[key] = arena;
     const int64_t at = arena;
-    arena += (int64_t)rows * t.chunks * 8 * kPlaneParts;
+    arena += plane_elems(rows, t.chunks);
     return at;
   };
   double* V = static_cast<double*>(plan->V.p);
@@ -531,7 +531,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
               sq.B = tag_ptr(3, (uint64_t)(psi_poff[bi] * 2));
               sq.ldb = (pb.rows + 7) / 8;
             } else {
-              const int64_t e = vi.poff[r2] + (int64_t)(pb.prow_in_stack / 8) * 8 * kPlaneParts;
+              const int64_t e = vi.poff[r2] + plane_off(0, pb.prow_in_stack / 8, 0, lay.stack_prows[pb.r] / 8);
               sq.B = tag_ptr(3, (uint64_t)(e * 2));
               sq.ldb = lay.stack_prows[pb.r] / 8;
             }
@@ -606,6 +606,28 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     plan->diag_plan = std::make_unique<GemmPlan>();
     plan->diag_plan->build(v, true);
   }
+  // plane arena: allocate now and turn arena offsets (tag 3) into absolute
+  // addresses, which the plane kernels read through buffer descriptors
+  plan->plane_bytes = (size_t)arena * 2;
+  plan->planes.reserve(std::max<size_t>(16, plan->plane_bytes));
+  const uint64_t arena_base = (uint64_t)(uintptr_t)plan->planes.p;
+  auto absolute = [&](uint64_t t) {
+    return (t >> kTagShift) == 3 ? tag_ptr(0, arena_base + (t & ((1ull << kTagShift) - 1))) : t;
+  };
+  for (int k = 0; k < nchunks; ++k) {
+    for (auto& gp : p1s[k]) {
+      gp.C = absolute(gp.C);
+      for (auto& sg : gp.segs) {
+        sg.A = absolute(sg.A);
+        sg.B = absolute(sg.B);
+      }
+    }
+    for (auto& kv : p2s[k])
+      for (auto& sg : kv.second.segs) {
+        sg.A = absolute(sg.A);
+        sg.B = absolute(sg.B);
+      }
+  }
   plan->nseg = 0;
   plan->phase1s.resize(nchunks);
   plan->phase2s.resize(nchunks);
@@ -645,8 +667,6 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   if (!kmap.empty())
     BSD_HIP(hipMemcpy(plan->kmaps.p, kmap.data(), kmap.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   const int32_t* kmap_dev = static_cast<const int32_t*>(plan->kmaps.p);
-  plan->plane_bytes = (size_t)arena * 2;
-  plan->planes.reserve(std::max<size_t>(16, plan->plane_bytes));
   uint16_t* ar = static_cast<uint16_t*>(plan->planes.p);
   std::vector<SplitTask> tasks;
   for (size_t bi = 0; bi < lay.blocks.size(); ++bi) {

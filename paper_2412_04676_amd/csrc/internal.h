@@ -238,6 +238,12 @@ struct Block {
 constexpr int kTagShift = 56;
 inline uint64_t tag_ptr(int cls, uint64_t off) { return ((uint64_t)cls << kTagShift) | off; }
 enum { kTransA = 1, kTransB = 2, kIdentA = 4 };
+// Plane-operand lists are expanded into steps of one pass (32 values of K):
+// a step's A and B point at its first chunk, K counts the values left from
+// there, flags carry kIdentA, kStepFresh (first pass of its segment: start a
+// new sum), kStepEnd (last pass: add alpha times the sum into the tile) and,
+// from bit kStepPassShift on, the pass index (for the identity operand).
+enum { kStepFresh = 8, kStepEnd = 16, kStepPassShift = 8 };
 
 struct GSeg {
   uint64_t A, B;
@@ -286,12 +292,18 @@ struct GemmProblem {
 constexpr int kShapes = 6;
 // Split-bf16 operand planes.  A float64 matrix X (rows x K) is stored once as
 // bf16 parts X ~ h + m + l (h = bf16(X), m = bf16(X - h), l = bf16(X - h - m)),
-// laid out for the MFMA operand fetch: each row is cut into ceil(K / 8) chunks
-// of 8 consecutive K values and a chunk keeps its three parts side by side
-// (48 bytes), so element (i, k, part p) sits at
-//   ((i * chunks + k / 8) * 3 + p) * 8 + k % 8.
-// Values past K (and columns that kmap sends to -1) are zero.
+// laid out for the MFMA operand fetch: K is cut into chunks of 8 consecutive
+// values, rows into groups of 8, and one (row group, chunk, part) is a 128-byte
+// line holding the 8 x 8 values row by row:
+//   element (i, k, part p) at (((i / 8) * chunks + k / 8) * 3 + p) * 64 + (i % 8) * 8 + k % 8.
+// An MFMA operand load (16 rows x 4 chunks, 16 bytes per lane) then reads 8
+// whole lines.  Values past K (and columns that kmap sends to -1) are zero;
+// rows are padded to a multiple of 8 (padding rows are never read).
 constexpr int kPlaneParts = 3;
+__host__ __device__ inline int64_t plane_off(int i, int c, int p, int64_t chunks) {
+  return ((((int64_t)(i >> 3) * chunks + c) * kPlaneParts + p) << 6) + ((i & 7) << 3);
+}
+inline int64_t plane_elems(int rows, int chunks) { return (int64_t)((rows + 7) / 8) * chunks * kPlaneParts * 64; }
 struct SplitTask {
   uint64_t src;         // tagged float64 source
   int64_t lds;          // source leading dimension

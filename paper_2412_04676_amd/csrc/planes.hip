@@ -25,7 +25,7 @@ __device__ __forceinline__ void split3(double x, unsigned short& h, unsigned sho
   l = bf16_rne((float)r2);
 }
 
-// one workgroup per task; each thread writes whole chunks (3 x 16 bytes)
+// one workgroup per task; each thread writes one row of one chunk in all parts
 __global__ void __launch_bounds__(256)
 split_planes_kernel(const SplitTask* __restrict__ tasks, GBases bases) {
   const SplitTask t = tasks[blockIdx.x];
@@ -59,9 +59,9 @@ split_planes_kernel(const SplitTask* __restrict__ tasks, GBases bases) {
 #pragma unroll
       for (int pl = 0; pl < kPlaneParts; ++pl) w[pl][h] = (unsigned int)p[pl][0] | ((unsigned int)p[pl][1] << 16);
     }
-    u32x4_t* d = reinterpret_cast<u32x4_t*>(t.dst + ((int64_t)i * t.chunks + c) * (kPlaneParts * 8));
 #pragma unroll
-    for (int pl = 0; pl < kPlaneParts; ++pl) d[pl] = w[pl];
+    for (int pl = 0; pl < kPlaneParts; ++pl)
+      *reinterpret_cast<u32x4_t*>(t.dst + plane_off(i, c, pl, t.chunks)) = w[pl];
   }
 }
 
@@ -75,67 +75,103 @@ void launch_split_planes(const SplitTask* tasks, int n, const GBases& b, hipStre
 // Every wave owns one TW x TW output tile.  In a pass over 32 values of K the
 // lane (r, q) (r = lane % 16, q = lane / 16) loads chunk 4 pass + q of its A
 // rows and of its B columns; the identity operand is generated in registers.
+//
+// Operands arrive through buffer loads: A and B of a segment are absolute
+// plane addresses, every lane keeps 32-bit byte offsets of its rows, and a
+// lane outside the tile or past K gets an offset beyond the buffer, which the
+// hardware answers with zeros (no branches around loads).  Descriptors are
+// read with scalar loads.  Two operand sets alternate (load the next pass
+// into one while the MFMAs run on the other).
+typedef __attribute__((address_space(4))) const GSeg* cseg_ptr;
+typedef __attribute__((address_space(4))) const GTile* ctile_ptr;
+
+// member-wise reads through the constant address space (scalar loads for
+// wave-uniform indices)
+__device__ __forceinline__ GSeg ld_seg(cseg_ptr p, int i) {
+  GSeg g;
+  g.A = p[i].A;
+  g.B = p[i].B;
+  g.lda = p[i].lda;
+  g.ldb = p[i].ldb;
+  g.K = p[i].K;
+  g.flags = p[i].flags;
+  g.alpha = p[i].alpha;
+  return g;
+}
+__device__ __forceinline__ GTile ld_tile(ctile_ptr p, int i) {
+  GTile t;
+  t.C = p[i].C;
+  t.ldc = p[i].ldc;
+  t.M = p[i].M;
+  t.N = p[i].N;
+  t.m0 = p[i].m0;
+  t.n0 = p[i].n0;
+  t.seg0 = p[i].seg0;
+  t.nseg = p[i].nseg;
+  t.beta = p[i].beta;
+  return t;
+}
+constexpr unsigned kBufOut = 0x80000000u;    // byte offset past every plane buffer
+constexpr int kBufFlags = 0x00020000;        // raw buffer, 32-bit data
+
 struct PSeg {
-  const uint16_t* A;
-  const uint16_t* B;
-  int64_t lda, ldb;  // in chunks
-  int K, flags;
+  __amdgpu_buffer_rsrc_t ra, rb;
+  int lda, ldb;      // chunks per row group
+  int nch;           // chunks of K left from this step (0: empty step)
+  int kbase;         // first K index of the step (identity operand)
+  bool ident, fresh, end;
   double alpha;
 };
 
-__device__ __forceinline__ PSeg load_pseg(const GSeg* __restrict__ segs, int idx, const GBases& bases) {
-  const GSeg g = segs[idx];
+// valid = false gives an empty step (its loads return zeros, nothing flushes)
+__device__ __forceinline__ PSeg decode_step(const GSeg& g, bool valid) {
   PSeg w;
-  w.A = reinterpret_cast<const uint16_t*>(resolve((uint64_t)uni64((int64_t)g.A), bases));
-  w.B = reinterpret_cast<const uint16_t*>(resolve((uint64_t)uni64((int64_t)g.B), bases));
-  w.lda = uni64(g.lda);
-  w.ldb = uni64(g.ldb);
-  w.K = uni(g.K);
-  w.flags = uni(g.flags);
-  w.alpha = unid(g.alpha);
+  w.ra = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(g.A), (short)0, 0x7FFFFFFF, kBufFlags);
+  w.rb = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(g.B), (short)0, 0x7FFFFFFF, kBufFlags);
+  w.lda = (int)g.lda;
+  w.ldb = (int)g.ldb;
+  w.nch = valid ? (g.K + 7) >> 3 : 0;
+  w.kbase = (g.flags >> kStepPassShift) * 32;
+  w.ident = g.flags & kIdentA;
+  w.fresh = g.flags & kStepFresh;
+  w.end = valid && (g.flags & kStepEnd);
+  w.alpha = g.alpha;
   return w;
 }
 
+// byte offset of (row, chunk q) inside a plane buffer with ld chunks per row group
+__device__ __forceinline__ unsigned lane_off(int row, int q, int ld) {
+  return (unsigned)(plane_off(row, q, 0, ld) * 2);
+}
+
 template <int NI, int NPL>
-__device__ __forceinline__ void load_ppass(const PSeg& sg, int pass, const bool* rowok, const int* gi,
-                                           const bool* colok, const int* gj, int q, u32x4_t (&a)[NI][NPL],
-                                           u32x4_t (&b)[NI][NPL]) {
-  const int c = 4 * pass + q;
-  const bool cok = 8 * c < sg.K;
-  const bool ia = sg.flags & kIdentA;
+__device__ __forceinline__ void load_step(const PSeg& sg, const bool* rowok, const int* gi, const bool* colok,
+                                          const int* gj, int q, u32x4_t (&a)[NI][NPL], u32x4_t (&b)[NI][NPL]) {
+  const bool cok = q < sg.nch;
   const u32x4_t zero = {0u, 0u, 0u, 0u};
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
-    if (ia) {
+    if (sg.ident) {
       // alpha I: the h part is 1.0 (bf16 0x3F80) where row == k
       u32x4_t h = zero;
-      const int d = gi[i] - 8 * c;
-      if (rowok[i] && cok && d >= 0 && d < 8) {
+      const int d = gi[i] - sg.kbase - 8 * q;
+      const bool on = rowok[i] && cok && d >= 0 && d < 8;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) h[w] = (d >> 1) == w ? (0x3F80u << (16 * (d & 1))) : 0u;
-      }
+      for (int w = 0; w < 4; ++w) h[w] = (on && (d >> 1) == w) ? (0x3F80u << (16 * (d & 1))) : 0u;
       a[i][0] = h;
 #pragma unroll
       for (int pl = 1; pl < NPL; ++pl) a[i][pl] = zero;
-    } else if (rowok[i] && cok) {
-      const u32x4_t* p = reinterpret_cast<const u32x4_t*>(sg.A + ((int64_t)gi[i] * sg.lda + c) * (kPlaneParts * 8));
-#pragma unroll
-      for (int pl = 0; pl < NPL; ++pl) a[i][pl] = p[pl];
     } else {
+      const unsigned o = (rowok[i] && cok) ? lane_off(gi[i], q, sg.lda) : kBufOut;
 #pragma unroll
-      for (int pl = 0; pl < NPL; ++pl) a[i][pl] = zero;
+      for (int pl = 0; pl < NPL; ++pl) a[i][pl] = __builtin_amdgcn_raw_buffer_load_b128(sg.ra, o + pl * 128, 0, 0);
     }
   }
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
-    if (colok[j] && cok) {
-      const u32x4_t* p = reinterpret_cast<const u32x4_t*>(sg.B + ((int64_t)gj[j] * sg.ldb + c) * (kPlaneParts * 8));
+    const unsigned o = (colok[j] && cok) ? lane_off(gj[j], q, sg.ldb) : kBufOut;
 #pragma unroll
-      for (int pl = 0; pl < NPL; ++pl) b[j][pl] = p[pl];
-    } else {
-#pragma unroll
-      for (int pl = 0; pl < NPL; ++pl) b[j][pl] = zero;
-    }
+    for (int pl = 0; pl < NPL; ++pl) b[j][pl] = __builtin_amdgcn_raw_buffer_load_b128(sg.rb, o + pl * 128, 0, 0);
   }
 }
 
@@ -144,23 +180,25 @@ __device__ __forceinline__ float4_t mfma_bf16(u32x4_t a, u32x4_t b, float4_t c) 
                                                  0, 0, 0);
 }
 
-// smallest products first; the identity has no m and l parts
+// smallest products first (the identity's m and l parts are zero); a
+// segment's first pass starts from zero instead of the running sum
 template <int NI, int NPL, int NPROD>
 __device__ __forceinline__ void planes_mfma(const u32x4_t (&a)[NI][NPL], const u32x4_t (&b)[NI][NPL],
-                                            float4_t (&t)[NI][NI], bool ident) {
+                                            float4_t (&t)[NI][NI], bool fresh) {
+  const float4_t zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
-      float4_t c = t[i][j];
+      float4_t c;
       if (NPROD == 6) {
-        if (!ident) {
-          c = mfma_bf16(a[i][NPL - 1], b[j][0], c);
-          c = mfma_bf16(a[i][1], b[j][1], c);
-        }
+        c = mfma_bf16(a[i][NPL - 1], b[j][0], fresh ? zero : t[i][j]);
+        c = mfma_bf16(a[i][1], b[j][1], c);
         c = mfma_bf16(a[i][0], b[j][NPL - 1], c);
+        c = mfma_bf16(a[i][1], b[j][0], c);
+      } else {
+        c = mfma_bf16(a[i][1], b[j][0], fresh ? zero : t[i][j]);
       }
-      if (!ident) c = mfma_bf16(a[i][1], b[j][0], c);
       c = mfma_bf16(a[i][0], b[j][1], c);
       c = mfma_bf16(a[i][0], b[j][0], c);
       t[i][j] = c;
@@ -172,15 +210,17 @@ __device__ __forceinline__ void planes_mfma(const u32x4_t (&a)[NI][NPL], const u
 // rows 4 (lane / 16) + v a lane holds are four consecutive K values of one chunk.
 template <int TW, int NPROD, int OUTP>
 __global__ void __launch_bounds__(256)
-wave_planes_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __restrict__ segs, GBases bases) {
+wave_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __restrict__ segs_g, GBases bases) {
   constexpr int NI = TW / 16;
   constexpr int NPL = NPROD == 6 ? 3 : 2;  // parts read per operand
+  const cseg_ptr segs = (cseg_ptr)segs_g;
+  const ctile_ptr tiles = (ctile_ptr)tiles_g;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ti = uni(blockIdx.x * 4 + wave);
   if (ti >= ntiles) return;
-  const GTile tile = tiles[ti];
-  const int M = uni(tile.M), N = uni(tile.N), m0 = uni(tile.m0), n0 = uni(tile.n0);
-  const int seg0 = uni(tile.seg0), nseg = uni(tile.nseg);
+  const GTile tile = ld_tile(tiles, ti);
+  const int M = tile.M, N = tile.N, m0 = tile.m0, n0 = tile.n0;
+  const int seg0 = tile.seg0, nseg = tile.nseg;
   const int mt = min(TW, M - m0);
   const int nt = min(TW, N - n0);
   const int r16 = lane & 15, q = lane >> 4;
@@ -198,55 +238,36 @@ wave_planes_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __re
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int j = 0; j < NI; ++j) {
-      t[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
-      acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
-    }
+    for (int j = 0; j < NI; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+  auto flush = [&](double alpha) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[i][j][v] += alpha * (double)t[i][j][v];
+  };
 
-  // software pipeline over the flattened (segment, pass) sequence
+  // steps alternate between two operand sets; raw descriptors are fetched
+  // two steps ahead so their scalar loads are in flight a step early
   if (nseg > 0) {
-    int si = 0, pass = 0;
-    PSeg cur = load_pseg(segs, seg0, bases);
-    int cur_np = (cur.K + 31) / 32;
-    u32x4_t a[NI][NPL], b[NI][NPL], an[NI][NPL], bn[NI][NPL];
-    load_ppass<NI, NPL>(cur, 0, rowok, gi, colok, gj, q, a, b);
-    while (true) {
-      int nsi = si, npass = pass + 1;
-      PSeg nxt = cur;
-      bool more = true;
-      if (npass >= cur_np) {
-        nsi = si + 1;
-        npass = 0;
-        if (nsi < nseg) nxt = load_pseg(segs, seg0 + nsi, bases);
-        else more = false;
-      }
-      if (more) load_ppass<NI, NPL>(nxt, npass, rowok, gi, colok, gj, q, an, bn);
-      planes_mfma<NI, NPL, NPROD>(a, b, t, cur.flags & kIdentA);
-      if (npass == 0) {
-        // end of the current segment: scale by its alpha into float64
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-#pragma unroll
-          for (int j = 0; j < NI; ++j) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[i][j][v] += cur.alpha * (double)t[i][j][v];
-            t[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
-          }
-      }
-      if (!more) break;
-      if (npass == 0) {
-        cur = nxt;
-        cur_np = (cur.K + 31) / 32;
-      }
-      si = nsi;
-      pass = npass;
-#pragma unroll
-      for (int i = 0; i < NI; ++i)
-#pragma unroll
-        for (int pl = 0; pl < NPL; ++pl) {
-          a[i][pl] = an[i][pl];
-          b[i][pl] = bn[i][pl];
-        }
+    u32x4_t a0[NI][NPL], b0[NI][NPL], a1[NI][NPL], b1[NI][NPL];
+    PSeg d0 = decode_step(ld_seg(segs, seg0), true);
+    GSeg gn = ld_seg(segs, seg0 + min(1, nseg - 1));
+    load_step<NI, NPL>(d0, rowok, gi, colok, gj, q, a0, b0);
+    for (int s = 0;; s += 2) {
+      const PSeg d1 = decode_step(gn, s + 1 < nseg);
+      gn = ld_seg(segs, seg0 + min(s + 2, nseg - 1));
+      load_step<NI, NPL>(d1, rowok, gi, colok, gj, q, a1, b1);
+      planes_mfma<NI, NPL, NPROD>(a0, b0, t, d0.fresh);
+      if (d0.end) flush(d0.alpha);
+      if (s + 1 >= nseg) break;
+      d0 = decode_step(gn, s + 2 < nseg);
+      gn = ld_seg(segs, seg0 + min(s + 3, nseg - 1));
+      load_step<NI, NPL>(d0, rowok, gi, colok, gj, q, a0, b0);
+      planes_mfma<NI, NPL, NPROD>(a1, b1, t, d1.fresh);
+      if (d1.end) flush(d1.alpha);
+      if (s + 2 >= nseg) break;
     }
   }
   if (OUTP == 1) {
@@ -262,11 +283,12 @@ wave_planes_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __re
           unsigned short h[4], m[4], l[4];
 #pragma unroll
           for (int v = 0; v < 4; ++v) split3(acc[i][j][v], h[v], m[v], l[v]);
-          uint16_t* d = P + ((int64_t)c * tile.ldc + (r >> 3)) * (kPlaneParts * 8) + (r & 7);
+          // plane row c (a column of C), K index r: parts 64 elements apart
+          uint16_t* d = P + plane_off(c, r >> 3, 0, tile.ldc) + (r & 7);
           typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
           *reinterpret_cast<u32x2_t*>(d) = u32x2_t{h[0] | ((unsigned)h[1] << 16), h[2] | ((unsigned)h[3] << 16)};
-          *reinterpret_cast<u32x2_t*>(d + 8) = u32x2_t{m[0] | ((unsigned)m[1] << 16), m[2] | ((unsigned)m[3] << 16)};
-          *reinterpret_cast<u32x2_t*>(d + 16) = u32x2_t{l[0] | ((unsigned)l[1] << 16), l[2] | ((unsigned)l[3] << 16)};
+          *reinterpret_cast<u32x2_t*>(d + 64) = u32x2_t{m[0] | ((unsigned)m[1] << 16), m[2] | ((unsigned)m[3] << 16)};
+          *reinterpret_cast<u32x2_t*>(d + 128) = u32x2_t{l[0] | ((unsigned)l[1] << 16), l[2] | ((unsigned)l[3] << 16)};
         }
       }
     return;
