@@ -13,6 +13,9 @@
 // float64 accumulators.
 #include "devutil.h"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace bsd {
 
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
@@ -23,6 +26,15 @@ __device__ __forceinline__ void split3(double x, unsigned short& h, unsigned sho
   m = bf16_rne((float)r1);
   const double r2 = r1 - bf16_to_double(m);
   l = bf16_rne((float)r2);
+}
+
+// the same for a float32 value (every step exact in float32)
+__device__ __forceinline__ void split3f(float x, unsigned short& h, unsigned short& m, unsigned short& l) {
+  h = bf16_rne(x);
+  const float r1 = x - __uint_as_float(((unsigned int)h) << 16);
+  m = bf16_rne(r1);
+  const float r2 = r1 - __uint_as_float(((unsigned int)m) << 16);
+  l = bf16_rne(r2);
 }
 
 // one workgroup per task; each thread writes one row of one chunk in all parts
@@ -205,10 +217,209 @@ __device__ __forceinline__ void planes_mfma(const u32x4_t (&a)[NI][NPL], const u
     }
 }
 
-// OUTP 0: C is float64 (C = beta C + result).  OUTP 1: the result is split and
-// stored as planes of C^T: element (r, c) goes to row c, K index r; the four
-// rows 4 (lane / 16) + v a lane holds are four consecutive K values of one chunk.
+// What the epilogue of a tile needs (wave-uniform).
+struct PEpi {
+  uint64_t C;
+  int64_t ldc;
+  int mt, nt;
+  double beta;
+};
+
+// tile -> lane coordinates of the loader
+template <int NI, int TW>
+__device__ __forceinline__ void tile_lanes(const GTile& T, int r16, bool* rowok, int* gi, bool* colok, int* gj) {
+  const int mt = min(TW, T.M - T.m0), nt = min(TW, T.N - T.n0);
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    rowok[i] = i * 16 + r16 < mt;
+    gi[i] = T.m0 + i * 16 + r16;
+    colok[i] = i * 16 + r16 < nt;
+    gj[i] = T.n0 + i * 16 + r16;
+  }
+}
+
+template <int TW>
+__device__ __forceinline__ PEpi tile_epi(const GTile& T) {
+  PEpi e;
+  e.C = T.C;
+  e.ldc = T.ldc;
+  e.mt = min(TW, T.M - T.m0);
+  e.nt = min(TW, T.N - T.n0);
+  e.beta = T.beta;
+  return e;
+}
+
+// OUTP 0: C is float64 (C = beta C + result), segment sums go into float64
+// accumulators.  OUTP 1: the result is split and stored as planes of C^T
+// (element (r, c) goes to row c, K index r; the four rows 4 (lane / 16) + v a
+// lane holds are four consecutive K values of one chunk); its sums stay in
+// float32, which is all three bf16 parts can hold.
+//
+// Waves are persistent: wave w takes tiles w, w + W, w + 2W, ... (W waves in
+// the grid) and runs one flattened sequence of (tile, step) through the two
+// operand sets, so the next tile's descriptors and operands are in flight
+// during the current tile's last MFMAs and its epilogue.
 template <int TW, int NPROD, int OUTP>
+__global__ void __launch_bounds__(256)
+planes_persistent_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __restrict__ segs_g,
+                         GBases bases) {
+  constexpr int NI = TW / 16;
+  constexpr int NPL = NPROD == 6 ? 3 : 2;  // parts read per operand
+  typedef typename std::conditional<OUTP == 1, float4_t, double4_t>::type acc_t;
+  const cseg_ptr segs = (cseg_ptr)segs_g;
+  const ctile_ptr tiles = (ctile_ptr)tiles_g;
+  const int lane = threadIdx.x & 63;
+  const int W = gridDim.x * 4;
+  int lt = uni(blockIdx.x * 4 + (threadIdx.x >> 6));
+  if (lt >= ntiles) return;
+  const int r16 = lane & 15, q = lane >> 4;
+
+  // loader: tile lt, step ls
+  GTile T = ld_tile(tiles, lt);
+  int ls = 0;
+  bool rowok[NI], colok[NI];
+  int gi[NI], gj[NI];
+  tile_lanes<NI, TW>(T, r16, rowok, gi, colok, gj);
+  bool loading = true;
+  // descriptor of the loader's step: a real step, or an empty one (loads read
+  // zeros, no memory access) for a tile without segments or past the last tile
+  auto step_desc = [&]() -> PSeg {
+    if (loading && T.nseg > 0) return decode_step(ld_seg(segs, T.seg0 + ls), true);
+    GSeg g;
+    g.A = 0;
+    g.B = 0;
+    g.lda = g.ldb = 0;
+    g.K = 0;
+    g.flags = kStepFresh | kStepEnd;
+    g.alpha = 0.0;
+    PSeg d = decode_step(g, false);
+    d.end = loading;   // an empty tile still writes its (zero) result
+    return d;
+  };
+  // move the loader one step on; returns whether that step ends its tile
+  auto advance = [&]() {
+    if (++ls < T.nseg) return;
+    lt += W;
+    ls = 0;
+    if (lt < ntiles) {
+      T = ld_tile(tiles, lt);
+      tile_lanes<NI, TW>(T, r16, rowok, gi, colok, gj);
+    } else {
+      loading = false;
+    }
+  };
+
+  float4_t t[NI][NI];
+  acc_t acc[NI][NI];
+  auto clear_acc = [&]() {
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
+  };
+  auto flush = [&](double alpha) {
+#pragma unroll
+    for (int i = 0; i < NI; ++i)
+#pragma unroll
+      for (int j = 0; j < NI; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (OUTP == 1) acc[i][j][v] += (float)alpha * t[i][j][v];
+          else acc[i][j][v] += alpha * (double)t[i][j][v];
+        }
+  };
+  auto epilogue = [&](const PEpi& e) {
+    if (OUTP == 1) {
+      // rows come in groups of 4 inside one chunk; mt is a multiple of 8
+      uint16_t* P = reinterpret_cast<uint16_t*>(const_cast<double*>(resolve(e.C, bases)));
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+          const int r = i * 16 + 4 * q;
+          const int c = j * 16 + r16;
+          if (r < e.mt && c < e.nt) {
+            unsigned short h[4], m[4], l[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) split3f(acc[i][j][v], h[v], m[v], l[v]);
+            // plane row c (a column of C), K index r: parts 64 elements apart
+            uint16_t* d = P + plane_off(c, r >> 3, 0, e.ldc) + (r & 7);
+            typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+            *reinterpret_cast<u32x2_t*>(d) = u32x2_t{h[0] | ((unsigned)h[1] << 16), h[2] | ((unsigned)h[3] << 16)};
+            *reinterpret_cast<u32x2_t*>(d + 64) = u32x2_t{m[0] | ((unsigned)m[1] << 16), m[2] | ((unsigned)m[3] << 16)};
+            *reinterpret_cast<u32x2_t*>(d + 128) = u32x2_t{l[0] | ((unsigned)l[1] << 16), l[2] | ((unsigned)l[3] << 16)};
+          }
+        }
+    } else {
+      double* C = const_cast<double*>(resolve(e.C, bases));
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            // bf16 16x16x32 output: accumulator register v of lane l holds row 4 (l / 16) + v
+            const int r = i * 16 + 4 * q + v;
+            const int c = j * 16 + r16;
+            if (r < e.mt && c < e.nt) {
+              double* p = C + (int64_t)r * e.ldc + c;
+              double x = acc[i][j][v];
+              if (e.beta != 0.0) x += e.beta * (*p);
+              *p = x;
+            }
+          }
+    }
+  };
+
+  clear_acc();
+  u32x4_t a0[NI][NPL], b0[NI][NPL], a1[NI][NPL], b1[NI][NPL];
+  // set 0: the first step
+  PSeg d0 = step_desc();
+  PEpi e0 = tile_epi<TW>(T);
+  load_step<NI, NPL>(d0, rowok, gi, colok, gj, q, a0, b0);
+  bool te0 = max(T.nseg, 1) == 1;   // this step ends its tile
+  advance();
+  PSeg d1;
+  PEpi e1 = e0;
+  bool te1 = false;
+  while (true) {
+    // set 1: the next step (beyond the last tile: an empty step)
+    d1 = step_desc();
+    e1 = tile_epi<TW>(T);
+    const bool more1 = loading;
+    te1 = ls + 1 >= max(T.nseg, 1);
+    load_step<NI, NPL>(d1, rowok, gi, colok, gj, q, a1, b1);
+    if (loading) advance();
+    planes_mfma<NI, NPL, NPROD>(a0, b0, t, d0.fresh);
+    if (d0.end) flush(d0.alpha);
+    if (te0) {
+      epilogue(e0);
+      clear_acc();
+    }
+    if (!more1) break;
+    // set 0: the step after
+    d0 = step_desc();
+    e0 = tile_epi<TW>(T);
+    const bool more0 = loading;
+    te0 = ls + 1 >= max(T.nseg, 1);
+    load_step<NI, NPL>(d0, rowok, gi, colok, gj, q, a0, b0);
+    if (loading) advance();
+    planes_mfma<NI, NPL, NPROD>(a1, b1, t, d1.fresh);
+    if (d1.end) flush(d1.alpha);
+    if (te1) {
+      epilogue(e1);
+      clear_acc();
+    }
+    if (!more0) break;
+  }
+}
+
+// Float64 output (C = beta C + result), one tile per wave: the tiles are long
+// split-K units and the hardware dispatcher balances them.  Segment sums are
+// added into float64 accumulators.
+template <int TW, int NPROD>
 __global__ void __launch_bounds__(256)
 wave_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __restrict__ segs_g, GBases bases) {
   constexpr int NI = TW / 16;
@@ -270,29 +481,6 @@ wave_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __
       if (s + 2 >= nseg) break;
     }
   }
-  if (OUTP == 1) {
-    // rows come in groups of 4 inside one chunk; mt is a multiple of 8
-    uint16_t* P = reinterpret_cast<uint16_t*>(const_cast<double*>(resolve(tile.C, bases)));
-#pragma unroll
-    for (int i = 0; i < NI; ++i)
-#pragma unroll
-      for (int j = 0; j < NI; ++j) {
-        const int r = i * 16 + 4 * q;
-        const int c = j * 16 + r16;
-        if (r < mt && c < nt) {
-          unsigned short h[4], m[4], l[4];
-#pragma unroll
-          for (int v = 0; v < 4; ++v) split3(acc[i][j][v], h[v], m[v], l[v]);
-          // plane row c (a column of C), K index r: parts 64 elements apart
-          uint16_t* d = P + plane_off(c, r >> 3, 0, tile.ldc) + (r & 7);
-          typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
-          *reinterpret_cast<u32x2_t*>(d) = u32x2_t{h[0] | ((unsigned)h[1] << 16), h[2] | ((unsigned)h[3] << 16)};
-          *reinterpret_cast<u32x2_t*>(d + 64) = u32x2_t{m[0] | ((unsigned)m[1] << 16), m[2] | ((unsigned)m[3] << 16)};
-          *reinterpret_cast<u32x2_t*>(d + 128) = u32x2_t{l[0] | ((unsigned)l[1] << 16), l[2] | ((unsigned)l[3] << 16)};
-        }
-      }
-    return;
-  }
   double* C = const_cast<double*>(resolve(tile.C, bases));
   const double beta = tile.beta;
 #pragma unroll
@@ -316,11 +504,21 @@ wave_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __
 template <int TW, int OUTP>
 static void launch_planes_tw(const GTile* tiles, int ntiles, const GSeg* segs, const GBases& b, hipStream_t s,
                              int precision) {
-  const dim3 grid((ntiles + 3) / 4), block(256);
-  if (precision == 1)
-    hipLaunchKernelGGL((wave_planes_kernel<TW, 3, OUTP>), grid, block, 0, s, tiles, ntiles, segs, b);
-  else
-    hipLaunchKernelGGL((wave_planes_kernel<TW, 6, OUTP>), grid, block, 0, s, tiles, ntiles, segs, b);
+  if (OUTP == 1) {
+    // planes-out tiles are short (one segment): persistent waves, at most 2048
+    // workgroups (8 per CU), each looping over its tiles
+    const dim3 grid(std::min((ntiles + 3) / 4, 2048)), block(256);
+    if (precision == 1)
+      hipLaunchKernelGGL((planes_persistent_kernel<TW, 3, 1>), grid, block, 0, s, tiles, ntiles, segs, b);
+    else
+      hipLaunchKernelGGL((planes_persistent_kernel<TW, 6, 1>), grid, block, 0, s, tiles, ntiles, segs, b);
+  } else {
+    const dim3 grid((ntiles + 3) / 4), block(256);
+    if (precision == 1)
+      hipLaunchKernelGGL((wave_planes_kernel<TW, 3>), grid, block, 0, s, tiles, ntiles, segs, b);
+    else
+      hipLaunchKernelGGL((wave_planes_kernel<TW, 6>), grid, block, 0, s, tiles, ntiles, segs, b);
+  }
 }
 
 void launch_planes_gemm(const GTile* tiles, int ntiles, int shape, const GSeg* segs, const GBases& b,
