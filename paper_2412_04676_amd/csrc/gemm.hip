@@ -10,6 +10,7 @@
 #include "devutil.h"
 
 #include <algorithm>
+#include <map>
 #include <set>
 
 namespace bsd {
@@ -485,6 +486,8 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
   struct Pending {
     GTile t;
     double work;
+    int group;
+    double f;   // where the unit starts in its tile's segment list (fraction of the work)
   };
   std::vector<Pending> t[kShapes];
   std::vector<GSeg> sg;
@@ -546,7 +549,7 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
         x.seg0 = seg0;
         x.nseg = nseg;
         x.beta = p.beta;
-        t[cls].push_back({x, ktot});
+        t[cls].push_back({x, ktot, p.group, 0.0});
       }
   }
   wave = wave_tiles || plane_operands;
@@ -586,6 +589,7 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
           u.t.beta = 0.0;
           u.work = 0.0;
           for (int k = s0; k <= si; ++k) u.work += segwork[k];
+          u.f = (acc - u.work) / x.work;
           units.push_back({u, ws_elems + (int64_t)made * stride});
           ++made;
           s0 = si + 1;
@@ -605,11 +609,61 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
       red_off.push_back(ws_elems);
       ws_elems += (int64_t)made * stride;
     }
-    // longest units first inside every launch (LPT order)
-    std::stable_sort(units.begin(), units.end(),
-                     [](const std::pair<Pending, int64_t>& a, const std::pair<Pending, int64_t>& b) {
-                       return a.first.work > b.first.work;
-                     });
+    bool grouped = !units.empty();
+    for (const auto& u : units) grouped = grouped && u.first.group >= 0;
+    if (grouped) {
+      // workgroup b runs on XCD b % 8 (round-robin dispatch).  Groups go whole
+      // to the least loaded XCD; inside an XCD, units run in the order of
+      // where they start in their segment lists, so the waves resident at one
+      // time on an XCD read the same operands through its L2.
+      constexpr int kXcd = 8;
+      const int per_wg = c >= 4 ? 4 : 1;
+      std::map<int, double> gwork;
+      for (const auto& u : units) gwork[u.first.group] += u.first.work;
+      std::vector<std::pair<double, int>> gl;
+      for (const auto& kv : gwork) gl.push_back({kv.second, kv.first});
+      std::sort(gl.begin(), gl.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+        return a.first > b.first || (a.first == b.first && a.second < b.second);
+      });
+      std::map<int, int> xcd_of;
+      double load[kXcd] = {0, 0, 0, 0, 0, 0, 0, 0};
+      for (const auto& g : gl) {
+        const int x = (int)(std::min_element(load, load + kXcd) - load);
+        xcd_of[g.second] = x;
+        load[x] += g.first;
+      }
+      std::vector<std::pair<Pending, int64_t>> lists[kXcd];
+      for (const auto& u : units) lists[xcd_of[u.first.group]].push_back(u);
+      for (auto& l : lists)
+        std::stable_sort(l.begin(), l.end(),
+                         [](const std::pair<Pending, int64_t>& a, const std::pair<Pending, int64_t>& b) {
+                           return a.first.f < b.first.f || (a.first.f == b.first.f && a.first.work > b.first.work);
+                         });
+      size_t pos[kXcd] = {0, 0, 0, 0, 0, 0, 0, 0};
+      std::vector<std::pair<Pending, int64_t>> order;
+      order.reserve(units.size());
+      for (int wg = 0; order.size() < units.size(); ++wg) {
+        int x = wg % kXcd;
+        for (int k = 0; k < per_wg && order.size() < units.size(); ++k) {
+          if (pos[x] >= lists[x].size()) {   // this XCD's list is done: lend from the longest
+            size_t best = 0;
+            for (int y = 0; y < kXcd; ++y)
+              if (lists[y].size() - pos[y] > best) {
+                best = lists[y].size() - pos[y];
+                x = y;
+              }
+          }
+          order.push_back(lists[x][pos[x]++]);
+        }
+      }
+      units.swap(order);
+    } else {
+      // longest units first inside every launch (LPT order)
+      std::stable_sort(units.begin(), units.end(),
+                       [](const std::pair<Pending, int64_t>& a, const std::pair<Pending, int64_t>& b) {
+                         return a.first.work > b.first.work;
+                       });
+    }
     first[c] = (int)all.size();
     count[c] = (int)units.size();
     for (const auto& u : units) {

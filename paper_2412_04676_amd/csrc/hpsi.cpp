@@ -516,6 +516,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
               gp.M = ob.rows;
               gp.N = ob.cols;
               gp.beta = 1.0;
+              gp.group = ob.r;   // outputs of one right sector read the same V_b columns
             }
             gp.segs.push_back(sg);
             if (!o.ident) useful += 2.0 * ob.rows * (double)ob.cols * pb.rows;
@@ -542,6 +543,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
               gq.M = gp.M;
               gq.N = gp.N;
               gq.beta = 1.0;
+              gq.group = gp.group;
             }
             gq.segs.push_back(sq);
           }

@@ -283,6 +283,9 @@ struct GemmProblem {
   int M, N;
   double beta;
   std::vector<GSeg> segs;
+  // locality group (>= 0): problems of one group share operands and are placed
+  // on one XCD, in the order of their segment lists; -1: no grouping
+  int group = -1;
 };
 
 // Device-resident tile/segment lists for one launch group (64x64 and 32x32 tiles).
