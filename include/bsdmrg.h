@@ -94,6 +94,12 @@ int bsdmrg_set_site_tensor(bsdmrg_ctx* ctx, int site, int n_blocks, const int32_
  * left).  Already built blocks are kept.  Synchronizes `stream`. */
 int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream);
 
+/* Device workspace budget of one renormalization step (bytes, default 8 GiB):
+ * the new block's operators are produced in batches whose aggregated operators
+ * and intermediates fit it (a batch holds at least one operator).  Applies to
+ * later bsdmrg_build_env calls.  EINVAL for 0. */
+int bsdmrg_set_renorm_workspace(bsdmrg_ctx* ctx, size_t bytes);
+
 /* Layout of the two-site wave function at sites (site, site+1), between the
  * left block of bond `site` and the right block of bond site+2.  With meta ==
  * NULL only *n_blocks and *n_elems are returned.  Otherwise meta (host, cap >=

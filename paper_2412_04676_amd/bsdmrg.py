@@ -59,6 +59,7 @@ _SIGS = {
     "bsdmrg_load_integrals": ([c_vp, c_vp, c_vp, ctypes.c_double], c_int),
     "bsdmrg_set_site_tensor": ([c_vp, c_int, c_int, c_vp, c_vp], c_int),
     "bsdmrg_build_env": ([c_vp, c_int, c_int, c_vp], c_int),
+    "bsdmrg_set_renorm_workspace": ([c_vp, c_sz], c_int),
     "bsdmrg_psi_layout": ([c_vp, c_int, ctypes.POINTER(c_int), c_i64p, c_vp, c_vp], c_int),
     "bsdmrg_hpsi_prepare": ([c_vp, c_int, c_int, c_sz, c_vp], c_int),
     "bsdmrg_hpsi": ([c_vp, c_int, c_vp, c_vp, c_int, c_vp], c_int),
@@ -147,6 +148,10 @@ def site_tensor_arrays(tensor):
 def bsdmrg_set_site_tensor(ctx, site, tensor):
     meta, data = site_tensor_arrays(tensor)
     _check(_lib.bsdmrg_set_site_tensor(ctx, site, len(meta), _ptr(meta), _ptr(data)))
+
+
+def bsdmrg_set_renorm_workspace(ctx, nbytes):
+    _check(_lib.bsdmrg_set_renorm_workspace(ctx, nbytes))
 
 
 def bsdmrg_build_env(ctx, side, bond, stream=None):

@@ -314,7 +314,6 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
   std::vector<Ref> refs;
   std::map<std::tuple<int, char, int, int, bool>, int> ref_index;  // stored/identity refs
   std::vector<AggOp> aggs;
-  int64_t ws_elems = 0;
   struct GRef {
     int ref;
     double coef;
@@ -358,8 +357,7 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
       } else {
         AggOp a;
         a.sk = make_skeleton(old->basis, old->basis, bdq);
-        a.off = ws_elems;
-        ws_elems += a.sk.layer_stride;
+        a.off = -1;   // workspace offset, assigned per batch
         for (const auto& t : g.terms) {
           Q tdq = t.key.kind == 'I' ? Q{0, 0} : key_dq(t.key, left);
           if (t.trans) tdq = -tdq;
@@ -367,10 +365,7 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
           if (t.key.kind != 'I' && old->ops.find(t.key) == old->ops.end()) continue;
           a.terms.push_back(t);
         }
-        if (a.terms.empty()) {
-          ws_elems -= a.sk.layer_stride;
-          continue;
-        }
+        if (a.terms.empty()) continue;
         Ref r;
         r.kind = 2;
         r.agg = (int)aggs.size();
@@ -395,17 +390,15 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
     int64_t off;     // -1: identity (use the site tensor block directly)
     int rows, cols;  // T rows x cols (ld = cols)
   };
-  std::map<TKey, TVal> tmap;
-  const int64_t agg_end = ws_elems;
-  // which (ref, s) pairs are needed
+  // which (ref, s) pairs are needed, and each ref's intermediates
   std::map<std::pair<int, int>, bool> need;
   for (auto& v : per_key)
     for (auto& gr : v)
       for (int sp = 0; sp < 4; ++sp)
         for (int s0 = 0; s0 < 4; ++s0)
           if (gr.M(sp, s0) != 0.0) need[{gr.ref, s0}] = true;
-  const double* wsbase = nullptr;  // fixed after allocation; offsets used until then
-  std::vector<std::tuple<TKey, int, int, int>> p1list;  // key, out rows, K, cols
+  std::vector<std::vector<std::pair<TKey, TVal>>> ref_t(refs.size());
+  std::vector<int64_t> ref_cost(refs.size(), 0);   // workspace elements of a ref (aggregate + its T)
   for (auto& nd : need) {
     int ri = nd.first.first, s0 = nd.first.second;
     const Ref& r = refs[ri];
@@ -415,7 +408,7 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
       int oo = old->basis.find(old->basis.q[oi] + r.dq);
       if (oo < 0) continue;
       if (r.kind == 1) {
-        tmap[{ri, s0, oi}] = {-1, 0, 0};
+        ref_t[ri].push_back({{ri, s0, oi}, {-1, 0, 0}});
         continue;
       }
       // does op(ref) have a block at oi?
@@ -426,171 +419,214 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
         int src = r.trans ? oo : oi;
         if (!old->op_block(r.key, src, &rr, &cc, &ld)) continue;
       }
-      int trows = old->basis.dim[oo];
-      int tcols = left ? tb.cols : tb.rows;  // d_new
-      tmap[{ri, s0, oi}] = {ws_elems, trows, tcols};
-      ws_elems += ((int64_t)trows * tcols + 1) / 2 * 2;
+      const int trows = old->basis.dim[oo];
+      const int tcols = left ? tb.cols : tb.rows;  // d_new
+      ref_t[ri].push_back({{ri, s0, oi}, {0, trows, tcols}});
+      ref_cost[ri] += ((int64_t)trows * tcols + 1) / 2 * 2;
     }
   }
-  ctx.ws.reserve(std::max<int64_t>(ws_elems, 1) * sizeof(double));
-  double* ws = static_cast<double*>(ctx.ws.p);
-  wsbase = ws;
-  (void)wsbase;
+  for (size_t ri = 0; ri < refs.size(); ++ri)
+    if (refs[ri].kind == 2) ref_cost[ri] += aggs[refs[ri].agg].sk.layer_stride;
 
-  // aggregation
-  {
-    std::vector<AggTask> tasks;
-    std::vector<AggTerm> terms;
-    for (auto& a : aggs)
-      for (const auto& sb : a.sk.blocks) {
-        AggTask t;
-        t.out = ws + a.off + sb.off;
-        t.ldo = sb.ld;
-        t.rows = sb.rows;
-        t.cols = sb.cols;
-        t.t0 = (int)terms.size();
-        for (const auto& tm : a.terms) {
-          AggTerm x;
-          x.coef = tm.coef;
-          x.pad = 0;
-          if (tm.key.kind == 'I') {
-            if (sb.in != sb.out) continue;
-            x.in = nullptr;
-            x.ldi = 0;
-            x.flags = kIdentA;
-          } else {
-            int rr, cc, ld;
-            const double* p = tm.trans ? old->op_block(tm.key, sb.out, &rr, &cc, &ld)
-                                       : old->op_block(tm.key, sb.in, &rr, &cc, &ld);
-            if (!p) continue;
-            x.in = p;
-            x.ldi = ld;
-            x.flags = tm.trans ? kTransA : 0;
-          }
-          terms.push_back(x);
+  // output operators in batches whose workspace (aggregates + intermediates of
+  // the refs they use) stays under the budget; a ref shared by two batches is
+  // computed in both
+  const int64_t budget = (int64_t)(ctx.renorm_ws_budget / sizeof(double));
+  double fl = 0.0;
+  size_t k0 = 0;
+  while (k0 < keys.size()) {
+    std::vector<char> in_batch(refs.size(), 0);
+    std::vector<int> brefs;
+    int64_t bws = 0;
+    size_t k1 = k0;
+    for (; k1 < keys.size(); ++k1) {
+      int64_t add = 0;
+      for (const auto& gr : per_key[k1])
+        if (!in_batch[gr.ref]) add += ref_cost[gr.ref];
+      if (k1 > k0 && bws + add > budget) break;
+      for (const auto& gr : per_key[k1])
+        if (!in_batch[gr.ref]) {
+          in_batch[gr.ref] = 1;
+          brefs.push_back(gr.ref);
         }
-        t.nt = (int)terms.size() - t.t0;
-        tasks.push_back(t);
+      bws += add;
+    }
+    // batch-local workspace offsets
+    std::map<TKey, TVal> tmap;
+    int64_t ws_elems = 0;
+    for (int ri : brefs) {
+      if (refs[ri].kind == 2) {
+        aggs[refs[ri].agg].off = ws_elems;
+        ws_elems += aggs[refs[ri].agg].sk.layer_stride;
       }
-    if (!tasks.empty()) {
-      DevBuf dt, dm;
-      dt.reserve(tasks.size() * sizeof(AggTask));
-      dm.reserve(std::max<size_t>(1, terms.size()) * sizeof(AggTerm));
-      BSD_HIP(hipMemcpyAsync(dt.p, tasks.data(), tasks.size() * sizeof(AggTask), hipMemcpyHostToDevice, s));
-      if (!terms.empty())
-        BSD_HIP(hipMemcpyAsync(dm.p, terms.data(), terms.size() * sizeof(AggTerm), hipMemcpyHostToDevice, s));
-      launch_aggregate((const AggTask*)dt.p, (const AggTerm*)dm.p, (int)tasks.size(), s);
+      for (auto tv : ref_t[ri]) {
+        if (tv.second.off >= 0) {
+          tv.second.off = ws_elems;
+          ws_elems += ((int64_t)tv.second.rows * tv.second.cols + 1) / 2 * 2;
+        }
+        tmap[tv.first] = tv.second;
+      }
+    }
+    ctx.ws.reserve(std::max<int64_t>(ws_elems, 1) * sizeof(double));
+    double* ws = static_cast<double*>(ctx.ws.p);
+
+    // aggregation
+    {
+      std::vector<AggTask> tasks;
+      std::vector<AggTerm> terms;
+      for (int ri : brefs) {
+        if (refs[ri].kind != 2) continue;
+        const AggOp& a = aggs[refs[ri].agg];
+        for (const auto& sb : a.sk.blocks) {
+          AggTask t;
+          t.out = ws + a.off + sb.off;
+          t.ldo = sb.ld;
+          t.rows = sb.rows;
+          t.cols = sb.cols;
+          t.t0 = (int)terms.size();
+          for (const auto& tm : a.terms) {
+            AggTerm x;
+            x.coef = tm.coef;
+            x.pad = 0;
+            if (tm.key.kind == 'I') {
+              if (sb.in != sb.out) continue;
+              x.in = nullptr;
+              x.ldi = 0;
+              x.flags = kIdentA;
+            } else {
+              int rr, cc, ld;
+              const double* p = tm.trans ? old->op_block(tm.key, sb.out, &rr, &cc, &ld)
+                                         : old->op_block(tm.key, sb.in, &rr, &cc, &ld);
+              if (!p) continue;
+              x.in = p;
+              x.ldi = ld;
+              x.flags = tm.trans ? kTransA : 0;
+            }
+            terms.push_back(x);
+          }
+          t.nt = (int)terms.size() - t.t0;
+          tasks.push_back(t);
+        }
+      }
+      if (!tasks.empty()) {
+        DevBuf dt, dm;
+        dt.reserve(tasks.size() * sizeof(AggTask));
+        dm.reserve(std::max<size_t>(1, terms.size()) * sizeof(AggTerm));
+        BSD_HIP(hipMemcpyAsync(dt.p, tasks.data(), tasks.size() * sizeof(AggTask), hipMemcpyHostToDevice, s));
+        if (!terms.empty())
+          BSD_HIP(hipMemcpyAsync(dm.p, terms.data(), terms.size() * sizeof(AggTerm), hipMemcpyHostToDevice, s));
+        launch_aggregate((const AggTask*)dt.p, (const AggTerm*)dm.p, (int)tasks.size(), s);
+        BSD_HIP(hipStreamSynchronize(s));
+      }
+    }
+
+    // phase 1: T = op(ref) X, X = A_s (left) or B_s^T (right)
+    std::vector<GemmProblem> p1;
+    for (auto& kv : tmap) {
+      if (kv.second.off < 0) continue;
+      const TKey& tk = kv.first;
+      const Ref& r = refs[tk.ref];
+      Operand o = ref_block(*old, r, aggs, ws, tk.oidx);
+      TB tb = tblock(tk.oidx, tk.sstate);
+      GemmProblem gp;
+      gp.C = tag_ptr(0, (uint64_t)(ws + kv.second.off));
+      gp.ldc = kv.second.cols;
+      gp.M = kv.second.rows;
+      gp.N = kv.second.cols;
+      gp.beta = 0.0;
+      GSeg sg;
+      sg.alpha = 1.0;
+      sg.K = o.cols;
+      sg.flags = (o.trans ? kTransA : 0) | (o.ident ? kIdentA : 0);
+      sg.A = tag_ptr(0, (uint64_t)o.p);
+      sg.lda = o.ld;
+      sg.B = tag_ptr(0, (uint64_t)tb.p);
+      if (left) {
+        sg.ldb = tb.cols;     // A_s: d_old x d_new
+      } else {
+        sg.flags |= kTransB;  // B_s: d_new x d_old, used transposed
+        sg.ldb = tb.cols;
+      }
+      gp.segs.push_back(sg);
+      p1.push_back(std::move(gp));
+    }
+    if (!p1.empty()) {
+      GemmPlan plan;
+      plan.build(p1);
+      GBases b{{0, 0, 0, 0}};
+      plan.launch(b, s);
+      fl += plan.flops;
       BSD_HIP(hipStreamSynchronize(s));
     }
-  }
-  (void)agg_end;
 
-  // phase 1: T = op(ref) X, X = A_s (left) or B_s^T (right)
-  std::vector<GemmProblem> p1;
-  for (auto& kv : tmap) {
-    if (kv.second.off < 0) continue;
-    const TKey& tk = kv.first;
-    const Ref& r = refs[tk.ref];
-    Operand o = ref_block(*old, r, aggs, ws, tk.oidx);
-    TB tb = tblock(tk.oidx, tk.sstate);
-    GemmProblem gp;
-    gp.C = tag_ptr(0, (uint64_t)(ws + kv.second.off));
-    gp.ldc = kv.second.cols;
-    gp.M = kv.second.rows;
-    gp.N = kv.second.cols;
-    gp.beta = 0.0;
-    GSeg sg;
-    sg.alpha = 1.0;
-    sg.K = o.cols;
-    sg.flags = (o.trans ? kTransA : 0) | (o.ident ? kIdentA : 0);
-    sg.A = tag_ptr(0, (uint64_t)o.p);
-    sg.lda = o.ld;
-    sg.B = tag_ptr(0, (uint64_t)tb.p);
-    if (left) {
-      sg.ldb = tb.cols;     // A_s: d_old x d_new
-    } else {
-      sg.flags |= kTransB;  // B_s: d_new x d_old, used transposed
-      sg.ldb = tb.cols;
-    }
-    gp.segs.push_back(sg);
-    p1.push_back(std::move(gp));
-  }
-  double fl = 0.0;
-  if (!p1.empty()) {
-    GemmPlan plan;
-    plan.build(p1);
-    GBases b{{0, 0, 0, 0}};
-    plan.launch(b, s);
-    fl += plan.flops;
-    BSD_HIP(hipStreamSynchronize(s));
-  }
-
-  // phase 2: new op blocks
-  std::vector<GemmProblem> p2;
-  for (size_t ki = 0; ki < keys.size(); ++ki) {
-    const OpRef& orf = nw->ops[keys[ki]];
-    Family& fam = nw->fams[orf.fam];
-    for (const auto& sb : fam.sk.blocks) {
-      GemmProblem gp;
-      gp.C = tag_ptr(0, (uint64_t)(fam.dev + (int64_t)orf.layer * fam.sk.layer_stride + sb.off));
-      gp.ldc = sb.ld;
-      gp.M = sb.rows;
-      gp.N = sb.cols;
-      gp.beta = 0.0;
-      const Q qn = nb.q[sb.in];
-      for (const auto& gr : per_key[ki]) {
-        const Ref& r = refs[gr.ref];
-        for (int s0 = 0; s0 < 4; ++s0) {
-          const Q qo = qn - kSiteQ[s0];
-          int oi = old->basis.find(qo);
-          if (oi < 0) continue;
-          auto it = tmap.find({gr.ref, s0, oi});
-          if (it == tmap.end()) continue;
-          int oo = old->basis.find(qo + r.dq);
-          for (int sp = 0; sp < 4; ++sp) {
-            double m = gr.M(sp, s0);
-            if (m == 0.0) continue;
-            if (old->basis.q[oo] + kSiteQ[sp] != nb.q[sb.out]) continue;
-            TB to = tblock(oo, sp);
-            if (!to.p) continue;
-            double sign;
-            if (left) sign = (gr.mpar && old->basis.q[oi].parity()) ? -1.0 : 1.0;
-            else sign = (r.dq.parity() && kSiteQ[s0].parity()) ? -1.0 : 1.0;
-            GSeg sg;
-            sg.alpha = gr.coef * m * sign;
-            sg.K = old->basis.dim[oo];
-            if (left) {
-              sg.A = tag_ptr(0, (uint64_t)to.p);    // A_{s'}: d_old' x d_new', used transposed
-              sg.lda = to.cols;
-              sg.flags = kTransA;
-            } else {
-              sg.A = tag_ptr(0, (uint64_t)to.p);    // B_{s'}: d_new' x d_old'
-              sg.lda = to.cols;
-              sg.flags = 0;
+    // phase 2: new op blocks of the batch's keys
+    std::vector<GemmProblem> p2;
+    for (size_t ki = k0; ki < k1; ++ki) {
+      const OpRef& orf = nw->ops[keys[ki]];
+      Family& fam = nw->fams[orf.fam];
+      for (const auto& sb : fam.sk.blocks) {
+        GemmProblem gp;
+        gp.C = tag_ptr(0, (uint64_t)(fam.dev + (int64_t)orf.layer * fam.sk.layer_stride + sb.off));
+        gp.ldc = sb.ld;
+        gp.M = sb.rows;
+        gp.N = sb.cols;
+        gp.beta = 0.0;
+        const Q qn = nb.q[sb.in];
+        for (const auto& gr : per_key[ki]) {
+          const Ref& r = refs[gr.ref];
+          for (int s0 = 0; s0 < 4; ++s0) {
+            const Q qo = qn - kSiteQ[s0];
+            int oi = old->basis.find(qo);
+            if (oi < 0) continue;
+            auto it = tmap.find({gr.ref, s0, oi});
+            if (it == tmap.end()) continue;
+            int oo = old->basis.find(qo + r.dq);
+            for (int sp = 0; sp < 4; ++sp) {
+              double m = gr.M(sp, s0);
+              if (m == 0.0) continue;
+              if (old->basis.q[oo] + kSiteQ[sp] != nb.q[sb.out]) continue;
+              TB to = tblock(oo, sp);
+              if (!to.p) continue;
+              double sign;
+              if (left) sign = (gr.mpar && old->basis.q[oi].parity()) ? -1.0 : 1.0;
+              else sign = (r.dq.parity() && kSiteQ[s0].parity()) ? -1.0 : 1.0;
+              GSeg sg;
+              sg.alpha = gr.coef * m * sign;
+              sg.K = old->basis.dim[oo];
+              if (left) {
+                sg.A = tag_ptr(0, (uint64_t)to.p);    // A_{s'}: d_old' x d_new', used transposed
+                sg.lda = to.cols;
+                sg.flags = kTransA;
+              } else {
+                sg.A = tag_ptr(0, (uint64_t)to.p);    // B_{s'}: d_new' x d_old'
+                sg.lda = to.cols;
+                sg.flags = 0;
+              }
+              if (it->second.off >= 0) {
+                sg.B = tag_ptr(0, (uint64_t)(ws + it->second.off));
+                sg.ldb = it->second.cols;
+              } else {
+                TB ti = tblock(oi, s0);
+                sg.B = tag_ptr(0, (uint64_t)ti.p);
+                sg.ldb = ti.cols;
+                if (!left) sg.flags |= kTransB;
+              }
+              gp.segs.push_back(sg);
             }
-            if (it->second.off >= 0) {
-              sg.B = tag_ptr(0, (uint64_t)(ws + it->second.off));
-              sg.ldb = it->second.cols;
-            } else {
-              TB ti = tblock(oi, s0);
-              sg.B = tag_ptr(0, (uint64_t)ti.p);
-              sg.ldb = ti.cols;
-              if (!left) sg.flags |= kTransB;
-            }
-            gp.segs.push_back(sg);
           }
         }
+        if (!gp.segs.empty()) p2.push_back(std::move(gp));
       }
-      if (!gp.segs.empty()) p2.push_back(std::move(gp));
     }
-  }
-  if (!p2.empty()) {
-    GemmPlan plan;
-    plan.build(p2);
-    GBases b{{0, 0, 0, 0}};
-    plan.launch(b, s);
-    fl += plan.flops;
-    BSD_HIP(hipStreamSynchronize(s));
+    if (!p2.empty()) {
+      GemmPlan plan;
+      plan.build(p2);
+      GBases b{{0, 0, 0, 0}};
+      plan.launch(b, s);
+      fl += plan.flops;
+      BSD_HIP(hipStreamSynchronize(s));
+    }
+    k0 = k1;
   }
   ctx.renorm_flops += fl;
   auto& m = left ? ctx.left : ctx.right;

@@ -268,6 +268,13 @@ int bsdmrg_truncate(bsdmrg_ctx* ctx, int site, const double* psi, int D, int dir
   });
 }
 
+int bsdmrg_set_renorm_workspace(bsdmrg_ctx* ctx, size_t bytes) {
+  return guard([&] {
+    BSD_CHECK(ctx && bytes > 0, BSDMRG_EINVAL, "NULL ctx or zero budget");
+    ctx->c.renorm_ws_budget = bytes;
+  });
+}
+
 int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream) {
   return guard([&] {
     BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");

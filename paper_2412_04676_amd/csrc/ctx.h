@@ -31,6 +31,7 @@ struct Ctx {
   std::map<int, std::unique_ptr<Block>> left, right;   // keyed by bond
   std::map<std::pair<int, int>, std::shared_ptr<HpsiPlan>> plans;  // (site, precision)
   DevBuf ws;                 // scratch for renormalization
+  size_t renorm_ws_budget = (size_t)8 << 30;   // per batch of new operators
   // statistics
   double last_hpsi_flops = 0.0;
   double renorm_flops = 0.0;

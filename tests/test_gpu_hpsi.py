@@ -202,3 +202,35 @@ def test_library_before_torch_keeps_one_hip_runtime():
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=100)
     assert r.returncode == 0 and "ok" in r.stdout, r.stdout + r.stderr
+
+
+def test_renormalization_in_batches_matches_one_batch():
+    # a tiny renormalization workspace forces many batches of new operators;
+    # the operators and the product must agree with the single-batch build
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    L, na, nb, D, site = 10, 5, 5, 100, 4
+    say("renormalization batches L=10")
+    ctx1, h, eri, dims, T = build_system(L, na, nb, D, site)
+    ctx2, *_ = build_system(L, na, nb, D, site, build=False)
+    B.bsdmrg_set_renorm_workspace(ctx2, 1 << 16)
+    B.bsdmrg_build_env(ctx2, B.LEFT, site)
+    B.bsdmrg_build_env(ctx2, B.RIGHT, site + 2)
+    checked = 0
+    for side, bond, keys in ((B.LEFT, site, [("H",), ("c", 3), ("A", 1, 4), ("B", 2, 5), ("S", 12)]),
+                             (B.RIGHT, site + 2, [("H",), ("c", 15), ("S", 3), ("P", 1, 6), ("Q", 2, 7)])):
+        for k in keys:
+            g1 = B.bsdmrg_get_block_op(ctx1, side, bond, k[0], *(list(k[1:]) + [-1, -1])[:2])
+            g2 = B.bsdmrg_get_block_op(ctx2, side, bond, k[0], *(list(k[1:]) + [-1, -1])[:2])
+            assert g1.keys() == g2.keys(), k
+            for q in g1:
+                scale = max(1.0, float(np.abs(g1[q]).max()))
+                assert np.abs(g1[q] - g2[q]).max() < 1e-12 * scale, (side, k, q)
+                checked += 1
+    assert checked > 20
+    psi = psi_for(dims, site, 9)
+    o1, _ = hpsi_gpu(ctx1, site, psi)
+    o2, _ = hpsi_gpu(ctx2, site, psi)
+    assert rel(o2, o1) < 1e-12
+    B.bsdmrg_destroy(ctx1)
+    B.bsdmrg_destroy(ctx2)
