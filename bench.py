@@ -154,7 +154,13 @@ def main():
 
     shapes = {0: "<2, 2>", 1: "<1, 1>", 2: "<1, 2>", 3: "<2, 1>", 4: "<16>", 5: "<32>"}
 
+    tuned = {}
+
     def time_precision(prec):
+        # schedule chosen by the library's autotuner (untimed setup)
+        best, dflt, ncand = B.bsdmrg_hpsi_autotune(ctx, site, prec, stream)
+        tuned[prec] = {"candidates": ncand, "default_ms": dflt, "tuned_ms": best}
+        log(f"bench: precision {prec}: autotune {ncand} schedules, default {dflt:.3f} ms -> {best:.3f} ms")
         for _ in range(args.warmup):
             B.bsdmrg_hpsi(ctx, site, x, y, prec, stream)
         torch.cuda.synchronize()
@@ -320,6 +326,7 @@ def main():
                               "d_rayleigh_Eh": de_rq[p], "per_launch_ms": res[p][5]}
                        for name, p in (("fp64", B.FP64), ("bf16x3", B.BF16X3), ("bf16x6", B.BF16X6))},
         "speedup_bf16x6_vs_fp64": res[B.FP64][0] / res[B.BF16X6][0],
+        "autotune": {name: tuned[p] for name, p in (("fp64", B.FP64), ("bf16x3", B.BF16X3), ("bf16x6", B.BF16X6))},
         "roofline": roof,
         "site_step": {"davidson_iters": it_dav, "davidson_ms": t_dav * 1e3, "energy": e_dav,
                       "residual": r_dav, "truncate_ms": t_tr * 1e3, "kept": kept, "trunc_err": err_tr,

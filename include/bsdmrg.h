@@ -119,6 +119,17 @@ int bsdmrg_psi_layout(bsdmrg_ctx* ctx, int site, int* n_blocks, int64_t* n_elems
 int bsdmrg_hpsi_prepare(bsdmrg_ctx* ctx, int site, int precision, size_t ws_bytes,
                         bsdmrg_stream_t stream);
 
+/* Choose the schedule of the prepared product at `site` for `precision` (the
+ * Tables step's tile and sector schedule): candidate split-K wave targets, XCD
+ * placement of locality groups and, for float64, the largest block given wave
+ * tiles are timed by graph replays on a scratch vector and the fastest is kept
+ * for this site.  best_ms and default_ms (optional) receive the product time of
+ * the chosen and of the default schedule, n_candidates (optional) the number
+ * tried.  Results are identical up to the order of float64 additions.
+ * Synchronizes `stream`. */
+int bsdmrg_hpsi_autotune(bsdmrg_ctx* ctx, int site, int precision, bsdmrg_stream_t stream, double* best_ms,
+                         double* default_ms, int* n_candidates);
+
 /* out = H_eff psi (Sec. II.B step 2) at two-site position `site`; psi and out
  * are device buffers in the layout of bsdmrg_psi_layout and must not overlap.
  * The product (output zero-fill and every grouped launch) is captured once

@@ -63,6 +63,8 @@ _SIGS = {
     "bsdmrg_psi_layout": ([c_vp, c_int, ctypes.POINTER(c_int), c_i64p, c_vp, c_vp], c_int),
     "bsdmrg_hpsi_prepare": ([c_vp, c_int, c_int, c_sz, c_vp], c_int),
     "bsdmrg_hpsi": ([c_vp, c_int, c_vp, c_vp, c_int, c_vp], c_int),
+    "bsdmrg_hpsi_autotune": ([c_vp, c_int, c_int, c_vp, ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_int)], c_int),
     "bsdmrg_hpsi_info": ([c_vp, c_int, c_int, ctypes.POINTER(ctypes.c_double), c_i64p, c_i64p,
                           c_i64p, c_i64p], c_int),
     "bsdmrg_hpsi_profile": ([c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_int, c_vp, c_vp, c_vp, c_vp,
@@ -200,6 +202,14 @@ def bsdmrg_hpsi_info(ctx, site, precision=FP64):
                                  ctypes.byref(c), ctypes.byref(d)))
     return {"flops": fl.value, "channels": a.value, "segments": b.value, "aggregates": c.value,
             "ws_bytes": d.value}
+
+
+def bsdmrg_hpsi_autotune(ctx, site, precision=FP64, stream=None):
+    """Returns (best ms, default ms, candidates tried); the best schedule is kept."""
+    best, dflt, n = ctypes.c_double(), ctypes.c_double(), c_int()
+    _check(_lib.bsdmrg_hpsi_autotune(ctx, site, precision, _stream(stream), ctypes.byref(best), ctypes.byref(dflt),
+                                     ctypes.byref(n)))
+    return best.value, dflt.value, n.value
 
 
 def bsdmrg_hpsi_profile(ctx, site, psi_dev, out_dev, precision=FP64, stream=None, cap=256):

@@ -357,6 +357,21 @@ int bsdmrg_hpsi_prepare(bsdmrg_ctx* ctx, int site, int precision, size_t ws_byte
   });
 }
 
+int bsdmrg_hpsi_autotune(bsdmrg_ctx* ctx, int site, int precision, bsdmrg_stream_t stream, double* best_ms,
+                         double* default_ms, int* n_candidates) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    HpsiPlan* p = get_plan(ctx->c, site, precision, 0, S(stream), false);
+    Block* Lb = get_block(ctx->c, true, site);
+    Block* Rb = get_block(ctx->c, false, site + 2);
+    BSD_CHECK(Lb && Rb && Lb->resident && Rb->resident, BSDMRG_EBUSY, "environment blocks not resident");
+    TuneResult r = autotune_hpsi(*p, precision, S(stream));
+    if (best_ms) *best_ms = r.best_ms;
+    if (default_ms) *default_ms = r.default_ms;
+    if (n_candidates) *n_candidates = r.n_candidates;
+  });
+}
+
 int bsdmrg_hpsi(bsdmrg_ctx* ctx, int site, const double* psi, double* out, int precision, bsdmrg_stream_t stream) {
   return guard([&] {
     BSD_CHECK(ctx && psi && out, BSDMRG_EINVAL, "NULL argument");

@@ -482,7 +482,7 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
   const int waves_per_tile[kShapes] = {4, 1, 2, 2, 1, 1};
   // split-K targets: about this many waves per launch, and parts of at least
   // this much work (work = sum of K + 16 per segment)
-  constexpr double kTargetWaves = 8192.0, kMinPartWork = 640.0;
+  const double kTargetWaves = opts.target_waves, kMinPartWork = opts.min_part_work;
   struct Pending {
     GTile t;
     double work;
@@ -502,7 +502,7 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
     // workgroup tile with the smallest padded area, then fewer tiles
     int cls = 0;
     int64_t best = -1;
-    if (plane_operands || (wave_tiles && p.M <= 64 && p.N <= 64)) {
+    if (plane_operands || (wave_tiles && p.M <= opts.wave_max && p.N <= opts.wave_max)) {
       cls = (p.M <= 16 && p.N <= 16) ? 4 : 5;
       best = 0;
     }
@@ -609,7 +609,7 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
       red_off.push_back(ws_elems);
       ws_elems += (int64_t)made * stride;
     }
-    bool grouped = !units.empty();
+    bool grouped = opts.xcd_order && !units.empty();
     for (const auto& u : units) grouped = grouped && u.first.group >= 0;
     if (grouped) {
       // workgroup b runs on XCD b % 8 (round-robin dispatch).  Groups go whole

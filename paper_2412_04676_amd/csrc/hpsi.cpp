@@ -633,6 +633,8 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   plan->nseg = 0;
   plan->phase1s.resize(nchunks);
   plan->phase2s.resize(nchunks);
+  plan->p2_probs.resize(nchunks);
+  plan->p2s_probs.resize(nchunks);
   for (int k = 0; k < nchunks; ++k) {
     plan->phase1[k] = std::make_unique<GemmPlan>();
     plan->phase1[k]->build(p1[k], true);
@@ -640,19 +642,14 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     o1.plane_output = true;
     plan->phase1s[k] = std::make_unique<GemmPlan>();
     plan->phase1s[k]->build(p1s[k], o1);
-    std::vector<GemmProblem> v, vs;
     for (auto& kv : p2[k]) {
       plan->nseg += kv.second.segs.size();
-      v.push_back(std::move(kv.second));
+      plan->p2_probs[k].push_back(std::move(kv.second));
     }
-    for (auto& kv : p2s[k]) vs.push_back(std::move(kv.second));
-    plan->phase2[k] = std::make_unique<GemmPlan>();
-    plan->phase2[k]->build(v, true);
-    GemmBuildOpts o2;
-    o2.plane_operands = true;
-    plan->phase2s[k] = std::make_unique<GemmPlan>();
-    plan->phase2s[k]->build(vs, o2);
+    for (auto& kv : p2s[k]) plan->p2s_probs[k].push_back(std::move(kv.second));
   }
+  // phase-2 tile lists from the kept problem lists (the autotuner rebuilds them)
+  rebuild_phase2(*plan, plan->opts64, plan->opts_planes);
 
   // ---------------------------------------------------------------- split tasks
   // padded-row maps of the right-sector stacks: plane column -> stack row or -1
@@ -717,6 +714,96 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   plan->nchannels = (int)chans.size();
   plan->naggs = (int)agg_sk.size();
   return plan;
+}
+
+void rebuild_phase2(HpsiPlan& plan, const GemmBuildOpts& o64, const GemmBuildOpts& oplanes) {
+  const size_t nchunks = plan.p2_probs.size();
+  for (auto& g : plan.graphs) (void)hipGraphExecDestroy(g.exec);
+  plan.graphs.clear();
+  plan.opts64 = o64;
+  plan.opts_planes = oplanes;
+  plan.opts_planes.plane_operands = true;
+  for (size_t k = 0; k < nchunks; ++k) {
+    plan.phase2[k] = std::make_unique<GemmPlan>();
+    plan.phase2[k]->build(plan.p2_probs[k], plan.opts64);
+    plan.phase2s[k] = std::make_unique<GemmPlan>();
+    plan.phase2s[k]->build(plan.p2s_probs[k], plan.opts_planes);
+  }
+}
+
+TuneResult autotune_hpsi(HpsiPlan& plan, int precision, hipStream_t s) {
+  const int64_t n = plan.lay.n_elems;
+  DevBuf x, y;
+  x.reserve(std::max<int64_t>(1, n) * sizeof(double));
+  y.reserve(std::max<int64_t>(1, n) * sizeof(double));
+  {
+    // any fixed non-trivial vector will do: the schedule does not depend on values
+    std::vector<double> h(std::max<int64_t>(1, n));
+    uint64_t z = 0x9E3779B97F4A7C15ull;
+    for (auto& v : h) {
+      z ^= z << 13;
+      z ^= z >> 7;
+      z ^= z << 17;
+      v = (double)(z >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+    }
+    BSD_HIP(hipMemcpy(x.p, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  const double* xp = static_cast<const double*>(x.p);
+  double* yp = static_cast<double*>(y.p);
+  // candidate schedules
+  std::vector<std::pair<GemmBuildOpts, GemmBuildOpts>> cand;
+  const GemmBuildOpts base64 = plan.opts64, basep = plan.opts_planes;
+  cand.push_back({base64, basep});
+  for (double tw : {4096.0, 8192.0, 16384.0, 32768.0})
+    for (int xcd = 0; xcd < 2; ++xcd)
+      for (int wm : {32, 64}) {
+        GemmBuildOpts a = base64, b = basep;
+        if (precision == 0) {
+          a.target_waves = tw;
+          a.xcd_order = xcd;
+          a.wave_max = wm;
+        } else {
+          if (wm == 32) continue;   // planes always use wave tiles
+          b.target_waves = tw;
+          b.xcd_order = xcd;
+        }
+        cand.push_back({a, b});
+      }
+  hipEvent_t e0, e1;
+  BSD_HIP(hipEventCreate(&e0));
+  BSD_HIP(hipEventCreate(&e1));
+  auto time_it = [&]() {
+    run_hpsi_graph(plan, xp, yp, s, precision);   // capture + warm-up
+    BSD_HIP(hipStreamSynchronize(s));
+    float best = 1e30f;
+    for (int r = 0; r < 5; ++r) {
+      BSD_HIP(hipEventRecord(e0, s));
+      run_hpsi_graph(plan, xp, yp, s, precision);
+      BSD_HIP(hipEventRecord(e1, s));
+      BSD_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      BSD_HIP(hipEventElapsedTime(&ms, e0, e1));
+      best = std::min(best, ms);
+    }
+    return (double)best;
+  };
+  TuneResult res;
+  res.n_candidates = (int)cand.size();
+  double best = 1e300;
+  for (size_t i = 0; i < cand.size(); ++i) {
+    rebuild_phase2(plan, cand[i].first, cand[i].second);
+    const double ms = time_it();
+    if (i == 0) res.default_ms = ms;
+    if (ms < best) {
+      best = ms;
+      res.best = (int)i;
+    }
+  }
+  rebuild_phase2(plan, cand[res.best].first, cand[res.best].second);
+  res.best_ms = best;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return res;
 }
 
 static GBases hpsi_bases(const HpsiPlan& plan, const double* psi, double* out) {

@@ -54,6 +54,10 @@ struct HpsiPlan {
   DevBuf planes, kmaps, split_tasks;
   size_t plane_bytes = 0;
   int n_split_psi = 0;                   // split tasks for psi (run first in every product)
+  // phase-2 problem lists per chunk (float64 and plane operands) and the build
+  // options of their current tile lists; the autotuner rebuilds from these
+  std::vector<std::vector<GemmProblem>> p1_probs, p2_probs, p2s_probs;
+  GemmBuildOpts opts64, opts_planes;
   std::unique_ptr<GemmPlan> diag_plan;   // diagonal of H_eff (rank-1 sector products)
   DevBuf ones, diag, dav_work;
   bool diag_ready = false;
@@ -72,6 +76,15 @@ void run_hpsi_graph(HpsiPlan& plan, const double* psi, double* out, hipStream_t 
 int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision, int cap,
                  double* ms, double* flops, double* bytes, int* kind);
 void zero_fill(double* p, int64_t n, hipStream_t s);
+// rebuild the phase-2 tile lists of every chunk with new schedule options
+void rebuild_phase2(HpsiPlan& plan, const GemmBuildOpts& o64, const GemmBuildOpts& oplanes);
+// time candidate schedules of phase 2 for `precision` on a scratch vector,
+// keep the fastest; returns its product time in milliseconds
+struct TuneResult {
+  double best_ms = 0.0, default_ms = 0.0;
+  int n_candidates = 0, best = 0;
+};
+TuneResult autotune_hpsi(HpsiPlan& plan, int precision, hipStream_t s);
 // diagonal of H_eff into the plan's own buffer (computed once per plan)
 const double* hpsi_diagonal(HpsiPlan& plan, hipStream_t s);
 

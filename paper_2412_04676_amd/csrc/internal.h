@@ -320,8 +320,12 @@ struct SplitTask {
 void launch_split_planes(const SplitTask* tasks, int n, const GBases& b, hipStream_t s);
 
 struct GemmBuildOpts {
-  bool wave_tiles = true;      // blocks up to 64 x 64 get wave tiles (float64 lists)
+  bool wave_tiles = true;      // float64 lists: blocks up to wave_max x wave_max get wave tiles
+  int wave_max = 64;
   bool split_k = true;         // cut long tiles so that every launch fills the device
+  double target_waves = 8192;  // split-K: about this many waves per launch ...
+  double min_part_work = 640;  // ... with parts of at least this work (sum of K + 16 per segment)
+  bool xcd_order = true;       // place problems of one locality group on one XCD
   bool plane_operands = false; // A and B are split-bf16 planes (wave tiles for every size)
   bool plane_output = false;   // C is written as split-bf16 planes of C^T (M a multiple of 8)
 };

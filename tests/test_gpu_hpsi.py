@@ -234,3 +234,26 @@ def test_renormalization_in_batches_matches_one_batch():
     assert rel(o2, o1) < 1e-12
     B.bsdmrg_destroy(ctx1)
     B.bsdmrg_destroy(ctx2)
+
+
+def test_autotune_keeps_the_product():
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    L, na, nb, D, site = 10, 5, 5, 100, 4
+    say("autotune L=10")
+    ctx, h, eri, dims, T = build_system(L, na, nb, D, site)
+    psi = psi_for(dims, site, 21)
+    ref, _ = hpsi_gpu(ctx, site, psi)
+    best, dflt, n = B.bsdmrg_hpsi_autotune(ctx, site, B.FP64)
+    say(f"  fp64: {n} candidates, default {dflt:.3f} ms, best {best:.3f} ms")
+    assert n > 1 and 0 < best <= dflt
+    out, _ = hpsi_gpu(ctx, site, psi)
+    assert rel(out, ref) < 1e-12
+    best, dflt, n = B.bsdmrg_hpsi_autotune(ctx, site, B.BF16X6)
+    lay = B.bsdmrg_psi_layout(ctx, site)
+    x = torch.from_numpy(B.psi_to_flat(psi, lay)).cuda()
+    y = torch.empty_like(x)
+    B.bsdmrg_hpsi(ctx, site, x, y, B.BF16X6)
+    torch.cuda.synchronize()
+    assert rel(B.flat_to_psi(y.cpu().numpy(), lay), ref) < 1e-6
+    B.bsdmrg_destroy(ctx)
