@@ -311,6 +311,7 @@ wave_gemm_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __rest
   const int seg0 = uni(tile.seg0), nseg = uni(tile.nseg);
   const int mt = min(TW, M - m0);
   const int nt = min(TW, N - n0);
+  const int ni = (mt + 15) >> 4, nj = (nt + 15) >> 4;   // 16 x 16 sub-tiles inside the block
   const int r16 = lane & 15, kq = lane >> 4;
   bool rowok[NI], colok[NI];
   int gi[NI], gj[NI];
@@ -354,7 +355,8 @@ wave_gemm_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __rest
         for (int i = 0; i < NI; ++i)
 #pragma unroll
           for (int j = 0; j < NI; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][i], b[st][j], acc[i][j], 0, 0, 0);
+            if (NI == 1 || (i < ni && j < nj))   // sub-tiles outside the block are skipped
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][i], b[st][j], acc[i][j], 0, 0, 0);
       }
       if (!more) break;
       si = nsi;

@@ -194,14 +194,17 @@ __device__ __forceinline__ float4_t mfma_bf16(u32x4_t a, u32x4_t b, float4_t c) 
 
 // smallest products first (the identity's m and l parts are zero); a
 // segment's first pass starts from zero instead of the running sum
+// Sub-tiles at or beyond (ni, nj) lie outside the block and are skipped
+// (wave-uniform bounds).
 template <int NI, int NPL, int NPROD>
 __device__ __forceinline__ void planes_mfma(const u32x4_t (&a)[NI][NPL], const u32x4_t (&b)[NI][NPL],
-                                            float4_t (&t)[NI][NI], bool fresh) {
+                                            float4_t (&t)[NI][NI], bool fresh, int ni = NI, int nj = NI) {
   const float4_t zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
+      if (NI > 1 && (i >= ni || j >= nj)) continue;
       float4_t c;
       if (NPROD == 6) {
         c = mfma_bf16(a[i][NPL - 1], b[j][0], fresh ? zero : t[i][j]);
@@ -311,6 +314,10 @@ planes_persistent_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GS
 
   float4_t t[NI][NI];
   acc_t acc[NI][NI];
+#pragma unroll
+  for (int i = 0; i < NI; ++i)
+#pragma unroll
+    for (int j = 0; j < NI; ++j) t[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
   auto clear_acc = [&]() {
 #pragma unroll
     for (int i = 0; i < NI; ++i)
@@ -444,12 +451,16 @@ wave_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __
     colok[i] = i * 16 + r16 < nt;
     gj[i] = n0 + i * 16 + r16;
   }
+  const int ni = (mt + 15) >> 4, nj = (nt + 15) >> 4;   // sub-tiles inside the block
   float4_t t[NI][NI];
   double4_t acc[NI][NI];
 #pragma unroll
   for (int i = 0; i < NI; ++i)
 #pragma unroll
-    for (int j = 0; j < NI; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NI; ++j) {
+      t[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+      acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    }
   auto flush = [&](double alpha) {
 #pragma unroll
     for (int i = 0; i < NI; ++i)
@@ -470,13 +481,13 @@ wave_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __
       const PSeg d1 = decode_step(gn, s + 1 < nseg);
       gn = ld_seg(segs, seg0 + min(s + 2, nseg - 1));
       load_step<NI, NPL>(d1, rowok, gi, colok, gj, q, a1, b1);
-      planes_mfma<NI, NPL, NPROD>(a0, b0, t, d0.fresh);
+      planes_mfma<NI, NPL, NPROD>(a0, b0, t, d0.fresh, ni, nj);
       if (d0.end) flush(d0.alpha);
       if (s + 1 >= nseg) break;
       d0 = decode_step(gn, s + 2 < nseg);
       gn = ld_seg(segs, seg0 + min(s + 3, nseg - 1));
       load_step<NI, NPL>(d0, rowok, gi, colok, gj, q, a0, b0);
-      planes_mfma<NI, NPL, NPROD>(a1, b1, t, d1.fresh);
+      planes_mfma<NI, NPL, NPROD>(a1, b1, t, d1.fresh, ni, nj);
       if (d1.end) flush(d1.alpha);
       if (s + 2 >= nseg) break;
     }
