@@ -156,8 +156,13 @@ typedef struct {
  * guess on entry (any nonzero vector) and the normalized eigenvector on return.
  * energy, iters, resid (host) receive the Ritz value, the iteration count and
  * the final residual norm; ritz (host, optional, cap entries) the lowest Ritz
- * value after every iteration.  opts == NULL uses the defaults.  Synchronizes
- * `stream` once per iteration (a 16-byte read of theta and |r|). */
+ * value after every iteration.  opts == NULL uses the defaults.  With a split
+ * precision the products run split until the residual reaches the product's
+ * noise level (4e-8 |theta| for BF16X6, 2e-5 |theta| for BF16X3), then the run
+ * restarts from that Ritz vector with float64 products down to tol (at least
+ * one float64 product): the energy and the residual returned are float64
+ * quantities, and iters counts both stages.  Synchronizes `stream` once per
+ * iteration (a 16-byte read of theta and |r|). */
 int bsdmrg_davidson(bsdmrg_ctx* ctx, int site, double* psi_dev, const bsdmrg_dav_opts* opts, double* energy,
                     int* iters, double* resid, double* ritz, int cap, bsdmrg_stream_t stream);
 

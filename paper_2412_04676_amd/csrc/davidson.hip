@@ -262,70 +262,88 @@ DavidsonResult davidson(HpsiPlan& plan, const double* diag, double* psi, const D
   plan.stage_out.reserve(std::max<int64_t>(1, n) * sizeof(double));
   double* sin = static_cast<double*>(plan.stage_in.p);
   double* sout = static_cast<double*>(plan.stage_out.p);
+  int prec = o.precision;
   auto H = [&](const double* in, double* out) {
     BSD_HIP(hipMemcpyAsync(sin, in, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-    run_hpsi_graph(plan, sin, sout, s, o.precision);
+    run_hpsi_graph(plan, sin, sout, s, prec);
     BSD_HIP(hipMemcpyAsync(out, sout, n * sizeof(double), hipMemcpyDeviceToDevice, s));
   };
   auto normalize_into = [&](const double* in, double* out) {
     dots(w, in, 1, in, w.sc + 2, s);
     hipLaunchKernelGGL(scale_by_inv_kernel, dim3(G), dim3(256), 0, s, in, w.sc + 2, out, n);
   };
-  // first vector
-  normalize_into(psi, w.V);
-  H(w.V, w.W);
-  int k = 1;
-  dots(w, w.V, 1, w.W, w.d, s);
-  hipLaunchKernelGGL(set_col_kernel, dim3(1), dim3(32), 0, s, w.S, 0, 1, w.d);
   double theta = 0.0, rn = 0.0;
-  int it = 0;
-  for (; it < o.max_iter; ++it) {
-    hipLaunchKernelGGL(small_eig_kernel, dim3(1), dim3(64), 0, s, w.S, k, w.ev, w.Y, w.sc);
-    hipLaunchKernelGGL(column_kernel, dim3(1), dim3(32), 0, s, w.Y, k, 0, w.d);
-    hipLaunchKernelGGL(combine_kernel, dim3(G), dim3(256), 0, s, w.V, n, k, w.d, 0.0, 1.0, w.x, n);
-    hipLaunchKernelGGL(combine_kernel, dim3(G), dim3(256), 0, s, w.W, n, k, w.d, 0.0, 1.0, w.hx, n);
-    hipLaunchKernelGGL(residual_kernel, dim3(G), dim3(256), 0, s, w.x, w.hx, diag, w.sc, o.precond_floor, o.precond,
-                       w.r, w.t, n);
-    dots(w, w.r, 1, w.r, w.sc + 1, s);
-    double hs[2];
-    BSD_HIP(hipMemcpyAsync(hs, w.sc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-    BSD_HIP(hipStreamSynchronize(s));
-    theta = hs[0];
-    rn = std::sqrt(std::max(0.0, hs[1]));
-    res.ritz.push_back(theta);
-    if (rn <= o.tol) break;
-    if (k == M) {
-      // thick restart: keep the R lowest Ritz vectors (and their products)
-      hipLaunchKernelGGL(rotate_kernel, dim3(G), dim3(256), 0, s, w.V, n, k, w.Y, R, w.tmp, n);
-      BSD_HIP(hipMemcpyAsync(w.V, w.tmp, R * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-      hipLaunchKernelGGL(rotate_kernel, dim3(G), dim3(256), 0, s, w.W, n, k, w.Y, R, w.tmp, n);
-      BSD_HIP(hipMemcpyAsync(w.W, w.tmp, R * n * sizeof(double), hipMemcpyDeviceToDevice, s));
-      k = R;
-      // projected matrix becomes diagonal in the Ritz basis
-      std::vector<double> Sh(32 * 32, 0.0), evh(32);
-      BSD_HIP(hipMemcpyAsync(evh.data(), w.ev, 32 * sizeof(double), hipMemcpyDeviceToHost, s));
+  int total = 0;
+  // one Davidson run from psi with products at `prec`; stops when the residual
+  // is below tol (rel_floor * |theta| counts too: the noise level of a split
+  // product) or after max_it iterations; leaves the Ritz vector in psi
+  auto solve = [&](double tol, double rel_floor, int max_it) {
+    normalize_into(psi, w.V);
+    H(w.V, w.W);
+    int k = 1;
+    dots(w, w.V, 1, w.W, w.d, s);
+    hipLaunchKernelGGL(set_col_kernel, dim3(1), dim3(32), 0, s, w.S, 0, 1, w.d);
+    int it = 0;
+    for (; it < max_it; ++it) {
+      hipLaunchKernelGGL(small_eig_kernel, dim3(1), dim3(64), 0, s, w.S, k, w.ev, w.Y, w.sc);
+      hipLaunchKernelGGL(column_kernel, dim3(1), dim3(32), 0, s, w.Y, k, 0, w.d);
+      hipLaunchKernelGGL(combine_kernel, dim3(G), dim3(256), 0, s, w.V, n, k, w.d, 0.0, 1.0, w.x, n);
+      hipLaunchKernelGGL(combine_kernel, dim3(G), dim3(256), 0, s, w.W, n, k, w.d, 0.0, 1.0, w.hx, n);
+      hipLaunchKernelGGL(residual_kernel, dim3(G), dim3(256), 0, s, w.x, w.hx, diag, w.sc, o.precond_floor,
+                         o.precond, w.r, w.t, n);
+      dots(w, w.r, 1, w.r, w.sc + 1, s);
+      double hs[2];
+      BSD_HIP(hipMemcpyAsync(hs, w.sc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
       BSD_HIP(hipStreamSynchronize(s));
-      for (int i = 0; i < k; ++i) Sh[i * 32 + i] = evh[i];
-      BSD_HIP(hipMemcpyAsync(w.S, Sh.data(), Sh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      theta = hs[0];
+      rn = std::sqrt(std::max(0.0, hs[1]));
+      res.ritz.push_back(theta);
+      if (rn <= std::max(tol, rel_floor * std::fabs(theta))) break;
+      if (k == M) {
+        // thick restart: keep the R lowest Ritz vectors (and their products)
+        hipLaunchKernelGGL(rotate_kernel, dim3(G), dim3(256), 0, s, w.V, n, k, w.Y, R, w.tmp, n);
+        BSD_HIP(hipMemcpyAsync(w.V, w.tmp, R * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(rotate_kernel, dim3(G), dim3(256), 0, s, w.W, n, k, w.Y, R, w.tmp, n);
+        BSD_HIP(hipMemcpyAsync(w.W, w.tmp, R * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        k = R;
+        // projected matrix becomes diagonal in the Ritz basis
+        std::vector<double> Sh(32 * 32, 0.0), evh(32);
+        BSD_HIP(hipMemcpyAsync(evh.data(), w.ev, 32 * sizeof(double), hipMemcpyDeviceToHost, s));
+        BSD_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < k; ++i) Sh[i * 32 + i] = evh[i];
+        BSD_HIP(hipMemcpyAsync(w.S, Sh.data(), Sh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+      }
+      // two passes of Gram-Schmidt against V
+      for (int pass = 0; pass < 2; ++pass) {
+        dots(w, w.V, k, w.t, w.d, s);
+        hipLaunchKernelGGL(combine_kernel, dim3(G), dim3(256), 0, s, w.V, n, k, w.d, 1.0, -1.0, w.t, n);
+      }
+      double* vk = w.V + (int64_t)k * n;
+      normalize_into(w.t, vk);
+      H(vk, w.W + (int64_t)k * n);
+      ++k;
+      dots(w, w.V, k, w.W + (int64_t)(k - 1) * n, w.d, s);
+      hipLaunchKernelGGL(set_col_kernel, dim3(1), dim3(32), 0, s, w.S, k - 1, k, w.d);
     }
-    // two passes of Gram-Schmidt against V
-    for (int pass = 0; pass < 2; ++pass) {
-      dots(w, w.V, k, w.t, w.d, s);
-      hipLaunchKernelGGL(combine_kernel, dim3(G), dim3(256), 0, s, w.V, n, k, w.d, 1.0, -1.0, w.t, n);
-    }
-    double* vk = w.V + (int64_t)k * n;
-    normalize_into(w.t, vk);
-    H(vk, w.W + (int64_t)k * n);
-    ++k;
-    dots(w, w.V, k, w.W + (int64_t)(k - 1) * n, w.d, s);
-    hipLaunchKernelGGL(set_col_kernel, dim3(1), dim3(32), 0, s, w.S, k - 1, k, w.d);
+    // eigenvector into psi (x is normalized up to rounding: renormalize)
+    normalize_into(w.x, psi);
+    total += std::min(it + 1, max_it);
+  };
+  if (o.precision == 0) {
+    solve(o.tol, 0.0, o.max_iter);
+  } else {
+    // split-bf16 products down to their noise level (relative product error
+    // about 5e-8 for six products, 5e-6 for three), then float64 products from
+    // the Ritz vector: the energy and the residual are float64 quantities
+    const double eps = o.precision == 2 ? 5e-8 : 5e-6;
+    solve(o.tol, 4.0 * eps, o.max_iter);
+    prec = 0;
+    solve(o.tol, 0.0, std::max(1, o.max_iter - total));
   }
-  // eigenvector into psi (x is normalized up to rounding: renormalize)
-  normalize_into(w.x, psi);
   BSD_HIP(hipStreamSynchronize(s));
   res.energy = theta;
   res.resid = rn;
-  res.iters = it + 1;
+  res.iters = total;
   return res;
 }
 

@@ -73,3 +73,28 @@ def test_heff_diagonal_matches_dense():
         ref[i] = B.psi_to_flat(dense.apply(B.flat_to_psi(e, lay)), lay)[i]
     assert np.abs(got - ref).max() < 1e-11 * np.abs(ref).max()
     B.bsdmrg_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_split_precision_davidson_reaches_float64_energy(precision):
+    # split products down to their noise level, then float64 products: the
+    # energy must match the oracle's Lanczos value as the float64 run does
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    L, na, nb, D, site = 10, 5, 5, 100, 4
+    say(f"split davidson precision {precision}")
+    ctx, h, eri, dims, T = build_system(L, na, nb, D, site)
+    op = oracle_op(h, eri, T, L, na, nb, site)
+    psi0 = psi_for(dims, site, 5)
+    keys = sorted(psi0)
+    shapes = [psi0[k].shape for k in keys]
+    n = sum(a * b for a, b in shapes)
+    A = sla.LinearOperator((n, n), matvec=lambda v: flatten(op.apply(unflatten(v, keys, shapes)), keys), dtype=float)
+    w, V = sla.eigsh(A, k=1, which="SA", tol=1e-13, v0=flatten(psi0, keys))
+    lay = B.bsdmrg_psi_layout(ctx, site)
+    x = torch.from_numpy(B.psi_to_flat(psi0, lay)).cuda()
+    e, it, r, ritz = B.bsdmrg_davidson(ctx, site, x, tol=1e-9, max_iter=300, precond=1, precision=precision)
+    say(f"  E {e:.12f} oracle {w[0]:.12f} iters {it} resid {r:.2e}")
+    assert abs(e - w[0]) < 1e-9
+    assert r < 1e-9
+    B.bsdmrg_destroy(ctx)
