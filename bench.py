@@ -289,7 +289,8 @@ def main():
     torch.cuda.synchronize()
     xs = x.clone()
     t0 = time.time()
-    e_dav, it_dav, r_dav, _ = B.bsdmrg_davidson(ctx, site, xs, max_iter=40, tol=1e-8, precond=1, stream=stream)
+    e_dav, it_dav, r_dav, _ = B.bsdmrg_davidson(ctx, site, xs, max_iter=40, tol=1e-8, precond=1,
+                                                precision=chosen, stream=stream)
     torch.cuda.synchronize()
     t_dav = time.time() - t0
     t0 = time.time()
@@ -328,7 +329,8 @@ def main():
         "speedup_bf16x6_vs_fp64": res[B.FP64][0] / res[B.BF16X6][0],
         "autotune": {name: tuned[p] for name, p in (("fp64", B.FP64), ("bf16x3", B.BF16X3), ("bf16x6", B.BF16X6))},
         "roofline": roof,
-        "site_step": {"davidson_iters": it_dav, "davidson_ms": t_dav * 1e3, "energy": e_dav,
+        "site_step": {"davidson_precision": {0: "fp64", 1: "bf16x3", 2: "bf16x6"}[chosen],
+                      "davidson_iters": it_dav, "davidson_ms": t_dav * 1e3, "energy": e_dav,
                       "residual": r_dav, "truncate_ms": t_tr * 1e3, "kept": kept, "trunc_err": err_tr,
                       "renormalize_ms": t_ren * 1e3},
         "serializer": {"bytes": nbytes, "pack_ms": t_pack * 1e3, "pack_hbm_GBps": pack_gbs,
