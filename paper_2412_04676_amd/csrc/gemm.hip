@@ -244,75 +244,108 @@ grouped_gemm_bf16_kernel(const GTile* __restrict__ tiles, const GSeg* __restrict
 // ---------------------------------------------------------------- wave tiles
 // For small sector blocks (at most 64 x 64) the K dimension arrives in many
 // short segments, so LDS staging and workgroup barriers per segment would
-// dominate.  Here every wave owns one TW x TW output tile (TW = 16 or 32),
-// loads its MFMA operands straight from global memory / L2 (lane l holds
-// A[l % 16][k + l / 16] and B[k + l / 16][l % 16]) and never synchronizes; a
-// workgroup is four independent waves.
+// dominate.  Here every wave owns one TW x TW output tile (TW = 16 or 32) and
+// never synchronizes; a workgroup is four independent waves.  The host cuts
+// the segments into steps of 16 values of K.  Per step a lane (r, q) (r =
+// lane % 16, q = lane / 16) feeds MFMA step s with A[r][4 s + q] (times alpha)
+// and B[4 s + q][r]; operands come through buffer loads (lanes outside the
+// tile or past K get an offset beyond the buffer and read zeros), descriptors
+// through scalar loads two steps ahead, and two operand sets alternate.
+typedef __attribute__((address_space(4))) const GSeg* cseg64_ptr;
+typedef __attribute__((address_space(4))) const GTile* ctile64_ptr;
+constexpr unsigned kOut64 = 0x80000000u;   // byte offset past every operand buffer
+constexpr int kRawFlags = 0x00020000;      // raw buffer, 32-bit data
 
-// wave-uniform view of one K-segment
-struct WSeg {
-  const double* A;
-  const double* B;
-  int64_t lda, ldb;
-  int K, flags;
+__device__ __forceinline__ GSeg ld_seg64(cseg64_ptr p, int i) {
+  GSeg g;
+  g.A = p[i].A;
+  g.B = p[i].B;
+  g.lda = p[i].lda;
+  g.ldb = p[i].ldb;
+  g.K = p[i].K;
+  g.flags = p[i].flags;
+  g.alpha = p[i].alpha;
+  return g;
+}
+__device__ __forceinline__ GTile ld_tile64(ctile64_ptr p, int i) {
+  GTile t;
+  t.C = p[i].C;
+  t.ldc = p[i].ldc;
+  t.M = p[i].M;
+  t.N = p[i].N;
+  t.m0 = p[i].m0;
+  t.n0 = p[i].n0;
+  t.seg0 = p[i].seg0;
+  t.nseg = p[i].nseg;
+  t.beta = p[i].beta;
+  return t;
+}
+
+struct WStep {
+  __amdgpu_buffer_rsrc_t ra, rb;
+  int ai, ak, bk, bj;   // element strides of A along (row, k) and of B along (k, column)
+  int K;                // values of K left from this step (<= 0: empty step)
+  int kbase;            // first K index of the step (identity operand)
+  bool ident;
   double alpha;
 };
 
-__device__ __forceinline__ WSeg load_wseg(const GSeg* __restrict__ segs, int idx, const GBases& bases) {
-  const GSeg g = segs[idx];
-  WSeg w;
-  w.A = resolve((uint64_t)uni64((int64_t)g.A), bases);
-  w.B = resolve((uint64_t)uni64((int64_t)g.B), bases);
-  w.lda = uni64(g.lda);
-  w.ldb = uni64(g.ldb);
-  w.K = uni(g.K);
-  w.flags = uni(g.flags);
-  w.alpha = unid(g.alpha);
+__device__ __forceinline__ WStep decode64(const GSeg& g, bool valid, const GBases& bases) {
+  WStep w;
+  w.ra = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(resolve(g.A, bases)), (short)0, 0x7FFFFFFF, kRawFlags);
+  w.rb = __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(resolve(g.B, bases)), (short)0, 0x7FFFFFFF, kRawFlags);
+  const bool ta = g.flags & kTransA, tb = g.flags & kTransB;
+  w.ai = ta ? 1 : (int)g.lda;
+  w.ak = ta ? (int)g.lda : 1;
+  w.bk = tb ? 1 : (int)g.ldb;
+  w.bj = tb ? (int)g.ldb : 1;
+  w.K = valid ? g.K : 0;
+  w.kbase = (g.flags >> kStepPassShift) * 16;
+  w.ident = g.flags & kIdentA;
+  w.alpha = g.alpha;
   return w;
 }
 
-// operands of one pass (16 values of K) for this lane
 template <int NI>
-__device__ __forceinline__ void load_pass(const WSeg& sg, int k0, const bool* rowok, const int* gi,
-                                          const bool* colok, const int* gj, int kq, double (&a)[4][NI],
-                                          double (&b)[4][NI]) {
-  const bool ta = sg.flags & kTransA, tb = sg.flags & kTransB, ia = sg.flags & kIdentA;
+__device__ __forceinline__ void load_step64(const WStep& d, const bool* rowok, const int* gi, const bool* colok,
+                                            const int* gj, int q, double (&a)[4][NI], double (&b)[4][NI]) {
 #pragma unroll
   for (int st = 0; st < 4; ++st) {
-    const int k = k0 + 4 * st + kq;
-    const bool kok = k < sg.K;
+    const int k = 4 * st + q;
+    const bool kok = k < d.K;
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-      double v = 0.0;
-      if (rowok[i] && kok) {
-        if (ia) v = (gi[i] == k) ? sg.alpha : 0.0;
-        else v = sg.alpha * (ta ? sg.A[(int64_t)k * sg.lda + gi[i]] : sg.A[(int64_t)gi[i] * sg.lda + k]);
+      if (d.ident) {
+        a[st][i] = (rowok[i] && kok && gi[i] == d.kbase + k) ? d.alpha : 0.0;
+      } else {
+        const unsigned o = (rowok[i] && kok) ? (unsigned)(gi[i] * d.ai + k * d.ak) * 8u : kOut64;
+        a[st][i] = d.alpha * __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(d.ra, o, 0, 0));
       }
-      a[st][i] = v;
     }
 #pragma unroll
     for (int j = 0; j < NI; ++j) {
-      double v = 0.0;
-      if (colok[j] && kok) v = tb ? sg.B[(int64_t)gj[j] * sg.ldb + k] : sg.B[(int64_t)k * sg.ldb + gj[j]];
-      b[st][j] = v;
+      const unsigned o = (colok[j] && kok) ? (unsigned)(k * d.bk + gj[j] * d.bj) * 8u : kOut64;
+      b[st][j] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(d.rb, o, 0, 0));
     }
   }
 }
 
 template <int TW>
 __global__ void __launch_bounds__(256)
-wave_gemm_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __restrict__ segs, GBases bases) {
+wave_gemm_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __restrict__ segs_g, GBases bases) {
   constexpr int NI = TW / 16;
+  const cseg64_ptr segs = (cseg64_ptr)segs_g;
+  const ctile64_ptr tiles = (ctile64_ptr)tiles_g;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int ti = uni(blockIdx.x * 4 + wave);
   if (ti >= ntiles) return;
-  const GTile tile = tiles[ti];
-  const int M = uni(tile.M), N = uni(tile.N), m0 = uni(tile.m0), n0 = uni(tile.n0);
-  const int seg0 = uni(tile.seg0), nseg = uni(tile.nseg);
+  const GTile tile = ld_tile64(tiles, ti);
+  const int M = tile.M, N = tile.N, m0 = tile.m0, n0 = tile.n0;
+  const int seg0 = tile.seg0, nseg = tile.nseg;
   const int mt = min(TW, M - m0);
   const int nt = min(TW, N - n0);
   const int ni = (mt + 15) >> 4, nj = (nt + 15) >> 4;   // 16 x 16 sub-tiles inside the block
-  const int r16 = lane & 15, kq = lane >> 4;
+  const int r16 = lane & 15, q = lane >> 4;
   bool rowok[NI], colok[NI];
   int gi[NI], gj[NI];
 #pragma unroll
@@ -327,49 +360,35 @@ wave_gemm_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __rest
   for (int i = 0; i < NI; ++i)
 #pragma unroll
     for (int j = 0; j < NI; ++j) acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+  auto mfma = [&](const double (&a)[4][NI], const double (&b)[4][NI], int nst) {
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      if (st >= nst) break;
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int j = 0; j < NI; ++j)
+          if (NI == 1 || (i < ni && j < nj))   // sub-tiles outside the block are skipped
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][i], b[st][j], acc[i][j], 0, 0, 0);
+    }
+  };
 
-  // software pipeline over the flattened (segment, pass) sequence: the operands
-  // of the next pass are in flight while the MFMAs of the current one run
   if (nseg > 0) {
-    int si = 0, k0 = 0;
-    WSeg cur = load_wseg(segs, seg0, bases);
-    double a[4][NI], b[4][NI], an[4][NI], bn[4][NI];
-    load_pass<NI>(cur, 0, rowok, gi, colok, gj, kq, a, b);
-    int cur_nst = min(4, (cur.K + 3) / 4);
-    while (true) {
-      // next pass
-      int nsi = si, nk0 = k0 + 16;
-      WSeg nxt = cur;
-      bool more = true;
-      if (nk0 >= cur.K) {
-        nsi = si + 1;
-        nk0 = 0;
-        if (nsi < nseg) nxt = load_wseg(segs, seg0 + nsi, bases);
-        else more = false;
-      }
-      if (more) load_pass<NI>(nxt, nk0, rowok, gi, colok, gj, kq, an, bn);
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        if (st >= cur_nst) break;
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-#pragma unroll
-          for (int j = 0; j < NI; ++j)
-            if (NI == 1 || (i < ni && j < nj))   // sub-tiles outside the block are skipped
-              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st][i], b[st][j], acc[i][j], 0, 0, 0);
-      }
-      if (!more) break;
-      si = nsi;
-      k0 = nk0;
-      cur = nxt;
-      cur_nst = min(4, (cur.K - k0 + 3) / 4);
-#pragma unroll
-      for (int st = 0; st < 4; ++st)
-#pragma unroll
-        for (int i = 0; i < NI; ++i) {
-          a[st][i] = an[st][i];
-          b[st][i] = bn[st][i];
-        }
+    double a0[4][NI], b0[4][NI], a1[4][NI], b1[4][NI];
+    WStep d0 = decode64(ld_seg64(segs, seg0), true, bases);
+    GSeg gn = ld_seg64(segs, seg0 + min(1, nseg - 1));
+    load_step64<NI>(d0, rowok, gi, colok, gj, q, a0, b0);
+    for (int s = 0;; s += 2) {
+      const WStep d1 = decode64(gn, s + 1 < nseg, bases);
+      gn = ld_seg64(segs, seg0 + min(s + 2, nseg - 1));
+      load_step64<NI>(d1, rowok, gi, colok, gj, q, a1, b1);
+      mfma(a0, b0, min(4, (d0.K + 3) >> 2));
+      if (s + 1 >= nseg) break;
+      d0 = decode64(gn, s + 2 < nseg, bases);
+      gn = ld_seg64(segs, seg0 + min(s + 3, nseg - 1));
+      load_step64<NI>(d0, rowok, gi, colok, gj, q, a0, b0);
+      mfma(a1, b1, min(4, (d1.K + 3) >> 2));
+      if (s + 2 >= nseg) break;
     }
   }
   double* C = const_cast<double*>(resolve(tile.C, bases));
@@ -380,7 +399,8 @@ wave_gemm_kernel(const GTile* __restrict__ tiles, int ntiles, const GSeg* __rest
     for (int j = 0; j < NI; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = i * 16 + 4 * v + kq;
+        // f64 16x16x4 output: accumulator register v of lane l holds row 4 v + l / 16
+        const int r = i * 16 + 4 * v + q;
         const int c = j * 16 + r16;
         if (r < mt && c < nt) {
           double* p = C + (int64_t)r * tile.ldc + c;
@@ -703,6 +723,37 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
     }
     sg.swap(steps);
   }
+  if (!plane_operands && count[4] + count[5] > 0) {
+    // float64 wave tiles: steps of 16 values of K; a step's K counts the values
+    // left from its start, the pass index rides in the flags (identity operand)
+    std::vector<GSeg> st;
+    std::vector<int> first_step(sg.size() + 1);
+    for (size_t si = 0; si < sg.size(); ++si) {
+      first_step[si] = (int)st.size();
+      const GSeg& g = sg[si];
+      const int npass = (g.K + 15) / 16;
+      for (int p = 0; p < npass; ++p) {
+        GSeg x = g;
+        x.K = g.K - 16 * p;
+        x.flags = (g.flags & (kTransA | kTransB | kIdentA)) | (p << kStepPassShift);
+        const uint64_t da = (uint64_t)(16 * p) * ((g.flags & kTransA) ? (uint64_t)g.lda : 1u) * sizeof(double);
+        const uint64_t db = (uint64_t)(16 * p) * ((g.flags & kTransB) ? 1u : (uint64_t)g.ldb) * sizeof(double);
+        if (!(g.flags & kIdentA)) x.A += da;
+        x.B += db;
+        st.push_back(x);
+      }
+    }
+    first_step[sg.size()] = (int)st.size();
+    for (int c = 4; c <= 5; ++c)
+      for (int i = first[c]; i < first[c] + count[c]; ++i) {
+        GTile& x = all[i];
+        const int a = first_step[x.seg0], b = first_step[x.seg0 + x.nseg];
+        x.seg0 = a;
+        x.nseg = b - a;
+      }
+    steps.reserve(std::max<size_t>(1, st.size()) * sizeof(GSeg));
+    if (!st.empty()) BSD_HIP(hipMemcpy(steps.p, st.data(), st.size() * sizeof(GSeg), hipMemcpyHostToDevice));
+  }
   if (ws_elems > 0) parts.reserve(ws_elems * sizeof(double));
   double* ws = static_cast<double*>(parts.p);
   for (size_t i = 0; i < all.size(); ++i)
@@ -727,8 +778,10 @@ void GemmPlan::launch_shape_class(int c, const GBases& bases, hipStream_t s, int
     return;
   }
   BSD_CHECK(!(wave && count[4] + count[5] > 0 && precision != 0), 1, "float64 tile list launched at split precision");
-  launch_grouped_gemm(static_cast<const GTile*>(tiles.p) + first[c], count[c], c,
-                      static_cast<const GSeg*>(segs.p), bases, s, precision);
+  // wave classes read the 16-K steps, workgroup classes the segments
+  const void* sp = (c == 4 || c == 5) ? steps.p : segs.p;
+  launch_grouped_gemm(static_cast<const GTile*>(tiles.p) + first[c], count[c], c, static_cast<const GSeg*>(sp),
+                      bases, s, precision);
 }
 
 void GemmPlan::launch_reduce(const GBases& bases, hipStream_t s) const {

@@ -339,6 +339,9 @@ struct GemmPlan {
   // of C, ldc in chunks), the operand layout of a following planes product.
   bool planes = false, planes_out = false;
   DevBuf tiles, segs;
+  // float64 wave-tile classes read their segments as steps of 16 values of K
+  // (pointers advanced, K counted from the step, identity offset in the flags)
+  DevBuf steps;
   // split-K: parts of long tiles write workspace slots, summed by one reduction
   DevBuf parts, reduces;
   int nreduce = 0;
