@@ -91,8 +91,16 @@ int bsdmrg_set_site_tensor(bsdmrg_ctx* ctx, int site, int n_blocks, const int32_
  * three-operator complementary operators).  side = BSDMRG_RIGHT: blocks for bonds
  * L..bond from the right site tensors bond..L-1 (right blocks keep H, a+_r and
  * the complementary operators S_x, P_pq, Q_pq of every spin-orbital to their
- * left).  Already built blocks are kept.  Synchronizes `stream`. */
+ * left).  Growth starts from the nearest existing block on the way to `bond`;
+ * built blocks are kept.  Synchronizes `stream`. */
 int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream);
+
+/* Free a renormalized block (0 < bond < L; the vacuum blocks stay) and every
+ * prepared product plan; a later bsdmrg_build_env rebuilds the block when it
+ * is needed.  Lets a caller keep only the blocks at the front of a growing
+ * environment on the device.  EBUSY while an offload of the block is in
+ * flight.  Synchronizes the device. */
+int bsdmrg_drop_block(bsdmrg_ctx* ctx, int side, int bond);
 
 /* Device workspace budget of one renormalization step (bytes, default 8 GiB):
  * the new block's operators are produced in batches whose aggregated operators

@@ -60,6 +60,7 @@ _SIGS = {
     "bsdmrg_set_site_tensor": ([c_vp, c_int, c_int, c_vp, c_vp], c_int),
     "bsdmrg_build_env": ([c_vp, c_int, c_int, c_vp], c_int),
     "bsdmrg_set_renorm_workspace": ([c_vp, c_sz], c_int),
+    "bsdmrg_drop_block": ([c_vp, c_int, c_int], c_int),
     "bsdmrg_psi_layout": ([c_vp, c_int, ctypes.POINTER(c_int), c_i64p, c_vp, c_vp], c_int),
     "bsdmrg_hpsi_prepare": ([c_vp, c_int, c_int, c_sz, c_vp], c_int),
     "bsdmrg_hpsi": ([c_vp, c_int, c_vp, c_vp, c_int, c_vp], c_int),
@@ -150,6 +151,10 @@ def site_tensor_arrays(tensor):
 def bsdmrg_set_site_tensor(ctx, site, tensor):
     meta, data = site_tensor_arrays(tensor)
     _check(_lib.bsdmrg_set_site_tensor(ctx, site, len(meta), _ptr(meta), _ptr(data)))
+
+
+def bsdmrg_drop_block(ctx, side, bond):
+    _check(_lib.bsdmrg_drop_block(ctx, side, bond))
 
 
 def bsdmrg_set_renorm_workspace(ctx, nbytes):

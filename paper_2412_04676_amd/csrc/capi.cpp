@@ -281,9 +281,11 @@ int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream
     Ctx& c = ctx->c;
     BSD_CHECK(c.have_ints, BSDMRG_ESTATE, "integrals not loaded");
     BSD_CHECK(bond >= 0 && bond <= c.L, BSDMRG_EINVAL, "bond out of range");
+    // grow from the nearest block that exists on the way to `bond`
     if (side == BSDMRG_LEFT) {
-      for (int b = 0; b < bond; ++b) {
-        if (get_block(c, true, b + 1)) continue;
+      int b0 = bond;
+      while (b0 > 0 && !get_block(c, true, b0)) --b0;
+      for (int b = b0; b < bond; ++b) {
         BSD_CHECK(c.sites[b].set, BSDMRG_ESTATE, "site tensor missing");
         Block* cur = get_block(c, true, b);
         BSD_CHECK(cur && cur->resident, BSDMRG_EBUSY, "source block not resident");
@@ -291,8 +293,9 @@ int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream
       }
     } else {
       BSD_CHECK(side == BSDMRG_RIGHT, BSDMRG_EINVAL, "side must be LEFT or RIGHT");
-      for (int b = c.L; b > bond; --b) {
-        if (get_block(c, false, b - 1)) continue;
+      int b0 = bond;
+      while (b0 < c.L && !get_block(c, false, b0)) ++b0;
+      for (int b = b0; b > bond; --b) {
         BSD_CHECK(c.sites[b - 1].set, BSDMRG_ESTATE, "site tensor missing");
         Block* cur = get_block(c, false, b);
         BSD_CHECK(cur && cur->resident, BSDMRG_EBUSY, "source block not resident");
@@ -300,6 +303,23 @@ int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream
       }
     }
     BSD_HIP(hipStreamSynchronize(S(stream)));
+  });
+}
+
+int bsdmrg_drop_block(bsdmrg_ctx* ctx, int side, int bond) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    Ctx& c = ctx->c;
+    BSD_CHECK(side == BSDMRG_LEFT || side == BSDMRG_RIGHT, BSDMRG_EINVAL, "side must be LEFT or RIGHT");
+    const bool left = side == BSDMRG_LEFT;
+    BSD_CHECK(bond > 0 && bond < c.L, BSDMRG_EINVAL, "bond out of range (the vacuum blocks stay)");
+    auto& m = left ? c.left : c.right;
+    auto it = m.find(bond);
+    if (it == m.end()) return;
+    BSD_CHECK(!it->second->offload_pending, BSDMRG_EBUSY, "offload in flight; wait first");
+    BSD_HIP(hipDeviceSynchronize());
+    c.plans.clear();   // plans may reference the block
+    m.erase(it);
   });
 }
 

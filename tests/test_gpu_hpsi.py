@@ -257,3 +257,44 @@ def test_autotune_keeps_the_product():
     torch.cuda.synchronize()
     assert rel(B.flat_to_psi(y.cpu().numpy(), lay), ref) < 1e-6
     B.bsdmrg_destroy(ctx)
+
+
+def test_dropped_blocks_are_rebuilt_from_the_nearest_one():
+    from paper_2412_04676_amd import bsdmrg as B
+    L, na, nb, D, site = 10, 5, 5, 100, 4
+    say("drop blocks L=10")
+    ctx1, h, eri, dims, T = build_system(L, na, nb, D, site)
+    ctx2, *_ = build_system(L, na, nb, D, site, build=False)
+    # keep only the front of each environment, then grow it by one bond
+    B.bsdmrg_build_env(ctx2, B.LEFT, site - 1)
+    B.bsdmrg_build_env(ctx2, B.RIGHT, site + 3)
+    for b in range(1, site - 1):
+        B.bsdmrg_drop_block(ctx2, B.LEFT, b)
+    for b in range(site + 4, L):
+        B.bsdmrg_drop_block(ctx2, B.RIGHT, b)
+    B.bsdmrg_drop_block(ctx2, B.LEFT, 8)          # absent: no-op
+    B.bsdmrg_build_env(ctx2, B.LEFT, site)
+    B.bsdmrg_build_env(ctx2, B.RIGHT, site + 2)
+    for side, bond, keys in ((B.LEFT, site, [("H",), ("c", 3), ("A", 1, 4), ("S", 12)]),
+                             (B.RIGHT, site + 2, [("H",), ("c", 15), ("P", 1, 6), ("Q", 2, 7)])):
+        for k in keys:
+            a = list(k[1:]) + [-1, -1]
+            g1 = B.bsdmrg_get_block_op(ctx1, side, bond, k[0], *a[:2])
+            g2 = B.bsdmrg_get_block_op(ctx2, side, bond, k[0], *a[:2])
+            assert g1.keys() == g2.keys(), k
+            for q in g1:
+                assert np.abs(g1[q] - g2[q]).max() < 1e-12 * max(1.0, float(np.abs(g1[q]).max())), (side, k, q)
+    psi = psi_for(dims, site, 5)
+    ref, _ = hpsi_gpu(ctx1, site, psi)
+    out, _ = hpsi_gpu(ctx2, site, psi)
+    assert rel(out, ref) < 1e-12
+    # drop the whole left environment: it is rebuilt from bond 0
+    for b in range(1, site + 1):
+        B.bsdmrg_drop_block(ctx2, B.LEFT, b)
+    B.bsdmrg_build_env(ctx2, B.LEFT, site)
+    out, _ = hpsi_gpu(ctx2, site, psi)
+    assert rel(out, ref) < 1e-12
+    with pytest.raises(RuntimeError):
+        B.bsdmrg_drop_block(ctx2, B.LEFT, 0)
+    B.bsdmrg_destroy(ctx1)
+    B.bsdmrg_destroy(ctx2)
