@@ -108,6 +108,12 @@ int bsdmrg_drop_block(bsdmrg_ctx* ctx, int side, int bond);
  * later bsdmrg_build_env calls.  EINVAL for 0. */
 int bsdmrg_set_renorm_workspace(bsdmrg_ctx* ctx, size_t bytes);
 
+/* Running totals of the renormalization steps done so far (Sec. II.B step 4):
+ * useful flops of the grouped-GEMM phases (2mnk per product), wall seconds,
+ * the part of them spent between each launch and its stream synchronization,
+ * and the step count.  Any pointer may be NULL. */
+int bsdmrg_renorm_stats(bsdmrg_ctx* ctx, double* flops, double* wall_s, double* device_s, int64_t* steps);
+
 /* Layout of the two-site wave function at sites (site, site+1), between the
  * left block of bond `site` and the right block of bond site+2.  With meta ==
  * NULL only *n_blocks and *n_elems are returned.  Otherwise meta (host, cap >=

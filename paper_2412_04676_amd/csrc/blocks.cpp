@@ -2,6 +2,7 @@
 // (Sec. II.B: the enlarged block's operators are mapped to the new basis and
 // kept for later steps).  Operators of one block that share a quantum-number
 // change dq share one skeleton and live as layers of one family (Fig. 4a).
+#include <chrono>
 #include "ctx.h"
 
 #include <algorithm>
@@ -242,8 +243,14 @@ static Operand ref_block(const Block& blk, const Ref& r, const std::vector<AggOp
   return o;
 }
 
+static double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
   BSD_CHECK(ctx.have_ints, 1, "integrals not loaded");
+  const double t_start = now_s();
+  double t_dev = 0.0, t0;
   const int L = ctx.L, NM = 2 * L;
   Block* old = get_block(ctx, left, bond);
   BSD_CHECK(old != nullptr, 1, "source block missing");
@@ -515,8 +522,10 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
         BSD_HIP(hipMemcpyAsync(dt.p, tasks.data(), tasks.size() * sizeof(AggTask), hipMemcpyHostToDevice, s));
         if (!terms.empty())
           BSD_HIP(hipMemcpyAsync(dm.p, terms.data(), terms.size() * sizeof(AggTerm), hipMemcpyHostToDevice, s));
+        t0 = now_s();
         launch_aggregate((const AggTask*)dt.p, (const AggTerm*)dm.p, (int)tasks.size(), s);
         BSD_HIP(hipStreamSynchronize(s));
+        t_dev += now_s() - t0;
       }
     }
 
@@ -554,9 +563,11 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
       GemmPlan plan;
       plan.build(p1);
       GBases b{{0, 0, 0, 0}};
+      t0 = now_s();
       plan.launch(b, s);
-      fl += plan.flops;
       BSD_HIP(hipStreamSynchronize(s));
+      t_dev += now_s() - t0;
+      fl += plan.flops;
     }
 
     // phase 2: new op blocks of the batch's keys
@@ -622,13 +633,18 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
       GemmPlan plan;
       plan.build(p2);
       GBases b{{0, 0, 0, 0}};
+      t0 = now_s();
       plan.launch(b, s);
-      fl += plan.flops;
       BSD_HIP(hipStreamSynchronize(s));
+      t_dev += now_s() - t0;
+      fl += plan.flops;
     }
     k0 = k1;
   }
   ctx.renorm_flops += fl;
+  ctx.renorm_dev_s += t_dev;
+  ctx.renorm_wall_s += now_s() - t_start;
+  ctx.renorm_steps += 1;
   auto& m = left ? ctx.left : ctx.right;
   m[left ? bond + 1 : bond - 1] = std::move(nw);
 }

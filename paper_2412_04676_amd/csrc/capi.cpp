@@ -275,6 +275,17 @@ int bsdmrg_set_renorm_workspace(bsdmrg_ctx* ctx, size_t bytes) {
   });
 }
 
+int bsdmrg_renorm_stats(bsdmrg_ctx* ctx, double* flops, double* wall_s, double* device_s, int64_t* steps) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    const Ctx& c = ctx->c;
+    if (flops) *flops = c.renorm_flops;
+    if (wall_s) *wall_s = c.renorm_wall_s;
+    if (device_s) *device_s = c.renorm_dev_s;
+    if (steps) *steps = c.renorm_steps;
+  });
+}
+
 int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream) {
   return guard([&] {
     BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");

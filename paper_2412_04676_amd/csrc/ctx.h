@@ -34,7 +34,10 @@ struct Ctx {
   size_t renorm_ws_budget = (size_t)8 << 30;   // per batch of new operators
   // statistics
   double last_hpsi_flops = 0.0;
-  double renorm_flops = 0.0;
+  double renorm_flops = 0.0;     // useful flops of the grouped-GEMM phases
+  double renorm_wall_s = 0.0;    // wall time of renormalization steps
+  double renorm_dev_s = 0.0;     // of it: from each launch to its stream sync
+  int64_t renorm_steps = 0;
   ~Ctx();
 };
 
