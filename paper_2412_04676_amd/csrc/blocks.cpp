@@ -6,6 +6,11 @@
 #include "ctx.h"
 
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
+#include <exception>
+#include <mutex>
+#include <thread>
 #include <unordered_map>
 
 namespace bsd {
@@ -183,7 +188,6 @@ struct Ref {
 
 struct AggOp {
   Skeleton sk;
-  int64_t off;     // element offset in the workspace
   std::vector<Term> terms;
 };
 
@@ -198,8 +202,8 @@ struct Operand {
 
 }  // namespace
 
-static Operand ref_block(const Block& blk, const Ref& r, const std::vector<AggOp>& aggs,
-                         const double* ws, int in_idx) {
+static Operand ref_block(const Block& blk, const Ref& r, const AggOp* agg, const double* agg_base,
+                         int in_idx) {
   Operand o;
   const Basis& bs = blk.basis;
   Q qout = bs.q[in_idx] + r.dq;
@@ -208,15 +212,15 @@ static Operand ref_block(const Block& blk, const Ref& r, const std::vector<AggOp
   if (r.kind == 1) {
     o.ident = true;
     o.rows = o.cols = bs.dim[in_idx];
-    o.p = ws;  // unused
+    o.p = nullptr;  // unused
     return o;
   }
   if (r.kind == 2) {
-    const AggOp& a = aggs[r.agg];
+    const AggOp& a = *agg;
     int b = a.sk.by_in[in_idx];
     if (b < 0) return o;
     const SkBlock& sb = a.sk.blocks[b];
-    o.p = ws + a.off + sb.off;
+    o.p = agg_base + sb.off;
     o.ld = sb.ld;
     o.rows = sb.rows;
     o.cols = sb.cols;
@@ -250,7 +254,6 @@ static double now_s() {
 static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
   BSD_CHECK(ctx.have_ints, 1, "integrals not loaded");
   const double t_start = now_s();
-  double t_dev = 0.0, t0;
   const int L = ctx.L, NM = 2 * L;
   Block* old = get_block(ctx, left, bond);
   BSD_CHECK(old != nullptr, 1, "source block missing");
@@ -364,7 +367,6 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
       } else {
         AggOp a;
         a.sk = make_skeleton(old->basis, old->basis, bdq);
-        a.off = -1;   // workspace offset, assigned per batch
         for (const auto& t : g.terms) {
           Q tdq = t.key.kind == 'I' ? Q{0, 0} : key_dq(t.key, left);
           if (t.trans) tdq = -tdq;
@@ -438,32 +440,57 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
   // output operators in batches whose workspace (aggregates + intermediates of
   // the refs they use) stays under the budget; a ref shared by two batches is
   // computed in both
+  struct Batch {
+    size_t k0 = 0, k1 = 0;
+    std::vector<int> refs;
+    DevBuf tasks, terms;   // aggregation lists
+    int ntasks = 0;
+    GemmPlan p1, p2;       // phase 1 and phase 2 tile lists
+    bool has_p1 = false, has_p2 = false;
+    bool ready = false;
+    std::exception_ptr err;
+  };
   const int64_t budget = (int64_t)(ctx.renorm_ws_budget / sizeof(double));
-  double fl = 0.0;
-  size_t k0 = 0;
-  while (k0 < keys.size()) {
+  // at least two batches per planning thread where the budget allows fewer
+  const int max_threads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const size_t max_keys = std::max<size_t>(1, (keys.size() + 2 * max_threads - 1) / (2 * max_threads));
+  std::vector<std::unique_ptr<Batch>> batches;
+  int64_t ws_max = 1;
+  for (size_t k0 = 0; k0 < keys.size();) {
+    auto B = std::make_unique<Batch>();
     std::vector<char> in_batch(refs.size(), 0);
-    std::vector<int> brefs;
     int64_t bws = 0;
     size_t k1 = k0;
     for (; k1 < keys.size(); ++k1) {
       int64_t add = 0;
       for (const auto& gr : per_key[k1])
         if (!in_batch[gr.ref]) add += ref_cost[gr.ref];
-      if (k1 > k0 && bws + add > budget) break;
+      if (k1 > k0 && (bws + add > budget || k1 - k0 >= max_keys)) break;
       for (const auto& gr : per_key[k1])
         if (!in_batch[gr.ref]) {
           in_batch[gr.ref] = 1;
-          brefs.push_back(gr.ref);
+          B->refs.push_back(gr.ref);
         }
       bws += add;
     }
-    // batch-local workspace offsets
+    B->k0 = k0;
+    B->k1 = k1;
+    ws_max = std::max(ws_max, bws);
+    batches.push_back(std::move(B));
+    k0 = k1;
+  }
+  ctx.ws.reserve(ws_max * sizeof(double));
+  double* const ws = static_cast<double*>(ctx.ws.p);
+
+  // host lists of one batch (run by the planning threads; reads shared state only)
+  auto plan_batch = [&](Batch& bt, hipStream_t up) {
+    // batch-local workspace offsets of the aggregates and intermediates
+    std::unordered_map<int, int64_t> agg_off;
     std::map<TKey, TVal> tmap;
     int64_t ws_elems = 0;
-    for (int ri : brefs) {
+    for (int ri : bt.refs) {
       if (refs[ri].kind == 2) {
-        aggs[refs[ri].agg].off = ws_elems;
+        agg_off[refs[ri].agg] = ws_elems;
         ws_elems += aggs[refs[ri].agg].sk.layer_stride;
       }
       for (auto tv : ref_t[ri]) {
@@ -474,60 +501,70 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
         tmap[tv.first] = tv.second;
       }
     }
-    ctx.ws.reserve(std::max<int64_t>(ws_elems, 1) * sizeof(double));
-    double* ws = static_cast<double*>(ctx.ws.p);
+    BSD_CHECK(ws_elems <= ws_max, 1, "renormalization workspace bookkeeping");
+    auto agg_base = [&](const Ref& r) -> const double* {
+      return r.kind == 2 ? ws + agg_off.at(r.agg) : nullptr;
+    };
 
     // aggregation
-    {
-      std::vector<AggTask> tasks;
-      std::vector<AggTerm> terms;
-      for (int ri : brefs) {
-        if (refs[ri].kind != 2) continue;
-        const AggOp& a = aggs[refs[ri].agg];
-        for (const auto& sb : a.sk.blocks) {
-          AggTask t;
-          t.out = ws + a.off + sb.off;
-          t.ldo = sb.ld;
-          t.rows = sb.rows;
-          t.cols = sb.cols;
-          t.t0 = (int)terms.size();
-          for (const auto& tm : a.terms) {
-            AggTerm x;
-            x.coef = tm.coef;
-            x.pad = 0;
-            if (tm.key.kind == 'I') {
-              if (sb.in != sb.out) continue;
-              x.in = nullptr;
-              x.ldi = 0;
-              x.flags = kIdentA;
-            } else {
-              int rr, cc, ld;
-              const double* p = tm.trans ? old->op_block(tm.key, sb.out, &rr, &cc, &ld)
-                                         : old->op_block(tm.key, sb.in, &rr, &cc, &ld);
-              if (!p) continue;
-              x.in = p;
-              x.ldi = ld;
-              x.flags = tm.trans ? kTransA : 0;
-            }
-            terms.push_back(x);
-          }
-          t.nt = (int)terms.size() - t.t0;
-          tasks.push_back(t);
+    std::vector<AggTask> tasks;
+    std::vector<AggTerm> terms;
+    std::vector<const OpRef*> term_op;
+    for (int ri : bt.refs) {
+      if (refs[ri].kind != 2) continue;
+      const AggOp& a = aggs[refs[ri].agg];
+      double* base = ws + agg_off.at(refs[ri].agg);
+      // each term's stored operator, looked up once
+      term_op.assign(a.terms.size(), nullptr);
+      for (size_t ti = 0; ti < a.terms.size(); ++ti)
+        if (a.terms[ti].key.kind != 'I') {
+          auto it = old->ops.find(a.terms[ti].key);
+          if (it != old->ops.end()) term_op[ti] = &it->second;
         }
-      }
-      if (!tasks.empty()) {
-        DevBuf dt, dm;
-        dt.reserve(tasks.size() * sizeof(AggTask));
-        dm.reserve(std::max<size_t>(1, terms.size()) * sizeof(AggTerm));
-        BSD_HIP(hipMemcpyAsync(dt.p, tasks.data(), tasks.size() * sizeof(AggTask), hipMemcpyHostToDevice, s));
-        if (!terms.empty())
-          BSD_HIP(hipMemcpyAsync(dm.p, terms.data(), terms.size() * sizeof(AggTerm), hipMemcpyHostToDevice, s));
-        t0 = now_s();
-        launch_aggregate((const AggTask*)dt.p, (const AggTerm*)dm.p, (int)tasks.size(), s);
-        BSD_HIP(hipStreamSynchronize(s));
-        t_dev += now_s() - t0;
+      for (const auto& sb : a.sk.blocks) {
+        AggTask t;
+        t.out = base + sb.off;
+        t.ldo = sb.ld;
+        t.rows = sb.rows;
+        t.cols = sb.cols;
+        t.t0 = (int)terms.size();
+        for (size_t ti = 0; ti < a.terms.size(); ++ti) {
+          const Term& tm = a.terms[ti];
+          AggTerm x;
+          x.coef = tm.coef;
+          x.pad = 0;
+          if (tm.key.kind == 'I') {
+            if (sb.in != sb.out) continue;
+            x.in = nullptr;
+            x.ldi = 0;
+            x.flags = kIdentA;
+          } else {
+            if (!term_op[ti]) continue;
+            const Family& f = old->fams[term_op[ti]->fam];
+            const int b = f.sk.by_in[tm.trans ? sb.out : sb.in];
+            if (b < 0) continue;
+            const SkBlock& ob = f.sk.blocks[b];
+            x.in = f.dev + (int64_t)term_op[ti]->layer * f.sk.layer_stride + ob.off;
+            x.ldi = ob.ld;
+            x.flags = tm.trans ? kTransA : 0;
+          }
+          terms.push_back(x);
+        }
+        t.nt = (int)terms.size() - t.t0;
+        tasks.push_back(t);
       }
     }
+    if (!tasks.empty()) {
+      bt.tasks.reserve(tasks.size() * sizeof(AggTask));
+      bt.terms.reserve(std::max<size_t>(1, terms.size()) * sizeof(AggTerm));
+      BSD_HIP(hipMemcpyAsync(bt.tasks.p, tasks.data(), tasks.size() * sizeof(AggTask), hipMemcpyHostToDevice, up));
+      if (!terms.empty())
+        BSD_HIP(hipMemcpyAsync(bt.terms.p, terms.data(), terms.size() * sizeof(AggTerm), hipMemcpyHostToDevice, up));
+      BSD_HIP(hipStreamSynchronize(up));
+      bt.ntasks = (int)tasks.size();
+    }
+    GemmBuildOpts opts;
+    opts.upload = up;
 
     // phase 1: T = op(ref) X, X = A_s (left) or B_s^T (right)
     std::vector<GemmProblem> p1;
@@ -535,7 +572,7 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
       if (kv.second.off < 0) continue;
       const TKey& tk = kv.first;
       const Ref& r = refs[tk.ref];
-      Operand o = ref_block(*old, r, aggs, ws, tk.oidx);
+      Operand o = ref_block(*old, r, r.kind == 2 ? &aggs[r.agg] : nullptr, agg_base(r), tk.oidx);
       TB tb = tblock(tk.oidx, tk.sstate);
       GemmProblem gp;
       gp.C = tag_ptr(0, (uint64_t)(ws + kv.second.off));
@@ -560,21 +597,15 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
       p1.push_back(std::move(gp));
     }
     if (!p1.empty()) {
-      GemmPlan plan;
-      plan.build(p1);
-      GBases b{{0, 0, 0, 0}};
-      t0 = now_s();
-      plan.launch(b, s);
-      BSD_HIP(hipStreamSynchronize(s));
-      t_dev += now_s() - t0;
-      fl += plan.flops;
+      bt.p1.build(p1, opts);
+      bt.has_p1 = true;
     }
 
     // phase 2: new op blocks of the batch's keys
     std::vector<GemmProblem> p2;
-    for (size_t ki = k0; ki < k1; ++ki) {
-      const OpRef& orf = nw->ops[keys[ki]];
-      Family& fam = nw->fams[orf.fam];
+    for (size_t ki = bt.k0; ki < bt.k1; ++ki) {
+      const OpRef& orf = nw->ops.at(keys[ki]);
+      const Family& fam = nw->fams[orf.fam];
       for (const auto& sb : fam.sk.blocks) {
         GemmProblem gp;
         gp.C = tag_ptr(0, (uint64_t)(fam.dev + (int64_t)orf.layer * fam.sk.layer_stride + sb.off));
@@ -630,17 +661,88 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
       }
     }
     if (!p2.empty()) {
-      GemmPlan plan;
-      plan.build(p2);
-      GBases b{{0, 0, 0, 0}};
-      t0 = now_s();
-      plan.launch(b, s);
-      BSD_HIP(hipStreamSynchronize(s));
-      t_dev += now_s() - t0;
-      fl += plan.flops;
+      bt.p2.build(p2, opts);
+      bt.has_p2 = true;
     }
-    k0 = k1;
+  };
+
+  // Batches are planned by a pool of host threads, each copying its lists on
+  // a stream of its own, and launched in order on `s` as they become ready, so
+  // that the planning of later batches overlaps the device work of earlier
+  // ones.  Every batch reuses the one workspace: stream order serializes them.
+  // The lists stay allocated until the step's final synchronization.
+  const int nthreads = (int)std::min<size_t>(batches.size(), max_threads);
+  std::vector<hipStream_t> ups(nthreads, nullptr);
+  for (auto& u : ups) BSD_HIP(hipStreamCreateWithFlags(&u, hipStreamNonBlocking));
+  std::mutex mu;
+  std::condition_variable cv;
+  std::atomic<size_t> next{0};
+  std::atomic<bool> stop{false};
+  std::vector<std::thread> pool;
+  int dev = 0;
+  BSD_HIP(hipGetDevice(&dev));
+  for (int t = 0; t < nthreads; ++t)
+    pool.emplace_back([&, t] {
+      (void)hipSetDevice(dev);   // a failure shows in the batch's own HIP calls
+      for (;;) {
+        const size_t i = next.fetch_add(1);
+        if (i >= batches.size() || stop.load()) return;
+        Batch& bt = *batches[i];
+        try {
+          plan_batch(bt, ups[t]);
+        } catch (...) {
+          bt.err = std::current_exception();
+        }
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          bt.ready = true;
+        }
+        cv.notify_all();
+      }
+    });
+  std::vector<hipEvent_t> evs(2 * batches.size(), nullptr);
+  std::exception_ptr failure;
+  double fl = 0.0;
+  try {
+    for (auto& e : evs) BSD_HIP(hipEventCreate(&e));
+    for (size_t i = 0; i < batches.size(); ++i) {
+      Batch& bt = *batches[i];
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return bt.ready; });
+      }
+      if (bt.err) std::rethrow_exception(bt.err);
+      GBases b{{0, 0, 0, 0}};
+      BSD_HIP(hipEventRecord(evs[2 * i], s));
+      if (bt.ntasks > 0)
+        launch_aggregate((const AggTask*)bt.tasks.p, (const AggTerm*)bt.terms.p, bt.ntasks, s);
+      if (bt.has_p1) {
+        bt.p1.launch(b, s);
+        fl += bt.p1.flops;
+      }
+      if (bt.has_p2) {
+        bt.p2.launch(b, s);
+        fl += bt.p2.flops;
+      }
+      BSD_HIP(hipEventRecord(evs[2 * i + 1], s));
+    }
+  } catch (...) {
+    failure = std::current_exception();
+    stop = true;
   }
+  for (auto& th : pool) th.join();
+  (void)hipStreamSynchronize(s);
+  double t_dev = 0.0;
+  if (!failure)
+    for (size_t i = 0; i < batches.size(); ++i) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, evs[2 * i], evs[2 * i + 1]) == hipSuccess) t_dev += ms * 1e-3;
+    }
+  for (auto e : evs)
+    if (e) (void)hipEventDestroy(e);
+  for (auto u : ups) (void)hipStreamDestroy(u);
+  if (failure) std::rethrow_exception(failure);
+  BSD_HIP(hipGetLastError());
   ctx.renorm_flops += fl;
   ctx.renorm_dev_s += t_dev;
   ctx.renorm_wall_s += now_s() - t_start;

@@ -497,6 +497,14 @@ void launch_split_reduce(const GReduce* red, int n, const GBases& b, hipStream_t
 }
 
 void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts& opts) {
+  auto upload = [&](void* dst, const void* src, size_t bytes) {
+    if (opts.upload) {
+      BSD_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, opts.upload));
+      BSD_HIP(hipStreamSynchronize(opts.upload));
+    } else {
+      BSD_HIP(hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+    }
+  };
   const bool wave_tiles = opts.wave_tiles, plane_operands = opts.plane_operands || opts.plane_output;
   const bool split_k = opts.split_k && !opts.plane_output;
   // tile shape classes and the waves one tile of each class occupies
@@ -516,7 +524,9 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
   std::vector<double> segwork;
   flops = 0.0;
   for (int c = 0; c < kShapes; ++c) shape_flops[c] = shape_in_elems[c] = shape_out_bytes[c] = 0.0;
-  std::set<uint64_t> seen_a[kShapes], seen_b[kShapes];
+  // operands read by each shape class: (address, elements); each distinct
+  // address counts once in shape_in_elems
+  std::vector<std::pair<uint64_t, double>> operands[kShapes];
   for (const auto& p : probs) {
     if (p.M <= 0 || p.N <= 0) continue;
     int seg0 = (int)sg.size();
@@ -548,9 +558,9 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
         double f = 2.0 * p.M * (double)p.N * s.K;
         flops += f;
         shape_flops[cls] += f;
-        if (seen_a[cls].insert(s.A).second) shape_in_elems[cls] += p.M * kk;
+        operands[cls].push_back({s.A, p.M * kk});
       }
-      if (seen_b[cls].insert(s.B).second) shape_in_elems[cls] += p.N * kk;
+      operands[cls].push_back({s.B, p.N * kk});
     }
     shape_out_bytes[cls] += opts.plane_output ? (double)p.M * p.N * 2.0 * kPlaneParts
                                               : (double)p.M * p.N * sizeof(double) * (p.beta != 0.0 ? 2 : 1);
@@ -573,6 +583,13 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
         x.beta = p.beta;
         t[cls].push_back({x, ktot, p.group, 0.0});
       }
+  }
+  for (int c = 0; c < kShapes; ++c) {
+    auto& v = operands[c];
+    std::sort(v.begin(), v.end());
+    for (size_t i = 0; i < v.size(); ++i)
+      if (i == 0 || v[i].first != v[i - 1].first) shape_in_elems[c] += v[i].second;
+    std::vector<std::pair<uint64_t, double>>().swap(v);
   }
   wave = wave_tiles || plane_operands;
   planes = plane_operands;
@@ -680,11 +697,14 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
       }
       units.swap(order);
     } else {
-      // longest units first inside every launch (LPT order)
-      std::stable_sort(units.begin(), units.end(),
-                       [](const std::pair<Pending, int64_t>& a, const std::pair<Pending, int64_t>& b) {
-                         return a.first.work > b.first.work;
-                       });
+      // longest units first inside every launch (LPT order), ties in list order
+      std::vector<std::pair<double, uint32_t>> key(units.size());
+      for (size_t i = 0; i < key.size(); ++i) key[i] = {-units[i].first.work, (uint32_t)i};
+      std::sort(key.begin(), key.end());
+      std::vector<std::pair<Pending, int64_t>> order;
+      order.reserve(units.size());
+      for (const auto& k : key) order.push_back(units[k.second]);
+      units.swap(order);
     }
     first[c] = (int)all.size();
     count[c] = (int)units.size();
@@ -752,7 +772,7 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
         x.nseg = b - a;
       }
     steps.reserve(std::max<size_t>(1, st.size()) * sizeof(GSeg));
-    if (!st.empty()) BSD_HIP(hipMemcpy(steps.p, st.data(), st.size() * sizeof(GSeg), hipMemcpyHostToDevice));
+    if (!st.empty()) upload(steps.p, st.data(), st.size() * sizeof(GSeg));
   }
   if (ws_elems > 0) parts.reserve(ws_elems * sizeof(double));
   double* ws = static_cast<double*>(parts.p);
@@ -762,11 +782,11 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
   nreduce = (int)red.size();
   tiles.reserve(std::max<size_t>(1, all.size()) * sizeof(GTile));
   segs.reserve(std::max<size_t>(1, sg.size()) * sizeof(GSeg));
-  if (!all.empty()) BSD_HIP(hipMemcpy(tiles.p, all.data(), all.size() * sizeof(GTile), hipMemcpyHostToDevice));
-  if (!sg.empty()) BSD_HIP(hipMemcpy(segs.p, sg.data(), sg.size() * sizeof(GSeg), hipMemcpyHostToDevice));
+  if (!all.empty()) upload(tiles.p, all.data(), all.size() * sizeof(GTile));
+  if (!sg.empty()) upload(segs.p, sg.data(), sg.size() * sizeof(GSeg));
   if (nreduce > 0) {
     reduces.reserve(red.size() * sizeof(GReduce));
-    BSD_HIP(hipMemcpy(reduces.p, red.data(), red.size() * sizeof(GReduce), hipMemcpyHostToDevice));
+    upload(reduces.p, red.data(), red.size() * sizeof(GReduce));
   }
 }
 

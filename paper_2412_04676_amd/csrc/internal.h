@@ -328,6 +328,7 @@ struct GemmBuildOpts {
   bool xcd_order = true;       // place problems of one locality group on one XCD
   bool plane_operands = false; // A and B are split-bf16 planes (wave tiles for every size)
   bool plane_output = false;   // C is written as split-bf16 planes of C^T (M a multiple of 8)
+  hipStream_t upload = nullptr; // non-null: lists are copied on this stream (then synchronized)
 };
 
 struct GemmPlan {
