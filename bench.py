@@ -42,9 +42,17 @@ def build_workload(L, na, nb, D, site):
     for n, t in enumerate(T):
         if t is not None:
             B.bsdmrg_set_site_tensor(ctx, n, t)
+    # grow each environment one bond at a time and free the block behind it,
+    # so that only the blocks the middle-site step reads stay on the device
     t0 = time.time()
-    B.bsdmrg_build_env(ctx, B.LEFT, site)
-    B.bsdmrg_build_env(ctx, B.RIGHT, site + 2)
+    for b in range(1, site + 1):
+        B.bsdmrg_build_env(ctx, B.LEFT, b)
+        if b > 1:
+            B.bsdmrg_drop_block(ctx, B.LEFT, b - 1)
+    for b in range(L - 1, site + 1, -1):
+        B.bsdmrg_build_env(ctx, B.RIGHT, b)
+        if b < L - 1:
+            B.bsdmrg_drop_block(ctx, B.RIGHT, b + 1)
     t_env = time.time() - t0
     psi = random_two_site_psi(dims[site], dims[site + 2], 1)
     return ctx, psi, dims, T, h, eri, t_env
@@ -92,10 +100,11 @@ def cpu_baseline(L, na, nb, D, site, useful_flops, budget_s=20.0):
                       "same useful flops per product as the GPU figure"}
 
 
-def measured_traffic(kernel_label):
+def measured_traffic(kernel_label, workload):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain-copy calibration), or
-    None when the summary covers another kernel or its source has changed since."""
+    None when the summary covers another kernel or workload, or its source has
+    changed since."""
     import glob
     import hashlib
     for path in glob.glob(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "*_traffic.txt")):
@@ -105,7 +114,7 @@ def measured_traffic(kernel_label):
                 if "=" in line and not line.startswith("#"):
                     k, v = line.strip().split("=", 1)
                     kv[k] = v
-        if not kernel_label.startswith(kv.get("kernel", "\0")):
+        if not kernel_label.startswith(kv.get("kernel", "\0")) or kv.get("workload") != workload:
             continue
         src = os.path.join(os.path.dirname(os.path.abspath(__file__)), kv["source"])
         with open(src, "rb") as f:
@@ -127,6 +136,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     ap.add_argument("--ws-mb", type=int, default=0, help="H.psi workspace budget in MiB (0: library default)")
     ap.add_argument("--precision", type=int, default=0, help="0 fp64, 1 split-bf16 x3, 2 split-bf16 x6")
+    ap.add_argument("--no-autotune", action="store_true", help="time the default schedules")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
@@ -158,9 +168,12 @@ def main():
 
     def time_precision(prec):
         # schedule chosen by the library's autotuner (untimed setup)
-        best, dflt, ncand = B.bsdmrg_hpsi_autotune(ctx, site, prec, stream)
-        tuned[prec] = {"candidates": ncand, "default_ms": dflt, "tuned_ms": best}
-        log(f"bench: precision {prec}: autotune {ncand} schedules, default {dflt:.3f} ms -> {best:.3f} ms")
+        if args.no_autotune:
+            tuned[prec] = None
+        else:
+            best, dflt, ncand = B.bsdmrg_hpsi_autotune(ctx, site, prec, stream)
+            tuned[prec] = {"candidates": ncand, "default_ms": dflt, "tuned_ms": best}
+            log(f"bench: precision {prec}: autotune {ncand} schedules, default {dflt:.3f} ms -> {best:.3f} ms")
         for _ in range(args.warmup):
             B.bsdmrg_hpsi(ctx, site, x, y, prec, stream)
         torch.cuda.synchronize()
@@ -223,7 +236,7 @@ def main():
     # the roof that bounds the kernel at its algorithmic intensity
     intensity = mult * f_dom / b_dom
     ridge = peak_f * 1e12 / (HBM_PEAK_GBS * 1e9)
-    traffic = measured_traffic(dname)
+    traffic = measured_traffic(dname, f"L={L} N={N} D={D}")
     if intensity < ridge:
         roof = {"bound": "hbm", "achieved": ach_b, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_b / HBM_PEAK_GBS}
     else:

@@ -141,6 +141,15 @@ int bsdmrg_hpsi_prepare(bsdmrg_ctx* ctx, int site, int precision, size_t ws_byte
  * the chosen and of the default schedule, n_candidates (optional) the number
  * tried.  Results are identical up to the order of float64 additions.
  * Synchronizes `stream`. */
+/* Set the schedule of the prepared product at `site` for `precision` directly
+ * (one candidate of bsdmrg_hpsi_autotune): the split-K target of waves per
+ * launch (256 .. 2^20), XCD placement of locality groups (0/1) and, for
+ * float64, the largest block dimension given wave tiles (>= 16; larger blocks
+ * use workgroup tiles).  Rebuilds the phase-2 tile lists; results are
+ * identical up to the order of float64 additions.  ESTATE if not prepared. */
+int bsdmrg_hpsi_schedule(bsdmrg_ctx* ctx, int site, int precision, double target_waves, int xcd_order,
+                         int wave_max);
+
 int bsdmrg_hpsi_autotune(bsdmrg_ctx* ctx, int site, int precision, bsdmrg_stream_t stream, double* best_ms,
                          double* default_ms, int* n_candidates);
 

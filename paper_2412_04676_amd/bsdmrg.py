@@ -68,6 +68,7 @@ _SIGS = {
     "bsdmrg_hpsi": ([c_vp, c_int, c_vp, c_vp, c_int, c_vp], c_int),
     "bsdmrg_hpsi_autotune": ([c_vp, c_int, c_int, c_vp, ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_int)], c_int),
+    "bsdmrg_hpsi_schedule": ([c_vp, c_int, c_int, ctypes.c_double, c_int, c_int], c_int),
     "bsdmrg_hpsi_info": ([c_vp, c_int, c_int, ctypes.POINTER(ctypes.c_double), c_i64p, c_i64p,
                           c_i64p, c_i64p], c_int),
     "bsdmrg_hpsi_profile": ([c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_int, c_vp, c_vp, c_vp, c_vp,
@@ -216,6 +217,10 @@ def bsdmrg_hpsi_info(ctx, site, precision=FP64):
                                  ctypes.byref(c), ctypes.byref(d)))
     return {"flops": fl.value, "channels": a.value, "segments": b.value, "aggregates": c.value,
             "ws_bytes": d.value}
+
+
+def bsdmrg_hpsi_schedule(ctx, site, precision, target_waves=8192.0, xcd_order=1, wave_max=64):
+    _check(_lib.bsdmrg_hpsi_schedule(ctx, site, precision, float(target_waves), int(xcd_order), int(wave_max)))
 
 
 def bsdmrg_hpsi_autotune(ctx, site, precision=FP64, stream=None):

@@ -403,6 +403,29 @@ int bsdmrg_hpsi_autotune(bsdmrg_ctx* ctx, int site, int precision, bsdmrg_stream
   });
 }
 
+int bsdmrg_hpsi_schedule(bsdmrg_ctx* ctx, int site, int precision, double target_waves, int xcd_order,
+                         int wave_max) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    BSD_CHECK(precision >= BSDMRG_FP64 && precision <= BSDMRG_BF16X6, BSDMRG_EINVAL, "unsupported precision");
+    BSD_CHECK(target_waves >= 256.0 && target_waves <= 1048576.0, BSDMRG_EINVAL, "target_waves out of [256, 2^20]");
+    BSD_CHECK(wave_max >= 16, BSDMRG_EINVAL, "wave_max below 16");
+    auto it = ctx->c.plans.find({site, 0});
+    BSD_CHECK(it != ctx->c.plans.end(), BSDMRG_ESTATE, "product not prepared");
+    HpsiPlan& p = *it->second;
+    GemmBuildOpts a = p.opts64, b = p.opts_planes;
+    if (precision == BSDMRG_FP64) {
+      a.target_waves = target_waves;
+      a.xcd_order = xcd_order != 0;
+      a.wave_max = wave_max;
+    } else {
+      b.target_waves = target_waves;
+      b.xcd_order = xcd_order != 0;
+    }
+    rebuild_phase2(p, a, b, precision == BSDMRG_FP64 ? 1 : 2);
+  });
+}
+
 int bsdmrg_hpsi(bsdmrg_ctx* ctx, int site, const double* psi, double* out, int precision, bsdmrg_stream_t stream) {
   return guard([&] {
     BSD_CHECK(ctx && psi && out, BSDMRG_EINVAL, "NULL argument");

@@ -7,6 +7,9 @@
 // every uneven sector GEMM of one phase runs in a single launch.  Operands are
 // staged through LDS in K-slices of 16; each wave owns a 32x32 sub-tile made of
 // 2x2 v_mfma_f64_16x16x4 accumulators.
+#include <atomic>
+#include <exception>
+#include <thread>
 #include "devutil.h"
 
 #include <algorithm>
@@ -788,6 +791,38 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
     reduces.reserve(red.size() * sizeof(GReduce));
     upload(reduces.p, red.data(), red.size() * sizeof(GReduce));
   }
+}
+
+void parallel_jobs(int n, const std::function<void(int, hipStream_t)>& fn) {
+  if (n <= 0) return;
+  const int nt = std::min<int>(n, (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+  int dev = 0;
+  BSD_HIP(hipGetDevice(&dev));
+  std::atomic<int> next{0};
+  std::vector<std::exception_ptr> errs(n);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&] {
+      hipStream_t up = nullptr;
+      try {
+        BSD_HIP(hipSetDevice(dev));
+        BSD_HIP(hipStreamCreateWithFlags(&up, hipStreamNonBlocking));
+      } catch (...) {
+        up = nullptr;
+      }
+      for (int i; (i = next.fetch_add(1)) < n;) {
+        try {
+          BSD_CHECK(up != nullptr, 1, "no copy stream for a planning thread");
+          fn(i, up);
+        } catch (...) {
+          errs[i] = std::current_exception();
+        }
+      }
+      if (up) (void)hipStreamDestroy(up);
+    });
+  for (auto& th : pool) th.join();
+  for (auto& e : errs)
+    if (e) std::rethrow_exception(e);
 }
 
 void GemmPlan::launch_shape_class(int c, const GBases& bases, hipStream_t s, int precision) const {

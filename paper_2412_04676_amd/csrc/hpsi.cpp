@@ -637,19 +637,32 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   plan->p2s_probs.resize(nchunks);
   for (int k = 0; k < nchunks; ++k) {
     plan->phase1[k] = std::make_unique<GemmPlan>();
-    plan->phase1[k]->build(p1[k], true);
-    GemmBuildOpts o1;
-    o1.plane_output = true;
     plan->phase1s[k] = std::make_unique<GemmPlan>();
-    plan->phase1s[k]->build(p1s[k], o1);
+  }
+  parallel_jobs(2 * nchunks, [&](int j, hipStream_t up) {
+    const int k = j / 2;
+    GemmBuildOpts o;
+    o.upload = up;
+    if (j % 2 == 0) {
+      plan->phase1[k]->build(p1[k], o);
+    } else {
+      o.plane_output = true;
+      plan->phase1s[k]->build(p1s[k], o);
+    }
+  });
+  for (int k = 0; k < nchunks; ++k) {
     for (auto& kv : p2[k]) {
       plan->nseg += kv.second.segs.size();
       plan->p2_probs[k].push_back(std::move(kv.second));
     }
     for (auto& kv : p2s[k]) plan->p2s_probs[k].push_back(std::move(kv.second));
   }
-  // phase-2 tile lists from the kept problem lists (the autotuner rebuilds them)
-  rebuild_phase2(*plan, plan->opts64, plan->opts_planes);
+  // phase-2 tile lists from the kept problem lists (the autotuner rebuilds
+  // them); default schedule: wave tiles for every block, about 32k waves per
+  // launch
+  plan->opts64.wave_max = 1 << 30;
+  plan->opts64.target_waves = plan->opts_planes.target_waves = 32768;
+  rebuild_phase2(*plan, plan->opts64, plan->opts_planes, 3);
 
   // ---------------------------------------------------------------- split tasks
   // padded-row maps of the right-sector stacks: plane column -> stack row or -1
@@ -716,19 +729,30 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   return plan;
 }
 
-void rebuild_phase2(HpsiPlan& plan, const GemmBuildOpts& o64, const GemmBuildOpts& oplanes) {
-  const size_t nchunks = plan.p2_probs.size();
+void rebuild_phase2(HpsiPlan& plan, const GemmBuildOpts& o64, const GemmBuildOpts& oplanes, int which) {
+  const int nchunks = (int)plan.p2_probs.size();
   for (auto& g : plan.graphs) (void)hipGraphExecDestroy(g.exec);
   plan.graphs.clear();
   plan.opts64 = o64;
   plan.opts_planes = oplanes;
   plan.opts_planes.plane_operands = true;
-  for (size_t k = 0; k < nchunks; ++k) {
-    plan.phase2[k] = std::make_unique<GemmPlan>();
-    plan.phase2[k]->build(plan.p2_probs[k], plan.opts64);
-    plan.phase2s[k] = std::make_unique<GemmPlan>();
-    plan.phase2s[k]->build(plan.p2s_probs[k], plan.opts_planes);
+  plan.opts64.upload = plan.opts_planes.upload = nullptr;
+  for (int k = 0; k < nchunks; ++k) {
+    if (which & 1) plan.phase2[k] = std::make_unique<GemmPlan>();
+    if (which & 2) plan.phase2s[k] = std::make_unique<GemmPlan>();
   }
+  parallel_jobs(2 * nchunks, [&](int j, hipStream_t up) {
+    const int k = j / 2;
+    if (j % 2 == 0 && (which & 1)) {
+      GemmBuildOpts o = plan.opts64;
+      o.upload = up;
+      plan.phase2[k]->build(plan.p2_probs[k], o);
+    } else if (j % 2 == 1 && (which & 2)) {
+      GemmBuildOpts o = plan.opts_planes;
+      o.upload = up;
+      plan.phase2s[k]->build(plan.p2s_probs[k], o);
+    }
+  });
 }
 
 TuneResult autotune_hpsi(HpsiPlan& plan, int precision, hipStream_t s) {
@@ -754,21 +778,22 @@ TuneResult autotune_hpsi(HpsiPlan& plan, int precision, hipStream_t s) {
   std::vector<std::pair<GemmBuildOpts, GemmBuildOpts>> cand;
   const GemmBuildOpts base64 = plan.opts64, basep = plan.opts_planes;
   cand.push_back({base64, basep});
-  for (double tw : {4096.0, 8192.0, 16384.0, 32768.0})
+  for (double tw : {4096.0, 8192.0, 16384.0, 32768.0, 65536.0})
     for (int xcd = 0; xcd < 2; ++xcd)
-      for (int wm : {32, 64}) {
+      for (int wm : {32, 64, 128, 1 << 30}) {
         GemmBuildOpts a = base64, b = basep;
         if (precision == 0) {
           a.target_waves = tw;
           a.xcd_order = xcd;
           a.wave_max = wm;
         } else {
-          if (wm == 32) continue;   // planes always use wave tiles
+          if (wm != 64) continue;   // planes always use wave tiles
           b.target_waves = tw;
           b.xcd_order = xcd;
         }
         cand.push_back({a, b});
       }
+  const int which = precision == 0 ? 1 : 2;
   hipEvent_t e0, e1;
   BSD_HIP(hipEventCreate(&e0));
   BSD_HIP(hipEventCreate(&e1));
@@ -791,7 +816,7 @@ TuneResult autotune_hpsi(HpsiPlan& plan, int precision, hipStream_t s) {
   res.n_candidates = (int)cand.size();
   double best = 1e300;
   for (size_t i = 0; i < cand.size(); ++i) {
-    rebuild_phase2(plan, cand[i].first, cand[i].second);
+    rebuild_phase2(plan, cand[i].first, cand[i].second, which);
     const double ms = time_it();
     if (i == 0) res.default_ms = ms;
     if (ms < best) {
@@ -799,7 +824,7 @@ TuneResult autotune_hpsi(HpsiPlan& plan, int precision, hipStream_t s) {
       res.best = (int)i;
     }
   }
-  rebuild_phase2(plan, cand[res.best].first, cand[res.best].second);
+  rebuild_phase2(plan, cand[res.best].first, cand[res.best].second, which);
   res.best_ms = best;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

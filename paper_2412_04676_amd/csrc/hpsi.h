@@ -77,7 +77,8 @@ int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream
                  double* ms, double* flops, double* bytes, int* kind);
 void zero_fill(double* p, int64_t n, hipStream_t s);
 // rebuild the phase-2 tile lists of every chunk with new schedule options
-void rebuild_phase2(HpsiPlan& plan, const GemmBuildOpts& o64, const GemmBuildOpts& oplanes);
+// which: bit 0 rebuilds the float64 lists, bit 1 the split-bf16 lists
+void rebuild_phase2(HpsiPlan& plan, const GemmBuildOpts& o64, const GemmBuildOpts& oplanes, int which = 3);
 // time candidate schedules of phase 2 for `precision` on a scratch vector,
 // keep the fastest; returns its product time in milliseconds
 struct TuneResult {

@@ -6,6 +6,7 @@
 #include <array>
 #include <cstdint>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -387,6 +388,10 @@ void launch_aggregate(const AggTask* tasks_dev, const AggTerm* terms_dev, int nt
 void launch_grouped_gemm(const GTile* tiles, int ntiles, int shape, const GSeg* segs,
                          const GBases& b, hipStream_t s, int precision = 0);
 void launch_split_reduce(const GReduce* red, int n, const GBases& b, hipStream_t s);
+// Runs fn(i, upload) for i in [0, n) on a pool of host threads (at most 16),
+// each with a non-blocking stream of its own for copies; rethrows the first
+// failure after all threads have finished.
+void parallel_jobs(int n, const std::function<void(int, hipStream_t)>& fn);
 void launch_planes_gemm(const GTile* tiles, int ntiles, int shape, const GSeg* segs, const GBases& b,
                         hipStream_t s, int precision, bool planes_out);
 

@@ -298,3 +298,27 @@ def test_dropped_blocks_are_rebuilt_from_the_nearest_one():
         B.bsdmrg_drop_block(ctx2, B.LEFT, 0)
     B.bsdmrg_destroy(ctx1)
     B.bsdmrg_destroy(ctx2)
+
+
+@pytest.mark.parametrize("precision,tw,xcd,wm", [(0, 4096, 0, 1 << 30), (0, 32768, 1, 16), (0, 8192, 1, 128),
+                                                 (2, 4096, 0, 64), (1, 32768, 1, 64)])
+def test_explicit_schedule_keeps_the_product(precision, tw, xcd, wm):
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    L, na, nb, D, site = 24, 12, 12, 512, 11
+    say(f"schedule L=24 precision {precision} target {tw} xcd {xcd} wave_max {wm}")
+    ctx, h, eri, dims, T = build_system(L, na, nb, D, site)
+    psi = psi_for(dims, site, 33)
+    lay = B.bsdmrg_psi_layout(ctx, site)
+    x = torch.from_numpy(B.psi_to_flat(psi, lay)).cuda()
+    ref, y = torch.empty_like(x), torch.empty_like(x)
+    B.bsdmrg_hpsi(ctx, site, x, ref, precision)
+    B.bsdmrg_hpsi_schedule(ctx, site, precision, tw, xcd, wm)
+    B.bsdmrg_hpsi(ctx, site, x, y, precision)
+    torch.cuda.synchronize()
+    e = float(torch.linalg.norm(y - ref) / torch.linalg.norm(ref))
+    say(f"  relative change {e:.2e}")
+    assert e < (1e-13 if precision == 0 else 1e-7)
+    with pytest.raises(RuntimeError):
+        B.bsdmrg_hpsi_schedule(ctx, site, precision, 10.0, 1, 64)
+    B.bsdmrg_destroy(ctx)
