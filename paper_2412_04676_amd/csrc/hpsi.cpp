@@ -778,7 +778,7 @@ TuneResult autotune_hpsi(HpsiPlan& plan, int precision, hipStream_t s) {
   std::vector<std::pair<GemmBuildOpts, GemmBuildOpts>> cand;
   const GemmBuildOpts base64 = plan.opts64, basep = plan.opts_planes;
   cand.push_back({base64, basep});
-  for (double tw : {4096.0, 8192.0, 16384.0, 32768.0, 65536.0})
+  for (double tw : {4096.0, 8192.0, 16384.0, 32768.0, 65536.0, 131072.0})
     for (int xcd = 0; xcd < 2; ++xcd)
       for (int wm : {32, 64, 128, 1 << 30}) {
         GemmBuildOpts a = base64, b = basep;
