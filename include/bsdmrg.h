@@ -108,6 +108,18 @@ int bsdmrg_drop_block(bsdmrg_ctx* ctx, int side, int bond);
  * later bsdmrg_build_env calls.  EINVAL for 0. */
 int bsdmrg_set_renorm_workspace(bsdmrg_ctx* ctx, size_t bytes);
 
+/* Operator sets of right blocks built from now on: blocks at bonds >= `bond`
+ * keep the normal operators of their own spin-orbitals (H, a+_r, a+_r a+_s,
+ * a+_r a_s) plus S_x, the smaller set near the chain's right end; blocks at
+ * lower bonds keep the complementary set (H, a+_r, S_x, P_pq, Q_pq over every
+ * spin-orbital to their left; Sec. II.B step 4).  The block that switches
+ * builds its complementary two-index operators as sums over the normal ones of
+ * its source.  Products need the complementary set at bond site+2.  Default:
+ * no normal blocks.  A normal block can only be grown from a normal block or
+ * the vacuum (ESTATE from bsdmrg_build_env otherwise); a product at a site
+ * whose right block is normal fails with ESTATE.  EINVAL for bond < 1. */
+int bsdmrg_set_right_normal(bsdmrg_ctx* ctx, int bond);
+
 /* Running totals of the renormalization steps done so far (Sec. II.B step 4):
  * useful flops of the grouped-GEMM phases (2mnk per product), wall seconds,
  * the part of them spent between each launch and its stream synchronization,

@@ -61,6 +61,7 @@ _SIGS = {
     "bsdmrg_build_env": ([c_vp, c_int, c_int, c_vp], c_int),
     "bsdmrg_set_renorm_workspace": ([c_vp, c_sz], c_int),
     "bsdmrg_drop_block": ([c_vp, c_int, c_int], c_int),
+    "bsdmrg_set_right_normal": ([c_vp, c_int], c_int),
     "bsdmrg_renorm_stats": ([c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                              ctypes.POINTER(ctypes.c_double), c_i64p], c_int),
     "bsdmrg_psi_layout": ([c_vp, c_int, ctypes.POINTER(c_int), c_i64p, c_vp, c_vp], c_int),
@@ -161,6 +162,10 @@ def bsdmrg_renorm_stats(ctx):
     f, w, d, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
     _check(_lib.bsdmrg_renorm_stats(ctx, ctypes.byref(f), ctypes.byref(w), ctypes.byref(d), ctypes.byref(n)))
     return f.value, w.value, d.value, n.value
+
+
+def bsdmrg_set_right_normal(ctx, bond):
+    _check(_lib.bsdmrg_set_right_normal(ctx, bond))
 
 
 def bsdmrg_drop_block(ctx, side, bond):

@@ -355,12 +355,36 @@ std::vector<Group> expand_left(const OpKey& key, int nL, const SiteSet& C, const
 
 // ---------------------------------------------------------------- right (complementary) role
 std::vector<Group> expand_right(const OpKey& key, const SiteSet& s, int r0, int nmodes,
-                                const Integrals& I) {
+                                const Integrals& I, bool R_normal) {
   std::vector<Group> out;
   const int s0 = s.mode0(), s1 = s0 + s.nmodes();
   const Mat Id = mat_eye(s.dim);
   const bool haveR = r0 < nmodes;
   switch (key.kind) {
+    case 'A': {   // a+_p a+_q, p < q, both in s . R (normal right block)
+      BSD_CHECK(R_normal, 1, "expand_right: normal key on a complementary block");
+      const int p = key.p, q = key.q;
+      if (p >= r0)
+        push(out, Id, {{1.0, K('A', p, q), false}});
+      else if (q >= r0)
+        push(out, s.CD(p), {{1.0, K('c', q), false}});
+      else
+        push(out, mat_mul(s.CD(p), s.CD(q)), {{1.0, kIdent, false}});
+      break;
+    }
+    case 'B': {   // a+_p a_q, both in s . R (normal right block)
+      BSD_CHECK(R_normal, 1, "expand_right: normal key on a complementary block");
+      const int p = key.p, q = key.q;
+      if (p >= r0 && q >= r0)
+        push(out, Id, {{1.0, K('B', p, q), false}});
+      else if (q >= r0)
+        push(out, s.CD(p), {{1.0, K('c', q), true}});
+      else if (p >= r0)   // a+_p a_q = -a_q a+_p with a_q on s
+        push(out, mat_scale(s.C(q), -1.0), {{1.0, K('c', p), false}});
+      else
+        push(out, mat_mul(s.CD(p), s.C(q)), {{1.0, kIdent, false}});
+      break;
+    }
     case 'c': {
       if (s.has(key.p))
         push(out, s.CD(key.p), {{1.0, kIdent, false}});
@@ -447,7 +471,39 @@ std::vector<Group> expand_right(const OpKey& key, const SiteSet& s, int r0, int 
     default:
       throw Error(1, "expand_right: bad key");
   }
-  return out;
+  if (!R_normal || !haveR) return out;
+  // R holds normal operators: P^R_pq and Q^R_pq become sums over them.
+  //   P^R_pq = 1/2 sum_{r,s in R} (g_pqrs - g_qprs) a_r a_s, and with
+  //   A_rs = a+_r a+_s (r < s): a_r a_s = -A_rs^T, a_s a_r = A_rs^T, so
+  //   P^R_pq = sum_{r<s} 1/2 [(g_pqsr - g_qpsr) - (g_pqrs - g_qprs)] A_rs^T;
+  //   Q^R_pq = sum_{y,y' in R} (g_{p y y' q} - g_{p y q y'}) B_yy'.
+  // A transposed P or Q term transposes every term of its sum.
+  std::vector<Group> res;
+  for (auto& g : out) {
+    Group h;
+    h.M = g.M;
+    for (const auto& t : g.terms) {
+      if (t.key.kind == 'P') {
+        const int p = t.key.p, q = t.key.q;
+        for (int r = r0; r < nmodes; ++r)
+          for (int u = r + 1; u < nmodes; ++u) {
+            const double w = 0.5 * ((I.g(p, q, u, r) - I.g(q, p, u, r)) - (I.g(p, q, r, u) - I.g(q, p, r, u)));
+            if (w != 0.0) h.terms.push_back({t.coef * w, K('A', r, u), !t.trans});
+          }
+      } else if (t.key.kind == 'Q') {
+        const int p = t.key.p, q = t.key.q;
+        for (int y = r0; y < nmodes; ++y)
+          for (int y2 = r0; y2 < nmodes; ++y2) {
+            const double w = I.g(p, y, y2, q) - I.g(p, y, q, y2);
+            if (w != 0.0) h.terms.push_back({t.coef * w, K('B', y, y2), t.trans});
+          }
+      } else {
+        h.terms.push_back(t);
+      }
+    }
+    push(res, h.M, h.terms);
+  }
+  return res;
 }
 
 std::vector<Group> transpose_groups(const std::vector<Group>& gs, const SiteSet& C, int total_par) {

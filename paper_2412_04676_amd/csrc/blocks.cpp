@@ -77,7 +77,7 @@ size_t Block::device_bytes() const {
   return s;
 }
 
-static std::vector<OpKey> block_keys(bool left, int first, int last, int L) {
+static std::vector<OpKey> block_keys(bool left, int first, int last, int L, bool normal) {
   std::vector<OpKey> k;
   const int NM = 2 * L;
   auto add = [&](char c, int p, int q) {
@@ -96,6 +96,16 @@ static std::vector<OpKey> block_keys(bool left, int first, int last, int L) {
     for (int p = 0; p < nm; ++p)
       for (int q = 0; q < nm; ++q) add('B', p, q);
     for (int y = nm; y < NM; ++y) add('S', y, -1);
+  } else if (normal) {
+    // normal operators of the block's own modes (the smaller side)
+    const int m0 = 2 * first;
+    if (first < L) add('H', -1, -1);
+    for (int r = m0; r < NM; ++r) add('c', r, -1);
+    for (int x = 0; x < m0; ++x) add('S', x, -1);
+    for (int p = m0; p < NM; ++p)
+      for (int q = p + 1; q < NM; ++q) add('A', p, q);
+    for (int p = m0; p < NM; ++p)
+      for (int q = m0; q < NM; ++q) add('B', p, q);
   } else {
     const int m0 = 2 * first;
     if (first < L) add('H', -1, -1);
@@ -317,8 +327,14 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
   };
 
   const int nfirst = left ? 0 : site, nlast = left ? site + 1 : L;
-  std::vector<OpKey> keys = block_keys(left, nfirst, nlast, L);
+  // a right block at a bond at or beyond right_normal_from keeps normal
+  // operators; its source must then be normal too (or the vacuum)
+  const bool normal = !left && site >= ctx.right_normal_from;
+  BSD_CHECK(!normal || old->normal || old->first == L, 2,
+            "a right block with normal operators needs a normal (or vacuum) source block");
+  std::vector<OpKey> keys = block_keys(left, nfirst, nlast, L, normal);
   auto nw = alloc_block(left, nfirst, nlast, nb, keys, s);
+  nw->normal = normal;
 
   // expansions and block-side references
   std::vector<Ref> refs;
@@ -334,7 +350,7 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
   for (size_t ki = 0; ki < keys.size(); ++ki) {
     const OpKey& k = keys[ki];
     std::vector<Group> gs = left ? expand_left(k, 2 * site, S, ctx.ints)
-                                 : expand_right(k, S, 2 * (site + 1), NM, ctx.ints);
+                                 : expand_right(k, S, 2 * (site + 1), NM, ctx.ints, old->normal || old->first == L);
     const Q kdq = key_dq(k, left);
     for (auto& g : gs) {
       Q ldq = local_dq(g.M, S);

@@ -275,6 +275,14 @@ int bsdmrg_set_renorm_workspace(bsdmrg_ctx* ctx, size_t bytes) {
   });
 }
 
+int bsdmrg_set_right_normal(bsdmrg_ctx* ctx, int bond) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    BSD_CHECK(bond >= 1, BSDMRG_EINVAL, "bond must be >= 1");
+    ctx->c.right_normal_from = std::min(bond, 1 << 30);
+  });
+}
+
 int bsdmrg_renorm_stats(bsdmrg_ctx* ctx, double* flops, double* wall_s, double* device_s, int64_t* steps) {
   return guard([&] {
     BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");

@@ -32,6 +32,7 @@ struct Ctx {
   std::map<std::pair<int, int>, std::shared_ptr<HpsiPlan>> plans;  // (site, precision)
   DevBuf ws;                 // scratch for renormalization
   size_t renorm_ws_budget = (size_t)8 << 30;   // per batch of new operators
+  int right_normal_from = 1 << 30;   // right blocks at bonds >= this keep normal operators
   // statistics
   double last_hpsi_flops = 0.0;
   double renorm_flops = 0.0;     // useful flops of the grouped-GEMM phases

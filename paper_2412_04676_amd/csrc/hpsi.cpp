@@ -130,6 +130,8 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   Block* Rb = get_block(ctx, false, site + 2);
   BSD_CHECK(Lb && Rb, 1, "environment blocks for this site are not built");
   BSD_CHECK(Lb->resident && Rb->resident, 6, "environment block is offloaded");
+  BSD_CHECK(!Rb->normal, 2, "the right block of this site holds normal operators; the product needs the "
+                            "complementary set (build it with a smaller right_normal_from)");
   const SiteSet C = make_siteset(site, 2);
   const int nL = 2 * site;
   const int r0 = 2 * (site + 2), NM = 2 * ctx.L;

@@ -128,9 +128,13 @@ struct Group {
 // Operators of an enlarged block L . C in the left (normal) role, C on the right.
 std::vector<Group> expand_left(const OpKey& key, int nL_modes, const SiteSet& C,
                                const Integrals& I);
-// Operators of s . R in the right (complementary) role, s on the left.
+// Operators of s . R in the right role, s on the left.  R holds either the
+// complementary set (H, a+_r, S_x, P_pq, Q_pq) or, with R_normal, the normal
+// set of its own modes (H, a+_r, a+_r a+_s, a+_r a_s) plus S_x; then every
+// complementary two-index operator of R is written as its sum over R's normal
+// operators.  Keys 'A' and 'B' (new normal operators) need R_normal.
 std::vector<Group> expand_right(const OpKey& key, const SiteSet& s, int R_mode0, int nmodes,
-                                const Integrals& I);
+                                const Integrals& I, bool R_normal = false);
 // Transpose of an expanded operator (graded: sign (-1)^{|M| |O|}).
 std::vector<Group> transpose_groups(const std::vector<Group>& g, const SiteSet& C,
                                     int op_parity_of_block);
@@ -219,6 +223,7 @@ using SerialPlanPtr = std::unique_ptr<SerialPlan, SerialPlanDeleter>;
 // A renormalized block with its operator families on the device.
 struct Block {
   bool left = true;
+  bool normal = false;       // right block holding normal operators of its own modes
   int first = 0, last = 0;   // sites [first, last)
   Basis basis;               // electrons inside the block
   std::vector<Family> fams;

@@ -322,3 +322,41 @@ def test_explicit_schedule_keeps_the_product(precision, tw, xcd, wm):
     with pytest.raises(RuntimeError):
         B.bsdmrg_hpsi_schedule(ctx, site, precision, 10.0, 1, 64)
     B.bsdmrg_destroy(ctx)
+
+
+@pytest.mark.parametrize("L,na,nb,D,site", [(10, 5, 5, 100, 3), (12, 7, 5, 120, 4)])
+def test_right_blocks_with_normal_operators_convert_to_the_complementary_set(L, na, nb, D, site):
+    """Right blocks beyond site+2 keep normal operators; the block at site+2
+    builds P and Q as sums over them and must equal the block grown with
+    complementary operators all the way."""
+    from paper_2412_04676_amd import bsdmrg as B
+    say(f"normal right blocks L={L} site={site}")
+    ctx1, h, eri, dims, T = build_system(L, na, nb, D, site)
+    ctx2, *_ = build_system(L, na, nb, D, site, build=False)
+    B.bsdmrg_set_right_normal(ctx2, site + 3)
+    B.bsdmrg_build_env(ctx2, B.LEFT, site)
+    B.bsdmrg_build_env(ctx2, B.RIGHT, site + 2)
+    bond = site + 2
+    m0 = 2 * bond
+    keys = [("H",), ("c", m0), ("c", 2 * L - 1), ("S", 0), ("S", m0 - 1), ("P", 0, 1), ("P", 2, m0 - 1),
+            ("Q", 0, 0), ("Q", 1, 4), ("Q", m0 - 1, 3)]
+    checked = 0
+    for k in keys:
+        a = list(k[1:]) + [-1, -1]
+        g1 = B.bsdmrg_get_block_op(ctx1, B.RIGHT, bond, k[0], *a[:2])
+        g2 = B.bsdmrg_get_block_op(ctx2, B.RIGHT, bond, k[0], *a[:2])
+        assert g1.keys() == g2.keys(), k
+        for q in g1:
+            scale = max(1.0, float(np.abs(g1[q]).max()))
+            assert np.abs(g1[q] - g2[q]).max() < 1e-11 * scale, (k, q)
+            checked += 1
+    assert checked > 10
+    psi = psi_for(dims, site, 17)
+    o1, _ = hpsi_gpu(ctx1, site, psi)
+    o2, _ = hpsi_gpu(ctx2, site, psi)
+    assert rel(o2, o1) < 1e-12
+    # a normal block holds A and B of its own spin-orbitals
+    g = B.bsdmrg_get_block_op(ctx2, B.RIGHT, site + 3, "A", 2 * (site + 3), 2 * (site + 3) + 1)
+    assert len(g) > 0
+    B.bsdmrg_destroy(ctx1)
+    B.bsdmrg_destroy(ctx2)
