@@ -39,6 +39,9 @@ def build_workload(L, na, nb, D, site):
     dims, T = random_mps(L, na, nb, D, site)
     ctx = B.bsdmrg_create(L, na, nb)
     B.bsdmrg_load_integrals(ctx, h, eri)
+    # right blocks beyond the product's right bond keep normal operators (the
+    # smaller side); the block at site+2 switches to the complementary set
+    B.bsdmrg_set_right_normal(ctx, site + 3)
     for n, t in enumerate(T):
         if t is not None:
             B.bsdmrg_set_site_tensor(ctx, n, t)
@@ -137,6 +140,7 @@ def main():
     ap.add_argument("--ws-mb", type=int, default=0, help="H.psi workspace budget in MiB (0: library default)")
     ap.add_argument("--precision", type=int, default=0, help="0 fp64, 1 split-bf16 x3, 2 split-bf16 x6")
     ap.add_argument("--no-autotune", action="store_true", help="time the default schedules")
+    ap.add_argument("--dav-iters", type=int, default=40, help="Davidson iteration cap of the site step")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
@@ -251,7 +255,7 @@ def main():
     # serializer and offload of the left environment block
     nbytes = B.bsdmrg_serialized_size(ctx, B.LEFT, site)
     staging = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device="cuda")
-    pinned = torch.empty(nbytes // 8 + 64, dtype=torch.float64).pin_memory()
+    pinned = torch.empty(nbytes // 8 + 64, dtype=torch.float64, pin_memory=True)
     side = torch.cuda.Stream()
     B.bsdmrg_pack(ctx, B.LEFT, site, staging, staging.numel() * 8, stream)
     torch.cuda.synchronize()
@@ -302,7 +306,7 @@ def main():
     torch.cuda.synchronize()
     xs = x.clone()
     t0 = time.time()
-    e_dav, it_dav, r_dav, _ = B.bsdmrg_davidson(ctx, site, xs, max_iter=40, tol=1e-8, precond=1,
+    e_dav, it_dav, r_dav, _ = B.bsdmrg_davidson(ctx, site, xs, max_iter=args.dav_iters, tol=1e-8, precond=1,
                                                 precision=chosen, stream=stream)
     torch.cuda.synchronize()
     t_dav = time.time() - t0
