@@ -316,14 +316,15 @@ __device__ __forceinline__ void load_step64(const WStep& d, const bool* rowok, c
   for (int st = 0; st < 4; ++st) {
     const int k = 4 * st + q;
     const bool kok = k < d.K;
+    // loads on every path (the identity operand's read zeros and its diagonal
+    // is added), so the loads in flight do not depend on the operand kind and
+    // the waits before the MFMAs stay exact
 #pragma unroll
     for (int i = 0; i < NI; ++i) {
-      if (d.ident) {
-        a[st][i] = (rowok[i] && kok && gi[i] == d.kbase + k) ? d.alpha : 0.0;
-      } else {
-        const unsigned o = (rowok[i] && kok) ? (unsigned)(gi[i] * d.ai + k * d.ak) * 8u : kOut64;
-        a[st][i] = d.alpha * __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(d.ra, o, 0, 0));
-      }
+      const unsigned o = (rowok[i] && kok && !d.ident) ? (unsigned)(gi[i] * d.ai + k * d.ak) * 8u : kOut64;
+      const double v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(d.ra, o, 0, 0));
+      const double id = (d.ident && rowok[i] && kok && gi[i] == d.kbase + k) ? d.alpha : 0.0;
+      a[st][i] = d.alpha * v + id;
     }
 #pragma unroll
     for (int j = 0; j < NI; ++j) {

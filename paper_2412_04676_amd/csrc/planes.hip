@@ -161,8 +161,15 @@ __device__ __forceinline__ void load_step(const PSeg& sg, const bool* rowok, con
                                           const int* gj, int q, u32x4_t (&a)[NI][NPL], u32x4_t (&b)[NI][NPL]) {
   const bool cok = q < sg.nch;
   const u32x4_t zero = {0u, 0u, 0u, 0u};
+  // The loads are issued on every path (the identity operand's read zeros and
+  // its h part is then generated in registers), so the number of loads in
+  // flight is the same on every path and the compiler can wait for exactly the
+  // pass it needs instead of for all of them.
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
+    const unsigned o = (rowok[i] && cok && !sg.ident) ? lane_off(gi[i], q, sg.lda) : kBufOut;
+#pragma unroll
+    for (int pl = 0; pl < NPL; ++pl) a[i][pl] = __builtin_amdgcn_raw_buffer_load_b128(sg.ra, o + pl * 128, 0, 0);
     if (sg.ident) {
       // alpha I: the h part is 1.0 (bf16 0x3F80) where row == k
       u32x4_t h = zero;
@@ -171,12 +178,6 @@ __device__ __forceinline__ void load_step(const PSeg& sg, const bool* rowok, con
 #pragma unroll
       for (int w = 0; w < 4; ++w) h[w] = (on && (d >> 1) == w) ? (0x3F80u << (16 * (d & 1))) : 0u;
       a[i][0] = h;
-#pragma unroll
-      for (int pl = 1; pl < NPL; ++pl) a[i][pl] = zero;
-    } else {
-      const unsigned o = (rowok[i] && cok) ? lane_off(gi[i], q, sg.lda) : kBufOut;
-#pragma unroll
-      for (int pl = 0; pl < NPL; ++pl) a[i][pl] = __builtin_amdgcn_raw_buffer_load_b128(sg.ra, o + pl * 128, 0, 0);
     }
   }
 #pragma unroll
