@@ -76,3 +76,31 @@ def test_serialized_size_matches_reference():
                        "rows": rows, "cols": cols, "ld": ld, "elem_offset": off,
                        "layer_stride": int(sum(rows * ld)) + 4, "data": 256})
     assert B.bsdmrg_serialized_size_desc(fams_b) == S.serialized_size(fams_o)
+
+
+def test_block_and_schedule_calls_validate_arguments():
+    from paper_2412_04676_amd import bsdmrg as B
+    ctx = B.bsdmrg_create(6, 3, 3)
+    assert B.bsdmrg_renorm_stats(ctx) == (0.0, 0.0, 0.0, 0)
+    for bond in (0, 6, -1):   # the vacuum blocks stay; out of range
+        with pytest.raises(B.BsdmrgError) as e:
+            B.bsdmrg_drop_block(ctx, B.LEFT, bond)
+        assert e.value.code == B.EINVAL
+    B.bsdmrg_drop_block(ctx, B.RIGHT, 3)   # not built: nothing to free
+    with pytest.raises(B.BsdmrgError) as e:
+        B.bsdmrg_drop_block(ctx, 7, 3)
+    assert e.value.code == B.EINVAL
+    with pytest.raises(B.BsdmrgError) as e:
+        B.bsdmrg_set_right_normal(ctx, 0)
+    assert e.value.code == B.EINVAL
+    B.bsdmrg_set_right_normal(ctx, 4)
+    with pytest.raises(B.BsdmrgError) as e:
+        B.bsdmrg_hpsi_schedule(ctx, 2, B.FP64, 8192, 1, 64)
+    assert e.value.code == B.ESTATE
+    with pytest.raises(B.BsdmrgError) as e:
+        B.bsdmrg_hpsi_schedule(ctx, 2, B.FP64, 10.0, 1, 64)
+    assert e.value.code == B.EINVAL
+    with pytest.raises(B.BsdmrgError) as e:
+        B.bsdmrg_hpsi_schedule(ctx, 2, 9, 8192, 1, 64)
+    assert e.value.code == B.EINVAL
+    B.bsdmrg_destroy(ctx)
