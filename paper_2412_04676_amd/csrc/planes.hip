@@ -131,6 +131,7 @@ struct PSeg {
   int lda, ldb;      // chunks per row group
   int nch;           // chunks of K left from this step (0: empty step)
   int kbase;         // first K index of the step (identity operand)
+  int m0, mt;        // rows of the tile the step was loaded for (identity operand)
   bool ident, fresh, end;
   double alpha;
 };
@@ -145,6 +146,8 @@ __device__ __forceinline__ PSeg decode_step(const GSeg& g, bool valid) {
   w.nch = valid ? (g.K + 7) >> 3 : 0;
   w.kbase = (g.flags >> kStepPassShift) * 32;
   w.ident = g.flags & kIdentA;
+  w.m0 = 0;
+  w.mt = 0;
   w.fresh = g.flags & kStepFresh;
   w.end = valid && (g.flags & kStepEnd);
   w.alpha = g.alpha;
@@ -160,31 +163,38 @@ template <int NI, int NPL>
 __device__ __forceinline__ void load_step(const PSeg& sg, const bool* rowok, const int* gi, const bool* colok,
                                           const int* gj, int q, u32x4_t (&a)[NI][NPL], u32x4_t (&b)[NI][NPL]) {
   const bool cok = q < sg.nch;
-  const u32x4_t zero = {0u, 0u, 0u, 0u};
-  // The loads are issued on every path (the identity operand's read zeros and
-  // its h part is then generated in registers), so the number of loads in
-  // flight is the same on every path and the compiler can wait for exactly the
-  // pass it needs instead of for all of them.
+  // The loads are issued on every path (an identity operand reads zeros; its
+  // h part is generated by ident_rows just before the MFMAs), so the number of
+  // loads in flight is the same on every path and the compiler waits for
+  // exactly one pass instead of for all of them.
 #pragma unroll
   for (int i = 0; i < NI; ++i) {
     const unsigned o = (rowok[i] && cok && !sg.ident) ? lane_off(gi[i], q, sg.lda) : kBufOut;
 #pragma unroll
     for (int pl = 0; pl < NPL; ++pl) a[i][pl] = __builtin_amdgcn_raw_buffer_load_b128(sg.ra, o + pl * 128, 0, 0);
-    if (sg.ident) {
-      // alpha I: the h part is 1.0 (bf16 0x3F80) where row == k
-      u32x4_t h = zero;
-      const int d = gi[i] - sg.kbase - 8 * q;
-      const bool on = rowok[i] && cok && d >= 0 && d < 8;
-#pragma unroll
-      for (int w = 0; w < 4; ++w) h[w] = (on && (d >> 1) == w) ? (0x3F80u << (16 * (d & 1))) : 0u;
-      a[i][0] = h;
-    }
   }
 #pragma unroll
   for (int j = 0; j < NI; ++j) {
     const unsigned o = (colok[j] && cok) ? lane_off(gj[j], q, sg.ldb) : kBufOut;
 #pragma unroll
     for (int pl = 0; pl < NPL; ++pl) b[j][pl] = __builtin_amdgcn_raw_buffer_load_b128(sg.rb, o + pl * 128, 0, 0);
+  }
+}
+
+// The identity operand of a step (its loads returned zeros): the h part is
+// 1.0 (bf16 0x3F80) where row == k, for the rows of the tile the step was
+// loaded for.
+template <int NI, int NPL>
+__device__ __forceinline__ void ident_rows(const PSeg& sg, int r16, int q, u32x4_t (&a)[NI][NPL]) {
+  const bool cok = q < sg.nch;
+#pragma unroll
+  for (int i = 0; i < NI; ++i) {
+    u32x4_t h = {0u, 0u, 0u, 0u};
+    const int d = sg.m0 + i * 16 + r16 - sg.kbase - 8 * q;
+    const bool on = i * 16 + r16 < sg.mt && cok && d >= 0 && d < 8;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) h[w] = (on && (d >> 1) == w) ? (0x3F80u << (16 * (d & 1))) : 0u;
+    a[i][0] = h;
   }
 }
 
@@ -288,7 +298,12 @@ planes_persistent_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GS
   // descriptor of the loader's step: a real step, or an empty one (loads read
   // zeros, no memory access) for a tile without segments or past the last tile
   auto step_desc = [&]() -> PSeg {
-    if (loading && T.nseg > 0) return decode_step(ld_seg(segs, T.seg0 + ls), true);
+    if (loading && T.nseg > 0) {
+      PSeg d = decode_step(ld_seg(segs, T.seg0 + ls), true);
+      d.m0 = T.m0;
+      d.mt = min(TW, T.M - T.m0);
+      return d;
+    }
     GSeg g;
     g.A = 0;
     g.B = 0;
@@ -338,27 +353,31 @@ planes_persistent_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GS
           else acc[i][j][v] += alpha * (double)t[i][j][v];
         }
   };
+  typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
   auto epilogue = [&](const PEpi& e) {
     if (OUTP == 1) {
-      // rows come in groups of 4 inside one chunk; mt is a multiple of 8
-      uint16_t* P = reinterpret_cast<uint16_t*>(const_cast<double*>(resolve(e.C, bases)));
+      // rows come in groups of 4 inside one chunk; mt is a multiple of 8.
+      // Buffer stores: a lane outside the tile stores to the out-of-range
+      // offset (dropped), so every step issues the same stores (park below).
+      const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<double*>(resolve(e.C, bases)), (short)0, 0x7FFFFFFF, kBufFlags);
 #pragma unroll
       for (int i = 0; i < NI; ++i)
 #pragma unroll
         for (int j = 0; j < NI; ++j) {
           const int r = i * 16 + 4 * q;
           const int c = j * 16 + r16;
-          if (r < e.mt && c < e.nt) {
-            unsigned short h[4], m[4], l[4];
+          unsigned short h[4], m[4], l[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) split3f(acc[i][j][v], h[v], m[v], l[v]);
-            // plane row c (a column of C), K index r: parts 64 elements apart
-            uint16_t* d = P + plane_off(c, r >> 3, 0, e.ldc) + (r & 7);
-            typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
-            *reinterpret_cast<u32x2_t*>(d) = u32x2_t{h[0] | ((unsigned)h[1] << 16), h[2] | ((unsigned)h[3] << 16)};
-            *reinterpret_cast<u32x2_t*>(d + 64) = u32x2_t{m[0] | ((unsigned)m[1] << 16), m[2] | ((unsigned)m[3] << 16)};
-            *reinterpret_cast<u32x2_t*>(d + 128) = u32x2_t{l[0] | ((unsigned)l[1] << 16), l[2] | ((unsigned)l[3] << 16)};
-          }
+          for (int v = 0; v < 4; ++v) split3f(acc[i][j][v], h[v], m[v], l[v]);
+          // plane row c (a column of C), K index r: parts 64 elements apart
+          const unsigned o = (r < e.mt && c < e.nt) ? (unsigned)((plane_off(c, r >> 3, 0, e.ldc) + (r & 7)) * 2) : kBufOut;
+          __builtin_amdgcn_raw_buffer_store_b64(u32x2_t{h[0] | ((unsigned)h[1] << 16), h[2] | ((unsigned)h[3] << 16)},
+                                                rc, o, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b64(u32x2_t{m[0] | ((unsigned)m[1] << 16), m[2] | ((unsigned)m[3] << 16)},
+                                                rc, o + 128, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b64(u32x2_t{l[0] | ((unsigned)l[1] << 16), l[2] | ((unsigned)l[3] << 16)},
+                                                rc, o + 256, 0, 0);
         }
     } else {
       double* C = const_cast<double*>(resolve(e.C, bases));
@@ -381,6 +400,17 @@ planes_persistent_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GS
     }
   };
 
+  // a step that does not end its tile issues the epilogue's stores to the
+  // out-of-range offset (dropped): every step then has the same number of
+  // memory operations, and the waits before the MFMAs stay exact
+  auto park = [&]() {
+    if (OUTP == 1) {
+      const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(nullptr, (short)0, 0, kBufFlags);
+      const u32x2_t z = {0u, 0u};
+#pragma unroll
+      for (int k = 0; k < NI * NI * 3; ++k) __builtin_amdgcn_raw_buffer_store_b64(z, rc, kBufOut, 0, 0);
+    }
+  };
   clear_acc();
   u32x4_t a0[NI][NPL], b0[NI][NPL], a1[NI][NPL], b1[NI][NPL];
   // set 0: the first step
@@ -400,11 +430,14 @@ planes_persistent_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GS
     te1 = ls + 1 >= max(T.nseg, 1);
     load_step<NI, NPL>(d1, rowok, gi, colok, gj, q, a1, b1);
     if (loading) advance();
+    if (d0.ident) ident_rows<NI, NPL>(d0, r16, q, a0);
     planes_mfma<NI, NPL, NPROD>(a0, b0, t, d0.fresh);
     if (d0.end) flush(d0.alpha);
     if (te0) {
       epilogue(e0);
       clear_acc();
+    } else {
+      park();
     }
     if (!more1) break;
     // set 0: the step after
@@ -414,11 +447,14 @@ planes_persistent_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GS
     te0 = ls + 1 >= max(T.nseg, 1);
     load_step<NI, NPL>(d0, rowok, gi, colok, gj, q, a0, b0);
     if (loading) advance();
+    if (d1.ident) ident_rows<NI, NPL>(d1, r16, q, a1);
     planes_mfma<NI, NPL, NPROD>(a1, b1, t, d1.fresh);
     if (d1.end) flush(d1.alpha);
     if (te1) {
       epilogue(e1);
       clear_acc();
+    } else {
+      park();
     }
     if (!more0) break;
   }
@@ -475,19 +511,27 @@ wave_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __
   // two steps ahead so their scalar loads are in flight a step early
   if (nseg > 0) {
     u32x4_t a0[NI][NPL], b0[NI][NPL], a1[NI][NPL], b1[NI][NPL];
-    PSeg d0 = decode_step(ld_seg(segs, seg0), true);
+    auto dec = [&](const GSeg& g, bool valid) {
+      PSeg d = decode_step(g, valid);
+      d.m0 = m0;
+      d.mt = mt;
+      return d;
+    };
+    PSeg d0 = dec(ld_seg(segs, seg0), true);
     GSeg gn = ld_seg(segs, seg0 + min(1, nseg - 1));
     load_step<NI, NPL>(d0, rowok, gi, colok, gj, q, a0, b0);
     for (int s = 0;; s += 2) {
-      const PSeg d1 = decode_step(gn, s + 1 < nseg);
+      const PSeg d1 = dec(gn, s + 1 < nseg);
       gn = ld_seg(segs, seg0 + min(s + 2, nseg - 1));
       load_step<NI, NPL>(d1, rowok, gi, colok, gj, q, a1, b1);
+      if (d0.ident) ident_rows<NI, NPL>(d0, r16, q, a0);
       planes_mfma<NI, NPL, NPROD>(a0, b0, t, d0.fresh, ni, nj);
       if (d0.end) flush(d0.alpha);
       if (s + 1 >= nseg) break;
-      d0 = decode_step(gn, s + 2 < nseg);
+      d0 = dec(gn, s + 2 < nseg);
       gn = ld_seg(segs, seg0 + min(s + 3, nseg - 1));
       load_step<NI, NPL>(d0, rowok, gi, colok, gj, q, a0, b0);
+      if (d1.ident) ident_rows<NI, NPL>(d1, r16, q, a1);
       planes_mfma<NI, NPL, NPROD>(a1, b1, t, d1.fresh, ni, nj);
       if (d1.end) flush(d1.alpha);
       if (s + 2 >= nseg) break;
