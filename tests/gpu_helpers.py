@@ -13,12 +13,16 @@ def say(msg):
     sys.stdout.flush()
 
 
-def build_system(L, na, nb, D, site, build=True):
+def build_system(L, na, nb, D, site, build=True, normal_right=False):
+    """normal_right: right blocks beyond site+2 keep normal operators and the
+    block at site+2 switches to the complementary set (as bench.py builds)."""
     from paper_2412_04676_amd import bsdmrg as B
     h, eri = make_integrals(L)
     dims, T = random_mps(L, na, nb, D, site)
     ctx = B.bsdmrg_create(L, na, nb)
     B.bsdmrg_load_integrals(ctx, h, eri)
+    if normal_right:
+        B.bsdmrg_set_right_normal(ctx, site + 3)
     for n, t in enumerate(T):
         if t is not None:
             B.bsdmrg_set_site_tensor(ctx, n, t)

@@ -17,7 +17,7 @@ def test_config2_hpsi_properties():
     L, na, nb, D = 48, 24, 24, 2048
     site = L // 2 - 1
     say(f"config2 L={L} D={D} site={site}: building environments")
-    ctx, h, eri, dims, T = build_system(L, na, nb, D, site)
+    ctx, h, eri, dims, T = build_system(L, na, nb, D, site, normal_right=True)
     s = torch.cuda.current_stream()
     B.bsdmrg_hpsi_prepare(ctx, site, B.FP64, 0, s)
     info = B.bsdmrg_hpsi_info(ctx, site)

@@ -1,5 +1,6 @@
 """Parity at the benchmark's full size (L=24, N=24, S_z=0, D=512, middle
-site), in the configuration bench.py times: sampled outputs against values the
+site), in the configuration bench.py times (right environment grown with
+normal operators, switched at site+2): sampled outputs against values the
 CPU oracle wrote (tests/golden/make_config1_hpsi.py), plus properties that
 hold at any size (symmetry of H_eff, split-bf16 x6 within 1e-6 of float64)."""
 import json
@@ -21,7 +22,7 @@ def config1():
     gold = json.load(open(os.path.join(HERE, "golden", "config1_hpsi_samples.json")))
     L, na, nb, D, site = gold["L"], gold["n_alpha"], gold["n_beta"], gold["D"], gold["site"]
     say(f"config 1 full size: L={L} D={D} site={site}")
-    ctx, h, eri, dims, T = build_system(L, na, nb, D, site)
+    ctx, h, eri, dims, T = build_system(L, na, nb, D, site, normal_right=True)
     lay = B.bsdmrg_psi_layout(ctx, site)
     psi = psi_for(dims, site, gold["psi_seed"])
     x = torch.from_numpy(B.psi_to_flat(psi, lay)).cuda()
