@@ -660,10 +660,13 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     for (auto& kv : p2s[k]) plan->p2s_probs[k].push_back(std::move(kv.second));
   }
   // phase-2 tile lists from the kept problem lists (the autotuner rebuilds
-  // them); default schedule: wave tiles for every block, about 32k waves per
-  // launch
+  // them); default schedule: wave tiles for every block and a split-K target
+  // that grows with the number of K-segments (one wave per ~128 segments,
+  // 8192 to 131072 waves): small products lose more to the part reduction
+  // than they gain in parallelism, large ones the reverse
   plan->opts64.wave_max = 1 << 30;
-  plan->opts64.target_waves = plan->opts_planes.target_waves = 32768;
+  plan->opts64.target_waves = plan->opts_planes.target_waves =
+      std::min(131072.0, std::max(8192.0, (double)plan->nseg / 128.0));
   rebuild_phase2(*plan, plan->opts64, plan->opts_planes, 3);
 
   // ---------------------------------------------------------------- split tasks
