@@ -32,6 +32,27 @@ def build_system(L, na, nb, D, site, build=True, normal_right=False):
     return ctx, h, eri, dims, T
 
 
+def build_system_front_only(L, na, nb, D, site):
+    """Environments grown one bond at a time, freeing the block behind, with
+    normal right blocks switched at site+2 (what bench.py does for large
+    workloads): only the blocks the middle-site product reads stay."""
+    from paper_2412_04676_amd import bsdmrg as B
+    ctx, h, eri, dims, T = build_system(L, na, nb, D, site, build=False, normal_right=True)
+    for b in range(1, site + 1):
+        B.bsdmrg_build_env(ctx, B.LEFT, b)
+        if b > 1:
+            B.bsdmrg_drop_block(ctx, B.LEFT, b - 1)
+        if b % 8 == 0:
+            say(f"  left block {b} built")
+    for b in range(L - 1, site + 1, -1):
+        B.bsdmrg_build_env(ctx, B.RIGHT, b)
+        if b < L - 1:
+            B.bsdmrg_drop_block(ctx, B.RIGHT, b + 1)
+        if b % 8 == 0:
+            say(f"  right block {b} built")
+    return ctx, h, eri, dims, T
+
+
 def hpsi_gpu(ctx, site, psi):
     import torch
     from paper_2412_04676_amd import bsdmrg as B
