@@ -10,6 +10,7 @@
 #include <condition_variable>
 #include <exception>
 #include <mutex>
+#include <system_error>
 #include <thread>
 #include <unordered_map>
 
@@ -697,25 +698,34 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
   std::vector<std::thread> pool;
   int dev = 0;
   BSD_HIP(hipGetDevice(&dev));
-  for (int t = 0; t < nthreads; ++t)
-    pool.emplace_back([&, t] {
-      (void)hipSetDevice(dev);   // a failure shows in the batch's own HIP calls
-      for (;;) {
-        const size_t i = next.fetch_add(1);
-        if (i >= batches.size() || stop.load()) return;
-        Batch& bt = *batches[i];
-        try {
-          plan_batch(bt, ups[t]);
-        } catch (...) {
-          bt.err = std::current_exception();
+  for (int t = 0; t < nthreads; ++t) {
+    try {
+      pool.emplace_back([&, t] {
+        (void)hipSetDevice(dev);   // a failure shows in the batch's own HIP calls
+        for (;;) {
+          const size_t i = next.fetch_add(1);
+          if (i >= batches.size() || stop.load()) return;
+          Batch& bt = *batches[i];
+          try {
+            plan_batch(bt, ups[t]);
+          } catch (...) {
+            bt.err = std::current_exception();
+          }
+          {
+            std::lock_guard<std::mutex> lk(mu);
+            bt.ready = true;
+          }
+          cv.notify_all();
         }
-        {
-          std::lock_guard<std::mutex> lk(mu);
-          bt.ready = true;
-        }
-        cv.notify_all();
-      }
-    });
+      });
+    } catch (const std::system_error&) {
+      break;   // fewer planning threads: the running ones take every batch
+    }
+  }
+  if (pool.empty() && !batches.empty()) {
+    for (auto u : ups) (void)hipStreamDestroy(u);
+    BSD_CHECK(false, 4, "could not start a planning thread");
+  }
   std::vector<hipEvent_t> evs(2 * batches.size(), nullptr);
   std::exception_ptr failure;
   double fl = 0.0;

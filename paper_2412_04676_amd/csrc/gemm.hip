@@ -9,6 +9,7 @@
 // 2x2 v_mfma_f64_16x16x4 accumulators.
 #include <atomic>
 #include <exception>
+#include <system_error>
 #include <thread>
 #include "devutil.h"
 
@@ -802,25 +803,32 @@ void parallel_jobs(int n, const std::function<void(int, hipStream_t)>& fn) {
   std::atomic<int> next{0};
   std::vector<std::exception_ptr> errs(n);
   std::vector<std::thread> pool;
-  for (int t = 0; t < nt; ++t)
-    pool.emplace_back([&] {
-      hipStream_t up = nullptr;
+  auto worker = [&] {
+    hipStream_t up = nullptr;
+    try {
+      BSD_HIP(hipSetDevice(dev));
+      BSD_HIP(hipStreamCreateWithFlags(&up, hipStreamNonBlocking));
+    } catch (...) {
+      up = nullptr;
+    }
+    for (int i; (i = next.fetch_add(1)) < n;) {
       try {
-        BSD_HIP(hipSetDevice(dev));
-        BSD_HIP(hipStreamCreateWithFlags(&up, hipStreamNonBlocking));
+        BSD_CHECK(up != nullptr, 1, "no copy stream for a planning thread");
+        fn(i, up);
       } catch (...) {
-        up = nullptr;
+        errs[i] = std::current_exception();
       }
-      for (int i; (i = next.fetch_add(1)) < n;) {
-        try {
-          BSD_CHECK(up != nullptr, 1, "no copy stream for a planning thread");
-          fn(i, up);
-        } catch (...) {
-          errs[i] = std::current_exception();
-        }
-      }
-      if (up) (void)hipStreamDestroy(up);
-    });
+    }
+    if (up) (void)hipStreamDestroy(up);
+  };
+  for (int t = 0; t < nt; ++t) {
+    try {
+      pool.emplace_back(worker);
+    } catch (const std::system_error&) {
+      break;   // fewer threads: the running ones (or this one) take every job
+    }
+  }
+  if (pool.empty()) worker();
   for (auto& th : pool) th.join();
   for (auto& e : errs)
     if (e) std::rethrow_exception(e);
