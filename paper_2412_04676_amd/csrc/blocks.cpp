@@ -568,6 +568,10 @@ static void renormalize(Ctx& ctx, bool left, int bond, hipStream_t s) {
           terms.push_back(x);
         }
         t.nt = (int)terms.size() - t.t0;
+        int ntrans = 0;
+        for (int k = t.t0; k < t.t0 + t.nt; ++k) ntrans += (terms[k].flags & kTransA) ? 1 : 0;
+        t.col_major = 2 * ntrans > t.nt ? 1 : 0;
+        t.pad = 0;
         tasks.push_back(t);
       }
     }

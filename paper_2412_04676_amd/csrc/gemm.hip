@@ -457,18 +457,34 @@ __global__ void __launch_bounds__(256)
 aggregate_kernel(const AggTask* __restrict__ tasks, const AggTerm* __restrict__ terms) {
   const AggTask t = tasks[blockIdx.x];
   const int n = t.rows * t.cols;
+  // one term's value at (r, c); the term is wave-uniform
+  auto val = [&](const AggTerm& a, int r, int c) -> double {
+    if (a.flags & kIdentA) return (r == c) ? 1.0 : 0.0;
+    if (a.flags & kTransA) return a.in[(int64_t)c * a.ldi + r];
+    return a.in[(int64_t)r * a.ldi + c];
+  };
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int r = e / t.cols, c = e % t.cols;
-    double acc = 0.0;
-    for (int k = 0; k < t.nt; ++k) {
-      const AggTerm a = terms[t.t0 + k];
-      double v;
-      if (a.flags & kIdentA) v = (r == c) ? 1.0 : 0.0;
-      else if (a.flags & kTransA) v = a.in[(int64_t)c * a.ldi + r];
-      else v = a.in[(int64_t)r * a.ldi + c];
-      acc += a.coef * v;
+    // neighbouring lanes read neighbouring addresses of most terms: row by row
+    // for terms read as stored, column by column for terms read transposed
+    const int r = t.col_major ? e % t.rows : e / t.cols;
+    const int c = t.col_major ? e / t.rows : e % t.cols;
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    int k = 0;
+    // four independent loads in flight per lane
+    for (; k + 4 <= t.nt; k += 4) {
+      const AggTerm a0 = terms[t.t0 + k], a1 = terms[t.t0 + k + 1];
+      const AggTerm a2 = terms[t.t0 + k + 2], a3 = terms[t.t0 + k + 3];
+      const double v0 = val(a0, r, c), v1 = val(a1, r, c), v2 = val(a2, r, c), v3 = val(a3, r, c);
+      acc0 += a0.coef * v0;
+      acc1 += a1.coef * v1;
+      acc2 += a2.coef * v2;
+      acc3 += a3.coef * v3;
     }
-    t.out[(int64_t)r * t.ldo + c] = acc;
+    for (; k < t.nt; ++k) {
+      const AggTerm a = terms[t.t0 + k];
+      acc0 += a.coef * val(a, r, c);
+    }
+    t.out[(int64_t)r * t.ldo + c] = (acc0 + acc1) + (acc2 + acc3);
   }
 }
 

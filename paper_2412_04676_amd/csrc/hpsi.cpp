@@ -298,6 +298,10 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
           terms.push_back(x);
         }
         t.nt = (int)terms.size() - t.t0;
+        int ntrans = 0;
+        for (int k = t.t0; k < t.t0 + t.nt; ++k) ntrans += (terms[k].flags & kTransA) ? 1 : 0;
+        t.col_major = 2 * ntrans > t.nt ? 1 : 0;
+        t.pad = 0;
         tasks.push_back(t);
       }
     if (!tasks.empty()) {

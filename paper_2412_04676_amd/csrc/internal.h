@@ -387,6 +387,8 @@ struct AggTask {
   int64_t ldo;
   int32_t rows, cols;
   int32_t t0, nt;
+  int32_t col_major;   // walk the block column by column (most terms are read transposed)
+  int32_t pad;
 };
 void launch_aggregate(const AggTask* tasks_dev, const AggTerm* terms_dev, int ntasks,
                       hipStream_t s);
