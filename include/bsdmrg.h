@@ -122,8 +122,9 @@ int bsdmrg_set_right_normal(bsdmrg_ctx* ctx, int bond);
 
 /* Running totals of the renormalization steps done so far (Sec. II.B step 4):
  * useful flops of the grouped-GEMM phases (2mnk per product), wall seconds,
- * the part of them spent between each launch and its stream synchronization,
- * and the step count.  Any pointer may be NULL. */
+ * device seconds (per batch of new operators, from the start of its first
+ * kernel to the end of its last, by events on `stream`; host planning of later
+ * batches overlaps them) and the step count.  Any pointer may be NULL. */
 int bsdmrg_renorm_stats(bsdmrg_ctx* ctx, double* flops, double* wall_s, double* device_s, int64_t* steps);
 
 /* Layout of the two-site wave function at sites (site, site+1), between the
@@ -153,6 +154,9 @@ int bsdmrg_hpsi_prepare(bsdmrg_ctx* ctx, int site, int precision, size_t ws_byte
  * the chosen and of the default schedule, n_candidates (optional) the number
  * tried.  Results are identical up to the order of float64 additions.
  * Synchronizes `stream`. */
+int bsdmrg_hpsi_autotune(bsdmrg_ctx* ctx, int site, int precision, bsdmrg_stream_t stream, double* best_ms,
+                         double* default_ms, int* n_candidates);
+
 /* Set the schedule of the prepared product at `site` for `precision` directly
  * (one candidate of bsdmrg_hpsi_autotune): the split-K target of waves per
  * launch (256 .. 2^20), XCD placement of locality groups (0/1) and, for
@@ -161,9 +165,6 @@ int bsdmrg_hpsi_prepare(bsdmrg_ctx* ctx, int site, int precision, size_t ws_byte
  * identical up to the order of float64 additions.  ESTATE if not prepared. */
 int bsdmrg_hpsi_schedule(bsdmrg_ctx* ctx, int site, int precision, double target_waves, int xcd_order,
                          int wave_max);
-
-int bsdmrg_hpsi_autotune(bsdmrg_ctx* ctx, int site, int precision, bsdmrg_stream_t stream, double* best_ms,
-                         double* default_ms, int* n_candidates);
 
 /* out = H_eff psi (Sec. II.B step 2) at two-site position `site`; psi and out
  * are device buffers in the layout of bsdmrg_psi_layout and must not overlap.
