@@ -332,7 +332,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16x6 (f32 acc, f64 in/out)" if chosen == B.BF16X6 else "f64",
+        "dtype": "f64" if chosen == B.FP64 else "bf16",   # MFMA operand type; config.precision_path names the scheme
         "data": "synthetic",
         "config": {"workload": f"middle-site two-site H.psi, L={L} N={N} S_z={(na - nb) / 2} D={D} "
                                "(synthetic integrals, random mixed-canonical MPS)",
