@@ -1,5 +1,6 @@
-// Truncation of the two-site wave function (Sec. II.B step 3: "a new basis
-// is formed for the enlarged block via SVD"), float64 on the device.
+// Truncation of the two-site wave function (Sec. II.B step 3, where the
+// enlarged block's new basis comes from a singular value decomposition),
+// float64 on the device.
 //
 // psi is split across the middle bond: rows (s1, q_l), columns (s2, q_r) for
 // each middle sector q_m = q_l + q_s1.  The left (right) singular vectors are

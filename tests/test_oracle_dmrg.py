@@ -63,3 +63,90 @@ def test_split_keeps_degenerate_partners_and_exact_weight():
     kept = sum(keep.values())
     assert kept >= 1
     assert abs(err - sum(x * x for x in s_all[kept:])) < 1e-14 * total
+
+
+def _psi_from_spectrum(dl, dr, spectrum, seed):
+    """Two-site wave function built sector by sector as U diag(sigma) V^T.
+
+    spectrum maps a middle sector q_m to its singular values.  Rows of the
+    sector matrix are the (s1, q_l = q_m - q_s1) pairs present in dl, columns
+    the (s2, q_r = q_m + q_s2) pairs present in dr, both in s order; U and V
+    are random orthonormal columns, so the sector's singular values are exactly
+    the given ones (up to rounding)."""
+    from synthetic.mps import QS
+    rng = np.random.default_rng(seed)
+    psi = {}
+    for qm, sig in spectrum.items():
+        rows = [(s1, (qm[0] - QS[s1][0], qm[1] - QS[s1][1])) for s1 in range(4)]
+        rows = [(s1, q) for s1, q in rows if q in dl]
+        cols = [(s2, (qm[0] + QS[s2][0], qm[1] + QS[s2][1])) for s2 in range(4)]
+        cols = [(s2, q) for s2, q in cols if q in dr]
+        nr = sum(dl[q] for _, q in rows)
+        nc = sum(dr[q] for _, q in cols)
+        k = len(sig)
+        assert k <= min(nr, nc)
+        U = np.linalg.qr(rng.normal(size=(nr, k)))[0]
+        V = np.linalg.qr(rng.normal(size=(nc, k)))[0]
+        M = (U * np.asarray(sig, dtype=float)) @ V.T
+        r0 = 0
+        for s1, ql in rows:
+            c0 = 0
+            for s2, qr in cols:
+                psi[(ql, s1, s2)] = M[r0:r0 + dl[ql], c0:c0 + dr[qr]].copy()
+                c0 += dr[qr]
+            r0 += dl[ql]
+    return psi
+
+
+# bonds of a two-site position in the (n_alpha, n_beta) = (1, 1) sector of a
+# 2-electron problem: middle sectors (1,0), (0,1), (1,1) and (0,0) all occur
+_DL = {(0, 0): 3, (1, 0): 3, (0, 1): 3}
+_DR = {(1, 1): 3, (1, 0): 3, (0, 1): 3, (0, 0): 2}
+
+
+def _kept_sigmas(svd, keep):
+    return sorted((float(x) for qm, k in keep.items() for x in svd[qm][5][:k]), reverse=True)
+
+
+def test_split_distinct_values_keep_exactly_D():
+    """Distinct singular values spread over three sectors: exactly the D largest
+    are kept and the error is the sum of the squares of the others."""
+    spectrum = {(1, 0): [0.70, 0.31, 0.05], (0, 1): [0.52, 0.21, 0.02], (1, 1): [0.40, 0.11]}
+    allsig = sorted((x for v in spectrum.values() for x in v), reverse=True)
+    psi = _psi_from_spectrum(_DL, _DR, spectrum, 1)
+    for D in (1, 2, 3, 5, 7):
+        svd, keep, err = split(psi, _DL, _DR, D)
+        got = sorted((float(x) for v in svd.values() for x in v[5] if x > 1e-12), reverse=True)
+        assert np.allclose(got, allsig, rtol=0, atol=1e-13)
+        assert sum(keep.values()) == D
+        assert np.allclose(_kept_sigmas(svd, keep), allsig[:D], rtol=0, atol=1e-13)
+        assert abs(err - sum(x * x for x in allsig[D:])) < 1e-13
+    # more room than states: everything above the floor stays
+    svd, keep, err = split(psi, _DL, _DR, 100)
+    assert sum(keep.values()) == len(allsig)
+    assert err < 1e-24
+
+
+def test_split_keeps_degenerate_pair_across_sectors():
+    """An exactly degenerate pair straddling position D, one partner in each of
+    two sectors (the spin-flip pair of an S_z = 0 state): both are kept."""
+    spectrum = {(1, 0): [0.70, 0.30, 0.05], (0, 1): [0.50, 0.30, 0.02]}
+    psi = _psi_from_spectrum(_DL, _DR, spectrum, 2)
+    svd, keep, err = split(psi, _DL, _DR, 3)     # 0.70, 0.50, then the 0.30 pair
+    assert keep == {(1, 0): 2, (0, 1): 2}
+    assert abs(err - (0.05 ** 2 + 0.02 ** 2)) < 1e-13
+    # a pair split by more than the 1e-10 relative tolerance is not extended
+    spectrum = {(1, 0): [0.70, 0.30, 0.05], (0, 1): [0.50, 0.30 * (1 - 1e-8), 0.02]}
+    psi = _psi_from_spectrum(_DL, _DR, spectrum, 2)
+    svd, keep, err = split(psi, _DL, _DR, 3)
+    assert keep == {(1, 0): 2, (0, 1): 1}
+
+
+def test_split_drops_values_below_floor():
+    """Values at or below 1e-14 sigma_max are dropped even when fewer than D
+    states exist, and a sector left with nothing disappears from the kept set."""
+    spectrum = {(1, 0): [0.9, 1e-16], (0, 1): [0.4, 0.0], (1, 1): [1e-17]}
+    psi = _psi_from_spectrum(_DL, _DR, spectrum, 3)
+    svd, keep, err = split(psi, _DL, _DR, 64)
+    assert keep == {(1, 0): 1, (0, 1): 1}
+    assert err < 1e-30

@@ -106,3 +106,32 @@ def test_heff_truncated_is_variational():
     v = flat(psi, keys)
     e = v @ flat(op.apply(psi), keys) / (v @ v)
     assert e >= ground_energy(H) - 1e-12
+
+
+@pytest.mark.parametrize("L,na,nb,i", [(6, 3, 3, 2), (6, 4, 2, 2), (5, 3, 2, 1)])
+def test_dense_heff_full_bonds_reproduces_fci(L, na, nb, i):
+    """The dense definition itself: with complete bond bases P is an orthogonal
+    map onto the sector, so P^T H P has exactly the FCI spectrum; its lowest
+    eigenvalue is E_FCI and it is symmetric."""
+    h, eri, dets, H = fci(L, na, nb)
+    dims, T = random_mps(L, na, nb, 10 ** 6, i)
+    op = DenseHeff(H, dets, L, T, i, (na, nb))
+    psi = random_two_site_psi(dims[i], dims[i + 2], 3)
+    keys = list(psi)
+    shapes = [psi[k].shape for k in keys]
+    n = sum(a * b for a, b in shapes)
+    assert n == len(dets)
+
+    def unflat(v):
+        d, o = {}, 0
+        for k, s in zip(keys, shapes):
+            d[k] = v[o:o + s[0] * s[1]].reshape(s)
+            o += s[0] * s[1]
+        return d
+
+    M = np.column_stack([flat(op.apply(unflat(e)), keys) for e in np.eye(n)])
+    assert np.abs(M - M.T).max() < 1e-12 * np.abs(M).max()
+    w = np.linalg.eigvalsh(0.5 * (M + M.T))
+    Hd = H.toarray() if hasattr(H, "toarray") else np.asarray(H)
+    assert np.allclose(w, np.linalg.eigvalsh(Hd), rtol=0, atol=1e-10)
+    assert abs(w[0] - ground_energy(H)) < 1e-10
