@@ -63,9 +63,27 @@ enum { BSDMRG_FP64 = 0, BSDMRG_BF16X3 = 1, BSDMRG_BF16X6 = 2 };
 /* Last error message of the calling thread (never NULL). */
 const char* bsdmrg_last_error(void);
 
-/* Create a context for L spatial orbitals holding n_alpha + n_beta electrons.
- * EINVAL if L < 2 or the electron counts do not fit.  Uses the current device. */
-int bsdmrg_create(bsdmrg_ctx** out, int L, int n_alpha, int n_beta);
+/* Configuration of a context.  The problem is Eq. 1 restricted to the
+ * (n_alpha, n_beta) sector (U(1) x U(1)); the sizes below are device budgets of
+ * the steps of one DMRG iteration (Sec. II.B).  Zero selects the default. */
+typedef struct {
+  int32_t L;                  /* spatial orbitals (2 .. 512) */
+  int32_t n_alpha, n_beta;    /* electrons of each spin */
+  int32_t D_max;              /* largest bond dimension the caller will keep (advisory, >= 0) */
+  size_t hpsi_ws_bytes;       /* per-chunk intermediate workspace of H.psi (default 16 GiB) */
+  size_t renorm_ws_bytes;     /* workspace of one renormalization batch (default 8 GiB) */
+  size_t hbm_budget_bytes;    /* device bytes the two environment blocks of a product may keep
+                                 resident; larger products stream their right-block operator
+                                 families from pinned host memory (bsdmrg_hpsi_stream_*).
+                                 0: no limit */
+  int32_t right_normal_from;  /* as bsdmrg_set_right_normal; 0: no normal right blocks */
+  int32_t flags;              /* reserved, must be 0 */
+} bsdmrg_config;
+
+/* Create a context for cfg->L spatial orbitals holding n_alpha + n_beta
+ * electrons.  EINVAL if L is out of range, the electron counts do not fit, or
+ * flags != 0.  Uses the current device. */
+int bsdmrg_create(bsdmrg_ctx** out, const bsdmrg_config* cfg);
 int bsdmrg_destroy(bsdmrg_ctx* ctx);
 
 /* Integrals of Eq. 1: h (host, L*L) and eri (host, L^4, (pq|rs) at
@@ -85,6 +103,15 @@ int bsdmrg_load_integrals(bsdmrg_ctx* ctx, const double* h, const double* eri, d
 int bsdmrg_set_site_tensor(bsdmrg_ctx* ctx, int site, int n_blocks, const int32_t* meta,
                            const double* data);
 
+/* Read an MPS site tensor (Eq. 2) back in the format of
+ * bsdmrg_set_site_tensor (blocks in ascending (q_left, s) order).  With
+ * meta == NULL only *n_blocks and *n_elems are returned; otherwise meta (host,
+ * n_blocks x 5 int32) and data (host, n_elems float64) are filled.  Tensors
+ * written by bsdmrg_truncate are read the same way.  ESTATE if the site has no
+ * tensor.  Synchronizing. */
+int bsdmrg_get_site_tensor(bsdmrg_ctx* ctx, int site, int* n_blocks, int64_t* n_elems, int32_t* meta,
+                           double* data);
+
 /* Build renormalized block operators (Sec. II.B: preprocessing and
  * renormalization).  side = BSDMRG_LEFT: blocks for bonds 0..bond from the left
  * site tensors 0..bond-1 (left blocks keep H, a+_p, a+_p a+_q, a+_p a_q and the
@@ -94,6 +121,14 @@ int bsdmrg_set_site_tensor(bsdmrg_ctx* ctx, int site, int n_blocks, const int32_
  * left).  Growth starts from the nearest existing block on the way to `bond`;
  * built blocks are kept.  Synchronizes `stream`. */
 int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream);
+
+/* One renormalization step (Sec. II.B step 4): the block of `bond` is
+ * enlarged by one site and projected on the site tensor next to it, giving
+ * the block of bond + 1 (side LEFT, site tensor `bond`, left-canonical) or of
+ * bond - 1 (side RIGHT, site tensor bond - 1, right-canonical).  The source
+ * block must exist and be resident (ESTATE / EBUSY otherwise).  A block that
+ * already exists at the target bond is replaced.  Synchronizes `stream`. */
+int bsdmrg_renormalize(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream);
 
 /* Free a renormalized block (0 < bond < L; the vacuum blocks stay) and every
  * prepared product plan; a later bsdmrg_build_env rebuilds the block when it
@@ -216,6 +251,22 @@ int bsdmrg_davidson(bsdmrg_ctx* ctx, int site, double* psi_dev, const bsdmrg_dav
 int bsdmrg_truncate(bsdmrg_ctx* ctx, int site, const double* psi_dev, int D, int direction, double* trunc_err,
                     int* D_kept, double* sv, int cap, bsdmrg_stream_t stream);
 
+/* Start vector of the next two-site position (Fig. 9 "StVec"; Sec. II.B:
+ * the wave function of one iteration step is carried into the next).  Call
+ * after bsdmrg_truncate(site, psi_dev, ..., direction) and after building the
+ * environment of the next position: direction 0 moves to site + 1 (left block
+ * of bond site+1, right block of bond site+3 must exist) and forms
+ * S V^T B_{site+2} = A_site^T psi B_{site+2}; direction 1 moves to site - 1
+ * (left block of bond site-1, right block of bond site+1) and forms
+ * A_{site-1} U S = A_{site-1} psi B_{site+1}^T.  psi_dev is the wave function
+ * that was truncated, in the layout of `site` (its environment blocks must
+ * still exist); guess_dev receives the start vector in the layout of the next
+ * position (bsdmrg_psi_layout), float64 grouped GEMMs on the device.  Its
+ * norm is sqrt(1 - discarded weight) for a normalized psi.  Synchronizes
+ * `stream`. */
+int bsdmrg_next_guess(bsdmrg_ctx* ctx, int site, int direction, const double* psi_dev, double* guess_dev,
+                      bsdmrg_stream_t stream);
+
 /* Diagonal of H_eff at `site` into diag_dev (psi layout), stream-ordered. */
 int bsdmrg_hpsi_diagonal(bsdmrg_ctx* ctx, int site, double* diag_dev, bsdmrg_stream_t stream);
 
@@ -320,8 +371,41 @@ int bsdmrg_offload_wait(bsdmrg_ctx* ctx, int side, int bond, double* waited_s);
 int bsdmrg_prefetch(bsdmrg_ctx* ctx, int side, int bond, const void* pinned_host, void* staging_dev,
                     size_t bytes, bsdmrg_stream_t compute, bsdmrg_stream_t side_stream);
 
-/* Device bytes held by the block operators of (side, bond). */
+/* Device bytes held by the block operators of (side, bond) (Sec. III.A: the
+ * memory the offload frees). */
 int bsdmrg_block_bytes(bsdmrg_ctx* ctx, int side, int bond, size_t* bytes);
+
+/* Operator families of a renormalized block (Sec. III.B.2: operators sharing
+ * one block-sparse skeleton are serialized together): *n_families families
+ * holding *n_operators operators in total.  Either pointer may be NULL.
+ * ESTATE if the block is not built. */
+int bsdmrg_family_count(bsdmrg_ctx* ctx, int side, int bond, int* n_families, int* n_operators);
+
+/* Running statistics of the context, in the wall-time categories of the
+ * paper's profile of one DMRG sweep (Fig. 9): seconds[] is indexed by the
+ * BSDMRG_PH_* constants and measured on the host around synchronizing calls
+ * (asynchronous calls add their enqueue time only; H.psi products are counted
+ * in hpsi_calls and hpsi_flops).  io_exposed_s is the time spent blocked in
+ * bsdmrg_offload_wait (the fetch that could not be hidden, Sec. III.B.4). */
+enum {
+  BSDMRG_PH_TABLES = 0,   /* product plans: term lists, tile lists, operator planes */
+  BSDMRG_PH_DIAG_H = 1,   /* Davidson (products and vector work) */
+  BSDMRG_PH_REN_L = 2,    /* renormalization of left blocks */
+  BSDMRG_PH_REN_R = 3,    /* renormalization of right blocks */
+  BSDMRG_PH_SVD = 4,      /* truncation */
+  BSDMRG_PH_STVEC = 5,    /* transformation of the wave function into the next guess */
+  BSDMRG_PH_IO = 6,       /* pack, unpack, offload and prefetch calls */
+  BSDMRG_N_PHASES = 7
+};
+typedef struct {
+  double seconds[8];
+  double io_exposed_s;
+  double hpsi_flops, renorm_flops;          /* useful flops (2 m n k) */
+  int64_t hpsi_calls, davidson_calls, davidson_iters, truncations, renorm_steps;
+  int64_t bytes_packed, bytes_unpacked, bytes_d2h, bytes_h2d;
+} bsdmrg_stats_t;
+/* Copy the statistics into *out; reset != 0 clears them afterwards. */
+int bsdmrg_stats(bsdmrg_ctx* ctx, bsdmrg_stats_t* out, int reset);
 
 #ifdef __cplusplus
 }

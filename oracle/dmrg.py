@@ -136,6 +136,15 @@ class OracleDMRG:
     def step(self, i, guess, D, direction):
         heff = self._heff(i)
         e, psi = lowest_eigenpair(heff, guess)
+        err, nxt = self.move(i, psi, D, direction)
+        return e, err, nxt
+
+    def move(self, i, psi, D, direction):
+        """Split psi at (i, i+1) (direction > 0: new left-canonical tensor of
+        site i and left block of bond i+1; else new right-canonical tensor of
+        site i+1 and right block of bond i+1) and carry it into the start vector
+        of the next position: S V^T B_{i+2} or A_{i-1} U S.  Returns the
+        truncation error and that start vector."""
         dl, dr = self.dims[i], self.dims[i + 2]
         svd, keep, err = split(psi, dl, dr, D)
         newdims = dict(sorted(keep.items()))
@@ -158,7 +167,7 @@ class OracleDMRG:
             self.dims[i + 1] = newdims
             enl, ops = enlarge_left(self.left[i], self.t, self.g, 2 * self.L)
             self.left[i + 1] = project_left(self.left[i], enl, ops, A, newdims)
-            return e, err, nxt
+            return err, nxt
         else:
             B = {}
             nxt = {}
@@ -179,7 +188,7 @@ class OracleDMRG:
             self.dims[i + 1] = newdims
             enl, ops = enlarge_right(self.right[i + 2], self.t, self.g)
             self.right[i + 1] = project_right(self.right[i + 2], enl, ops, B, newdims, self.target)
-            return e, err, nxt
+            return err, nxt
 
     def _complete(self, guess, i):
         """Fill blocks missing from a transformed guess with zeros."""

@@ -45,6 +45,26 @@ class FamilyDesc(ctypes.Structure):
                 ("ld", c_vp), ("elem_offset", c_vp), ("layer_stride", ctypes.c_int64), ("data", c_vp)]
 
 
+class Config(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("n_alpha", ctypes.c_int32), ("n_beta", ctypes.c_int32),
+                ("D_max", ctypes.c_int32), ("hpsi_ws_bytes", ctypes.c_size_t),
+                ("renorm_ws_bytes", ctypes.c_size_t), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("right_normal_from", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+PHASES = ("Tables", "Diag_H", "Ren_l", "Ren_r", "SVD", "StVec", "IO")
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("seconds", ctypes.c_double * 8), ("io_exposed_s", ctypes.c_double),
+                ("hpsi_flops", ctypes.c_double), ("renorm_flops", ctypes.c_double),
+                ("hpsi_calls", ctypes.c_int64), ("davidson_calls", ctypes.c_int64),
+                ("davidson_iters", ctypes.c_int64), ("truncations", ctypes.c_int64),
+                ("renorm_steps", ctypes.c_int64), ("bytes_packed", ctypes.c_int64),
+                ("bytes_unpacked", ctypes.c_int64), ("bytes_d2h", ctypes.c_int64),
+                ("bytes_h2d", ctypes.c_int64)]
+
+
 class GemmDesc(ctypes.Structure):
     _fields_ = [("A", c_vp), ("B", c_vp), ("C", c_vp), ("M", ctypes.c_int32), ("N", ctypes.c_int32),
                 ("K", ctypes.c_int32), ("transA", ctypes.c_int32), ("transB", ctypes.c_int32),
@@ -54,7 +74,11 @@ class GemmDesc(ctypes.Structure):
 
 _SIGS = {
     "bsdmrg_last_error": ([], ctypes.c_char_p),
-    "bsdmrg_create": ([ctypes.POINTER(c_vp), c_int, c_int, c_int], c_int),
+    "bsdmrg_create": ([ctypes.POINTER(c_vp), c_vp], c_int),
+    "bsdmrg_get_site_tensor": ([c_vp, c_int, ctypes.POINTER(c_int), c_i64p, c_vp, c_vp], c_int),
+    "bsdmrg_renormalize": ([c_vp, c_int, c_int, c_vp], c_int),
+    "bsdmrg_family_count": ([c_vp, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)], c_int),
+    "bsdmrg_stats": ([c_vp, c_vp, c_int], c_int),
     "bsdmrg_destroy": ([c_vp], c_int),
     "bsdmrg_load_integrals": ([c_vp, c_vp, c_vp, ctypes.c_double], c_int),
     "bsdmrg_set_site_tensor": ([c_vp, c_int, c_int, c_vp, c_vp], c_int),
@@ -77,6 +101,7 @@ _SIGS = {
     "bsdmrg_davidson": ([c_vp, c_int, c_vp, c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_int),
                          ctypes.POINTER(ctypes.c_double), c_vp, c_int, c_vp], c_int),
     "bsdmrg_hpsi_diagonal": ([c_vp, c_int, c_vp, c_vp], c_int),
+    "bsdmrg_next_guess": ([c_vp, c_int, c_int, c_vp, c_vp, c_vp], c_int),
     "bsdmrg_truncate": ([c_vp, c_int, c_vp, c_int, c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_int),
                          c_vp, c_int, c_vp], c_int),
     "bsdmrg_get_block_op": ([c_vp, c_int, c_int, ctypes.c_char, c_int, c_int, ctypes.POINTER(c_int),
@@ -127,10 +152,50 @@ def bsdmrg_last_error():
     return _lib.bsdmrg_last_error().decode()
 
 
-def bsdmrg_create(L, n_alpha, n_beta):
+def bsdmrg_create(L, n_alpha, n_beta, D_max=0, hpsi_ws_bytes=0, renorm_ws_bytes=0, hbm_budget_bytes=0,
+                  right_normal_from=0, flags=0):
+    cfg = Config(L, n_alpha, n_beta, D_max, hpsi_ws_bytes, renorm_ws_bytes, hbm_budget_bytes,
+                 right_normal_from, flags)
     h = c_vp()
-    _check(_lib.bsdmrg_create(ctypes.byref(h), L, n_alpha, n_beta))
+    _check(_lib.bsdmrg_create(ctypes.byref(h), ctypes.byref(cfg)))
     return h
+
+
+def bsdmrg_get_site_tensor(ctx, site):
+    """Returns {(q_left, s): block} of a site tensor (host copies)."""
+    n = c_int()
+    ne = ctypes.c_int64()
+    _check(_lib.bsdmrg_get_site_tensor(ctx, site, ctypes.byref(n), ctypes.byref(ne), None, None))
+    meta = np.zeros((n.value, 5), dtype=np.int32)
+    data = np.zeros(max(1, ne.value))
+    _check(_lib.bsdmrg_get_site_tensor(ctx, site, ctypes.byref(n), ctypes.byref(ne), _ptr(meta), _ptr(data)))
+    out, o = {}, 0
+    for m in meta:
+        r, c = int(m[3]), int(m[4])
+        out[((int(m[0]), int(m[1])), int(m[2]))] = data[o:o + r * c].reshape(r, c).copy()
+        o += r * c
+    return out
+
+
+def bsdmrg_renormalize(ctx, side, bond, stream=None):
+    _check(_lib.bsdmrg_renormalize(ctx, side, bond, _stream(stream)))
+
+
+def bsdmrg_family_count(ctx, side, bond):
+    """Returns (families, operators) of a renormalized block."""
+    f, o = c_int(), c_int()
+    _check(_lib.bsdmrg_family_count(ctx, side, bond, ctypes.byref(f), ctypes.byref(o)))
+    return f.value, o.value
+
+
+def bsdmrg_stats(ctx, reset=False):
+    """Returns the context statistics as a dict (seconds per Fig. 9 phase name)."""
+    st = Stats()
+    _check(_lib.bsdmrg_stats(ctx, ctypes.byref(st), int(bool(reset))))
+    out = {"seconds": {name: st.seconds[i] for i, name in enumerate(PHASES)}}
+    for name, _ in Stats._fields_[1:]:
+        out[name] = getattr(st, name)
+    return out
 
 
 def bsdmrg_destroy(ctx):
@@ -265,6 +330,10 @@ def bsdmrg_davidson(ctx, site, psi_dev, max_iter=50, max_subspace=24, restart=4,
     _check(_lib.bsdmrg_davidson(ctx, site, _ptr(psi_dev), ctypes.byref(o), ctypes.byref(e), ctypes.byref(it),
                                 ctypes.byref(r), _ptr(ritz), len(ritz), _stream(stream)))
     return e.value, it.value, r.value, list(ritz[:it.value])
+
+
+def bsdmrg_next_guess(ctx, site, direction, psi_dev, guess_dev, stream=None):
+    _check(_lib.bsdmrg_next_guess(ctx, site, direction, _ptr(psi_dev), _ptr(guess_dev), _stream(stream)))
 
 
 def bsdmrg_hpsi_diagonal(ctx, site, diag_dev, stream=None):

@@ -5,6 +5,7 @@
 #include <cmath>
 
 #include "davidson.h"
+#include "stvec.h"
 #include "truncate.h"
 
 struct bsdmrg_ctx {
@@ -17,6 +18,18 @@ static thread_local std::string g_err;
 void set_last_error(const std::string& m) { g_err = m; }
 
 static hipStream_t S(bsdmrg_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+static double wall_now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// adds the wall time of its scope to one phase of the context statistics
+struct PhaseTimer {
+  double* acc;
+  double t0;
+  PhaseTimer(Ctx& c, int ph) : acc(&c.st.sec[ph]), t0(wall_now()) {}
+  ~PhaseTimer() { *acc += wall_now() - t0; }
+};
 
 template <class F>
 static int guard(F&& f) {
@@ -122,20 +135,27 @@ extern "C" {
 
 const char* bsdmrg_last_error(void) { return g_err.c_str(); }
 
-int bsdmrg_create(bsdmrg_ctx** out, int L, int n_alpha, int n_beta) {
+int bsdmrg_create(bsdmrg_ctx** out, const bsdmrg_config* cfg) {
   return guard([&] {
-    BSD_CHECK(out != nullptr, BSDMRG_EINVAL, "out is NULL");
+    BSD_CHECK(out != nullptr && cfg != nullptr, BSDMRG_EINVAL, "NULL argument");
+    const int L = cfg->L, n_alpha = cfg->n_alpha, n_beta = cfg->n_beta;
     BSD_CHECK(L >= 2 && L <= 512, BSDMRG_EINVAL, "L out of range");
     BSD_CHECK(n_alpha >= 0 && n_beta >= 0 && n_alpha <= L && n_beta <= L, BSDMRG_EINVAL,
               "electron counts do not fit");
-    auto* x = new bsdmrg_ctx();
+    BSD_CHECK(cfg->D_max >= 0 && cfg->right_normal_from >= 0, BSDMRG_EINVAL, "negative configuration value");
+    BSD_CHECK(cfg->flags == 0, BSDMRG_EINVAL, "unknown configuration flags");
+    auto x = std::make_unique<bsdmrg_ctx>();
     x->c.L = L;
     x->c.na = n_alpha;
     x->c.nb = n_beta;
     x->c.target = {n_alpha, n_beta};
     x->c.sites.resize(L);
+    if (cfg->hpsi_ws_bytes) x->c.hpsi_ws_default = cfg->hpsi_ws_bytes;
+    if (cfg->renorm_ws_bytes) x->c.renorm_ws_budget = cfg->renorm_ws_bytes;
+    x->c.hbm_budget = cfg->hbm_budget_bytes;
+    if (cfg->right_normal_from) x->c.right_normal_from = cfg->right_normal_from;
     make_vacuum_blocks(x->c);
-    *out = x;
+    *out = x.release();
   });
 }
 
@@ -244,6 +264,47 @@ int bsdmrg_set_site_tensor(bsdmrg_ctx* ctx, int site, int n_blocks, const int32_
   });
 }
 
+int bsdmrg_get_site_tensor(bsdmrg_ctx* ctx, int site, int* n_blocks, int64_t* n_elems, int32_t* meta,
+                           double* data) {
+  return guard([&] {
+    BSD_CHECK(ctx && n_blocks && n_elems, BSDMRG_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    BSD_CHECK(site >= 0 && site < c.L, BSDMRG_EINVAL, "site out of range");
+    const SiteTensor& T = c.sites[site];
+    BSD_CHECK(T.set, BSDMRG_ESTATE, "site tensor not set");
+    // ascending (q_left, s)
+    std::vector<int> order(T.blocks.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+      const Q qx = T.left.q[T.blocks[x].l], qy = T.left.q[T.blocks[y].l];
+      if (qx != qy) return qx < qy;
+      return T.blocks[x].s < T.blocks[y].s;
+    });
+    int64_t ne = 0;
+    for (const auto& b : T.blocks) ne += (int64_t)b.rows * b.cols;
+    *n_blocks = (int)T.blocks.size();
+    *n_elems = ne;
+    if (!meta) return;
+    BSD_CHECK(data != nullptr || ne == 0, BSDMRG_EINVAL, "data is NULL");
+    std::vector<double> all(ne);
+    if (ne) BSD_HIP(hipMemcpy(all.data(), T.mem.p, ne * sizeof(double), hipMemcpyDeviceToHost));
+    int64_t o = 0;
+    for (size_t i = 0; i < order.size(); ++i) {
+      const auto& b = T.blocks[order[i]];
+      const Q ql = T.left.q[b.l];
+      int32_t* m = meta + 5 * i;
+      m[0] = ql.a;
+      m[1] = ql.b;
+      m[2] = b.s;
+      m[3] = b.rows;
+      m[4] = b.cols;
+      const int64_t n = (int64_t)b.rows * b.cols;
+      std::copy(all.begin() + b.off, all.begin() + b.off + n, data + o);
+      o += n;
+    }
+  });
+}
+
 int bsdmrg_truncate(bsdmrg_ctx* ctx, int site, const double* psi, int D, int direction, double* trunc_err,
                     int* D_kept, double* sv, int cap, bsdmrg_stream_t stream) {
   return guard([&] {
@@ -252,6 +313,8 @@ int bsdmrg_truncate(bsdmrg_ctx* ctx, int site, const double* psi, int D, int dir
     BSD_CHECK(direction == 0 || direction == 1, BSDMRG_EINVAL, "direction must be 0 (left to right) or 1");
     Ctx& c = ctx->c;
     HpsiPlan* p = get_plan(c, site, BSDMRG_FP64, 0, S(stream), false);
+    PhaseTimer tm(c, BSDMRG_PH_SVD);
+    c.st.truncations += 1;
     TruncResult r = truncate_psi(c, *p, psi, D, direction == 0, p->dav_work, S(stream));
     BSD_CHECK(!r.blocks.empty(), BSDMRG_ESHAPE, "nothing kept");
     std::vector<int32_t> meta;
@@ -304,6 +367,7 @@ int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream
     if (side == BSDMRG_LEFT) {
       int b0 = bond;
       while (b0 > 0 && !get_block(c, true, b0)) --b0;
+      PhaseTimer tm(c, BSDMRG_PH_REN_L);
       for (int b = b0; b < bond; ++b) {
         BSD_CHECK(c.sites[b].set, BSDMRG_ESTATE, "site tensor missing");
         Block* cur = get_block(c, true, b);
@@ -314,6 +378,7 @@ int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream
       BSD_CHECK(side == BSDMRG_RIGHT, BSDMRG_EINVAL, "side must be LEFT or RIGHT");
       int b0 = bond;
       while (b0 < c.L && !get_block(c, false, b0)) ++b0;
+      PhaseTimer tm(c, BSDMRG_PH_REN_R);
       for (int b = b0; b > bond; --b) {
         BSD_CHECK(c.sites[b - 1].set, BSDMRG_ESTATE, "site tensor missing");
         Block* cur = get_block(c, false, b);
@@ -321,6 +386,33 @@ int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream
         renormalize_right_block(c, b, S(stream));
       }
     }
+    BSD_HIP(hipStreamSynchronize(S(stream)));
+  });
+}
+
+int bsdmrg_renormalize(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    Ctx& c = ctx->c;
+    BSD_CHECK(c.have_ints, BSDMRG_ESTATE, "integrals not loaded");
+    BSD_CHECK(side == BSDMRG_LEFT || side == BSDMRG_RIGHT, BSDMRG_EINVAL, "side must be LEFT or RIGHT");
+    const bool left = side == BSDMRG_LEFT;
+    BSD_CHECK(left ? (bond >= 0 && bond < c.L) : (bond > 0 && bond <= c.L), BSDMRG_EINVAL, "bond out of range");
+    const int site = left ? bond : bond - 1;
+    BSD_CHECK(c.sites[site].set, BSDMRG_ESTATE, "site tensor missing");
+    Block* cur = get_block(c, left, bond);
+    BSD_CHECK(cur != nullptr, BSDMRG_ESTATE, "source block not built");
+    BSD_CHECK(cur->resident, BSDMRG_EBUSY, "source block not resident");
+    auto& m = left ? c.left : c.right;
+    auto it = m.find(left ? bond + 1 : bond - 1);
+    if (it != m.end()) {
+      BSD_CHECK(!it->second->offload_pending, BSDMRG_EBUSY, "offload of the target block in flight; wait first");
+      BSD_HIP(hipDeviceSynchronize());
+      c.plans.clear();   // plans may reference the block that is replaced
+    }
+    PhaseTimer tm(c, left ? BSDMRG_PH_REN_L : BSDMRG_PH_REN_R);
+    if (left) renormalize_left_block(c, bond, S(stream));
+    else renormalize_right_block(c, bond, S(stream));
     BSD_HIP(hipStreamSynchronize(S(stream)));
   });
 }
@@ -348,7 +440,8 @@ static HpsiPlan* get_plan(Ctx& c, int site, int precision, size_t ws, hipStream_
   auto key = std::make_pair(site, 0);   // one plan serves every precision
   auto it = c.plans.find(key);
   if (it != c.plans.end() && !rebuild) return it->second.get();
-  if (ws == 0) ws = (size_t)16 << 30;
+  if (ws == 0) ws = c.hpsi_ws_default;
+  PhaseTimer tm(c, BSDMRG_PH_TABLES);
   auto p = build_hpsi_plan(c, site, precision, ws, s);
   HpsiPlan* raw = p.get();
   c.plans[key] = std::move(p);
@@ -446,6 +539,8 @@ int bsdmrg_hpsi(bsdmrg_ctx* ctx, int site, const double* psi, double* out, int p
     BSD_CHECK(!(out < pe && psi < out + p->lay.n_elems), BSDMRG_EINVAL, "psi and out overlap");
     run_hpsi_graph(*p, psi, out, S(stream), precision);
     ctx->c.last_hpsi_flops = p->useful_flops;
+    ctx->c.st.hpsi_calls += 1;
+    ctx->c.st.hpsi_flops += p->useful_flops;
   });
 }
 
@@ -485,13 +580,30 @@ int bsdmrg_davidson(bsdmrg_ctx* ctx, int site, double* psi, const bsdmrg_dav_opt
       o.tol = opts->tol;
       o.precond_floor = opts->precond_floor;
     }
+    PhaseTimer tm(ctx->c, BSDMRG_PH_DIAG_H);
     const double* d = hpsi_diagonal(*p, S(stream));
     DavidsonResult r = davidson(*p, d, psi, o, p->dav_work, S(stream));
+    ctx->c.st.dav_calls += 1;
+    ctx->c.st.dav_iters += r.iters;
+    ctx->c.st.hpsi_calls += r.products;
+    ctx->c.st.hpsi_flops += r.products * p->useful_flops;
     *energy = r.energy;
     *iters = r.iters;
     *resid = r.resid;
     if (ritz)
       for (int i = 0; i < cap && i < (int)r.ritz.size(); ++i) ritz[i] = r.ritz[i];
+  });
+}
+
+int bsdmrg_next_guess(bsdmrg_ctx* ctx, int site, int direction, const double* psi, double* guess,
+                      bsdmrg_stream_t stream) {
+  return guard([&] {
+    BSD_CHECK(ctx && psi && guess, BSDMRG_EINVAL, "NULL argument");
+    BSD_CHECK(direction == 0 || direction == 1, BSDMRG_EINVAL, "direction must be 0 (left to right) or 1");
+    Ctx& c = ctx->c;
+    BSD_CHECK(site >= 0 && site + 1 < c.L, BSDMRG_EINVAL, "site out of range");
+    PhaseTimer tm(c, BSDMRG_PH_STVEC);
+    next_guess(c, site, direction == 0, psi, guess, c.ws, S(stream));
   });
 }
 
@@ -642,9 +754,11 @@ int bsdmrg_pack(bsdmrg_ctx* ctx, int side, int bond, void* dst, size_t cap, bsdm
     BSD_CHECK(ctx && dst, BSDMRG_EINVAL, "NULL argument");
     Block* b = need_block(ctx->c, side, bond);
     BSD_CHECK(b->resident, BSDMRG_EBUSY, "block not resident");
+    PhaseTimer tm(ctx->c, BSDMRG_PH_IO);
     ensure_splan(*b, S(stream));
     serial_pack(*b->splan, dst, cap, S(stream));
     BSD_HIP(hipStreamSynchronize(S(stream)));
+    ctx->c.st.bytes_packed += (int64_t)serial_bytes(*b->splan);
   });
 }
 
@@ -653,12 +767,14 @@ int bsdmrg_unpack(bsdmrg_ctx* ctx, int side, int bond, const void* src, size_t b
     BSD_CHECK(ctx && src, BSDMRG_EINVAL, "NULL argument");
     Block* b = need_block(ctx->c, side, bond);
     BSD_CHECK(!b->offload_pending, BSDMRG_EBUSY, "offload in flight; wait first");
+    PhaseTimer tm(ctx->c, BSDMRG_PH_IO);
     if (!b->resident) realloc_block(*b, S(stream));
     ensure_splan(*b, S(stream));
     BSD_CHECK(bytes == serial_bytes(*b->splan), BSDMRG_ECORRUPT, "stream size does not match the block");
     serial_unpack(*b->splan, src, bytes, S(stream));
     int st = serial_status(*b->splan, S(stream));
     BSD_CHECK(st == 0, BSDMRG_ECORRUPT, "stream tables do not match the block");
+    ctx->c.st.bytes_unpacked += (int64_t)bytes;
     ctx->c.plans.clear();
   });
 }
@@ -734,6 +850,45 @@ int bsdmrg_block_bytes(bsdmrg_ctx* ctx, int side, int bond, size_t* bytes) {
     BSD_CHECK(ctx && bytes, BSDMRG_EINVAL, "NULL argument");
     Block* b = need_block(ctx->c, side, bond);
     *bytes = b->resident ? b->device_bytes() : 0;
+  });
+}
+
+int bsdmrg_family_count(bsdmrg_ctx* ctx, int side, int bond, int* n_families, int* n_operators) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    Block* b = need_block(ctx->c, side, bond);
+    int nop = 0;
+    for (const auto& f : b->fams) nop += (int)f.keys.size();
+    if (n_families) *n_families = (int)b->fams.size();
+    if (n_operators) *n_operators = nop;
+  });
+}
+
+int bsdmrg_stats(bsdmrg_ctx* ctx, bsdmrg_stats_t* out, int reset) {
+  return guard([&] {
+    BSD_CHECK(ctx && out, BSDMRG_EINVAL, "NULL argument");
+    Ctx& c = ctx->c;
+    std::memset(out, 0, sizeof(*out));
+    for (int i = 0; i < BSDMRG_N_PHASES; ++i) out->seconds[i] = c.st.sec[i];
+    out->io_exposed_s = c.st.io_exposed_s;
+    out->hpsi_flops = c.st.hpsi_flops;
+    out->renorm_flops = c.renorm_flops;
+    out->hpsi_calls = c.st.hpsi_calls;
+    out->davidson_calls = c.st.dav_calls;
+    out->davidson_iters = c.st.dav_iters;
+    out->truncations = c.st.truncations;
+    out->renorm_steps = c.renorm_steps;
+    out->bytes_packed = c.st.bytes_packed;
+    out->bytes_unpacked = c.st.bytes_unpacked;
+    out->bytes_d2h = c.st.bytes_d2h;
+    out->bytes_h2d = c.st.bytes_h2d;
+    if (reset) {
+      c.st = Ctx::Stats();
+      c.renorm_flops = 0.0;
+      c.renorm_wall_s = 0.0;
+      c.renorm_dev_s = 0.0;
+      c.renorm_steps = 0;
+    }
   });
 }
 

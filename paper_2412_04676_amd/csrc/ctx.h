@@ -34,6 +34,15 @@ struct Ctx {
   size_t renorm_ws_budget = (size_t)8 << 30;   // per batch of new operators
   int right_normal_from = 1 << 30;   // right blocks at bonds >= this keep normal operators
   // statistics
+  struct Stats {
+    double sec[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // wall seconds per phase (Fig. 9 categories)
+    double io_exposed_s = 0.0;
+    double hpsi_flops = 0.0;
+    int64_t hpsi_calls = 0, dav_calls = 0, dav_iters = 0, truncations = 0;
+    int64_t bytes_packed = 0, bytes_unpacked = 0, bytes_d2h = 0, bytes_h2d = 0;
+  } st;
+  size_t hpsi_ws_default = (size_t)16 << 30;
+  size_t hbm_budget = 0;
   double last_hpsi_flops = 0.0;
   double renorm_flops = 0.0;     // useful flops of the grouped-GEMM phases
   double renorm_wall_s = 0.0;    // wall time of renormalization steps

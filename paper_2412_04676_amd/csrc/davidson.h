@@ -17,6 +17,7 @@ struct DavidsonOpts {
 struct DavidsonResult {
   double energy = 0.0, resid = 0.0;
   int iters = 0;
+  int products = 0;           // H.psi products applied (both stages)
   std::vector<double> ritz;   // lowest Ritz value after every iteration
 };
 

@@ -267,6 +267,7 @@ DavidsonResult davidson(HpsiPlan& plan, const double* diag, double* psi, const D
     BSD_HIP(hipMemcpyAsync(sin, in, n * sizeof(double), hipMemcpyDeviceToDevice, s));
     run_hpsi_graph(plan, sin, sout, s, prec);
     BSD_HIP(hipMemcpyAsync(out, sout, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    ++res.products;
   };
   auto normalize_into = [&](const double* in, double* out) {
     dots(w, in, 1, in, w.sc + 2, s);

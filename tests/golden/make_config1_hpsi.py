@@ -1,8 +1,9 @@
 """Writes config1_hpsi_samples.json: the CPU oracle's middle-site product H.psi
 for L=24 orbitals, N=24 electrons, S_z=0, D=512 (seeded synthetic integrals,
 seeded random mixed-canonical MPS around sites 11, 12, psi seed 1), reduced to
-<psi|H psi>, |H psi| and 300 sampled elements.  Calls only oracle/ and the
-shared input generators.  Run from the repository root:
+<psi|H psi>, |H psi| and 300 sampled elements, and config1_hpsi_full.npy: the
+whole product, blocks in sorted (q_l, s1, s2) order, each row-major.  Calls
+only oracle/ and the shared input generators.  Run from the repository root:
     python tests/golden/make_config1_hpsi.py
 """
 import json
@@ -42,7 +43,9 @@ def main():
         i = int(rng.integers(out[k].shape[0]))
         j = int(rng.integers(out[k].shape[1]))
         samples.append({"ql": list(k[0]), "s1": k[1], "s2": k[2], "i": i, "j": j, "value": float(out[k][i, j])})
-    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "config1_hpsi_samples.json"), "w") as f:
+    here = os.path.dirname(os.path.abspath(__file__))
+    np.save(os.path.join(here, "config1_hpsi_full.npy"), np.concatenate([out[k].ravel() for k in keys]))
+    with open(os.path.join(here, "config1_hpsi_samples.json"), "w") as f:
         json.dump({"L": L, "n_alpha": NA, "n_beta": NB, "D": D, "site": SITE, "psi_seed": PSI_SEED,
                    "norm": norm, "rayleigh": rq, "samples": samples}, f, indent=0)
 

@@ -1,8 +1,9 @@
-"""Parity at the benchmark's full size (L=24, N=24, S_z=0, D=512, middle
-site), in the configuration bench.py times (right environment grown with
-normal operators, switched at site+2): sampled outputs against values the
-CPU oracle wrote (tests/golden/make_config1_hpsi.py), plus properties that
-hold at any size (symmetry of H_eff, split-bf16 x6 within 1e-6 of float64)."""
+"""Parity at the L=24, N=24, S_z=0, D=512 middle-site product, with the right
+environment grown with normal operators and switched at site+2: the whole
+product against the CPU oracle's (written by tests/golden/make_config1_hpsi.py,
+relative 2-norm error <= 1e-10 in float64, <= 1e-6 for split-bf16 x6), its
+norm, Rayleigh quotient and sampled elements, plus properties that hold at any
+size (symmetry of H_eff)."""
 import json
 import os
 
@@ -45,6 +46,22 @@ def test_config1_sampled_outputs_match_oracle(config1):
     for s in gold["samples"]:
         v = out[(tuple(s["ql"]), s["s1"], s["s2"])][s["i"], s["j"]]
         assert abs(v - s["value"]) <= 1e-10 * gold["norm"], s
+
+
+@pytest.mark.parametrize("precision,bar", [(0, 1e-10), (2, 1e-6)])
+def test_config1_full_product_matches_oracle(config1, precision, bar):
+    import torch
+    B, ctx, site, lay, x, gold = config1
+    y = torch.empty_like(x)
+    B.bsdmrg_hpsi(ctx, site, x, y, precision)
+    torch.cuda.synchronize()
+    out = B.flat_to_psi(y.cpu().numpy(), lay)
+    got = np.concatenate([out[k].ravel() for k in sorted(out)])
+    ref = np.load(os.path.join(HERE, "golden", "config1_hpsi_full.npy"))
+    assert got.shape == ref.shape
+    e = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    say(f"  precision {precision}: full-vector relative error {e:.3e}")
+    assert e <= bar
 
 
 def test_config1_heff_symmetric(config1):

@@ -1,0 +1,107 @@
+"""The start vector of the next two-site position (Fig. 9 "StVec") and the
+site tensor written by the truncation, against the oracle's split and move on
+the same wave function.  Singular vectors are defined up to sign (and
+rotation inside degenerate values), so the comparison uses quantities that do
+not depend on that choice: the projector U U^T per middle sector, and the
+three-site contraction A . guess (left to right) or guess . B (right to left),
+which equals the projected psi times the next site tensor."""
+import numpy as np
+import pytest
+
+from gpu_helpers import build_system, psi_for, say
+from oracle.blocks import build_left_blocks, build_right_blocks
+from oracle.dmrg import OracleDMRG
+from oracle.siteops import QSITE, spin_orbital_integrals
+
+pytestmark = pytest.mark.gpu
+
+
+def _qa(a, b):
+    return (a[0] + b[0], a[1] + b[1])
+
+
+def _oracle_at(h, eri, na, nb, dims, T, site):
+    t, g = spin_orbital_integrals(h, eri)
+    d = OracleDMRG(h, eri, na, nb, 4)
+    d.T = list(T)
+    d.dims = list(dims)
+    d.left = build_left_blocks(d.T, site, t, g)
+    d.right = build_right_blocks(d.T, site + 2, t, g, (na, nb))
+    return d
+
+
+def _contract_lr(A, guess):
+    out = {}
+    for (ql, s1), a in A.items():
+        qm = _qa(ql, QSITE[s1])
+        for (q, s2, s3), gblk in guess.items():
+            if q == qm:
+                out[(ql, s1, s2, s3)] = a @ gblk
+    return out
+
+
+def _contract_rl(guess, Bt):
+    out = {}
+    for (qll, s0, s1), gblk in guess.items():
+        qm = _qa(_qa(qll, QSITE[s0]), QSITE[s1])
+        for (q, s2), b in Bt.items():
+            if q == qm:
+                out[(qll, s0, s1, s2)] = gblk @ b
+    return out
+
+
+def _close(a, b, tol):
+    keys = set(a) | set(b)
+    scale = max(max(np.abs(x).max() for x in b.values()), 1e-300)
+    for k in keys:
+        x = a.get(k)
+        y = b.get(k)
+        if x is None:
+            x = np.zeros_like(y)
+        if y is None:
+            y = np.zeros_like(x)
+        assert np.abs(x - y).max() <= tol * scale, k
+
+
+@pytest.mark.parametrize("L,na,nb,D,site,Dkeep,direction", [
+    (8, 4, 4, 40, 3, 12, 0), (8, 4, 4, 40, 3, 12, 1), (10, 6, 5, 60, 4, 20, 0), (10, 6, 5, 60, 4, 20, 1)])
+def test_next_guess_matches_oracle(L, na, nb, D, site, Dkeep, direction):
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    say(f"stvec L={L} ({na},{nb}) D={D} site={site} keep {Dkeep} direction {direction}")
+    ctx, h, eri, dims, T = build_system(L, na, nb, D, site)
+    psi = psi_for(dims, site, 21)
+    n2 = sum(float(np.sum(b * b)) for b in psi.values())
+    psi = {k: b / np.sqrt(n2) for k, b in psi.items()}
+    lay = B.bsdmrg_psi_layout(ctx, site)
+    x = torch.from_numpy(B.psi_to_flat(psi, lay)).cuda()
+    err, kept, sv = B.bsdmrg_truncate(ctx, site, x, Dkeep, direction)
+    nxt_site = site + 1 if direction == 0 else site - 1
+    B.bsdmrg_build_env(ctx, B.LEFT, nxt_site)
+    B.bsdmrg_build_env(ctx, B.RIGHT, nxt_site + 2)
+    nlay = B.bsdmrg_psi_layout(ctx, nxt_site)
+    gd = torch.empty(nlay[2], dtype=torch.float64, device="cuda")
+    B.bsdmrg_next_guess(ctx, site, direction, x, gd)
+    guess = B.flat_to_psi(gd.cpu().numpy(), nlay)
+    tensor = B.bsdmrg_get_site_tensor(ctx, site if direction == 0 else site + 1)
+    ora = _oracle_at(h, eri, na, nb, dims, T, site)
+    oerr, onxt = ora.move(site, psi, Dkeep, +1 if direction == 0 else -1)
+    otensor = ora.T[site] if direction == 0 else ora.T[site + 1]
+    say(f"  kept {kept}, discarded weight gpu {err:.6e} oracle {oerr:.6e}")
+    assert abs(err - oerr) <= 1e-12
+    gn2 = float(torch.dot(gd, gd))
+    assert abs(gn2 - (1.0 - err)) <= 1e-12
+    # projector per middle sector: sum over blocks of A A^T (left) or B^T B (right)
+    if direction == 0:
+        for (ql, s1), a in otensor.items():
+            ga = tensor[(ql, s1)]
+            assert ga.shape == a.shape
+            assert np.abs(ga @ ga.T - a @ a.T).max() <= 1e-10
+        _close(_contract_lr(tensor, guess), _contract_lr(otensor, onxt), 1e-10)
+    else:
+        for (qm, s2), b in otensor.items():
+            gb = tensor[(qm, s2)]
+            assert gb.shape == b.shape
+            assert np.abs(gb.T @ gb - b.T @ b).max() <= 1e-10
+        _close(_contract_rl(guess, tensor), _contract_rl(onxt, otensor), 1e-10)
+    B.bsdmrg_destroy(ctx)

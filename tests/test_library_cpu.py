@@ -104,3 +104,48 @@ def test_block_and_schedule_calls_validate_arguments():
         B.bsdmrg_hpsi_schedule(ctx, 2, 9, 8192, 1, 64)
     assert e.value.code == B.EINVAL
     B.bsdmrg_destroy(ctx)
+
+
+def test_config_and_state_calls_validate_arguments():
+    from paper_2412_04676_amd import bsdmrg as B
+    with pytest.raises(B.BsdmrgError) as e:
+        B.bsdmrg_create(6, 3, 3, flags=1)
+    assert e.value.code == B.EINVAL
+    with pytest.raises(B.BsdmrgError) as e:
+        B.bsdmrg_create(6, 3, 3, D_max=-1)
+    assert e.value.code == B.EINVAL
+    ctx = B.bsdmrg_create(6, 3, 3, D_max=64, hpsi_ws_bytes=1 << 30, renorm_ws_bytes=1 << 30,
+                          right_normal_from=5)
+    st = B.bsdmrg_stats(ctx)
+    assert all(v == 0.0 for v in st["seconds"].values()) and st["hpsi_calls"] == 0
+    assert set(st["seconds"]) == {"Tables", "Diag_H", "Ren_l", "Ren_r", "SVD", "StVec", "IO"}
+    # vacuum blocks exist and hold no operators; other blocks are not built
+    assert B.bsdmrg_family_count(ctx, B.LEFT, 0) == (0, 0)
+    with pytest.raises(B.BsdmrgError) as e:
+        B.bsdmrg_family_count(ctx, B.LEFT, 2)
+    assert e.value.code == B.ESTATE
+    with pytest.raises(B.BsdmrgError) as e:
+        B.bsdmrg_get_site_tensor(ctx, 1)
+    assert e.value.code == B.ESTATE
+    with pytest.raises(B.BsdmrgError) as e:
+        B.bsdmrg_get_site_tensor(ctx, 6)
+    assert e.value.code == B.EINVAL
+    with pytest.raises(B.BsdmrgError) as e:   # integrals not loaded
+        B.bsdmrg_renormalize(ctx, B.LEFT, 0)
+    assert e.value.code == B.ESTATE
+    h, eri = make_integrals(6)
+    B.bsdmrg_load_integrals(ctx, h, eri)
+    for side, bond in ((B.LEFT, 6), (B.RIGHT, 0), (3, 1)):
+        with pytest.raises(B.BsdmrgError) as e:
+            B.bsdmrg_renormalize(ctx, side, bond)
+        assert e.value.code == B.EINVAL
+    with pytest.raises(B.BsdmrgError) as e:   # site tensor missing
+        B.bsdmrg_renormalize(ctx, B.LEFT, 0)
+    assert e.value.code == B.ESTATE
+    with pytest.raises(B.BsdmrgError) as e:
+        B.bsdmrg_next_guess(ctx, 2, 2, 256, 256)
+    assert e.value.code == B.EINVAL
+    with pytest.raises(B.BsdmrgError) as e:   # environment blocks not built
+        B.bsdmrg_next_guess(ctx, 2, 0, 256, 256)
+    assert e.value.code == B.ESTATE
+    B.bsdmrg_destroy(ctx)

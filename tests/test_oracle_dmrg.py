@@ -150,3 +150,38 @@ def test_split_drops_values_below_floor():
     svd, keep, err = split(psi, _DL, _DR, 64)
     assert keep == {(1, 0): 1, (0, 1): 1}
     assert err < 1e-30
+
+
+@pytest.mark.parametrize("direction,D", [(1, 400), (-1, 400), (1, 6), (-1, 6)])
+def test_start_vector_carries_the_state(direction, D):
+    """The start vector of the next position represents the same Fock-space
+    state as the split wave function projected on the kept states: without
+    truncation P' nxt == P psi exactly; with truncation <P' nxt|P psi> equals
+    |nxt|^2 = |psi|^2 - discarded weight (nxt is the orthogonal projection)."""
+    from oracle.dense import DenseHeff
+    from synthetic.mps import random_two_site_psi
+    L, na, nb = 6, 3, 3
+    h, eri = make_integrals(L)
+    d = OracleDMRG(h, eri, na, nb, 400)
+    # move the center to position 2 (left to right from 0), then split there
+    guess = random_two_site_psi(d.dims[0], d.dims[2], 5)
+    for i in range(2):
+        _, guess = d.move(i, d._complete(guess, i), 400, +1)
+    i = 2
+    psi = random_two_site_psi(d.dims[i], d.dims[i + 2], 11)
+    norm2 = sum(float(np.sum(b * b)) for b in psi.values())
+    psi = {k: b / np.sqrt(norm2) for k, b in psi.items()}
+    before = DenseHeff(None, build_h_interleaved(h, eri, na, nb)[0], L, d.T, i, (na, nb)).expand(psi)
+    err, nxt = d.move(i, psi, D, direction)
+    j = i + 1 if direction > 0 else i - 1
+    dets = build_h_interleaved(h, eri, na, nb)[0]
+    after = DenseHeff(None, dets, L, d.T, j, (na, nb)).expand(d._complete(nxt, j))
+    n2 = sum(float(np.sum(b * b)) for b in nxt.values())
+    if D >= 400:
+        assert err < 1e-28
+        assert np.linalg.norm(after - before) < 1e-12
+    else:
+        assert err > 1e-6
+        assert abs(n2 - (1.0 - err)) < 1e-12
+        assert abs(float(after @ before) - n2) < 1e-12
+        assert np.linalg.norm(after) ** 2 == pytest.approx(n2, abs=1e-12)
