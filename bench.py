@@ -1,19 +1,28 @@
 """Benchmark of the two-site DMRG hot path on one MI355X.
 
-Workload (default): L=24 orbitals, N=24 electrons, S_z=0, bond dimension
-D=512, seeded synthetic integrals and a seeded random MPS in mixed-canonical
-form around the middle two-site position (sites 11, 12).  One step is one
-effective-Hamiltonian product H.psi in float64 on the grouped-GEMM path, with
-inputs resident in HBM.  Reported beside it: the serializer (pack of the left
-environment block into one contiguous stream, GB/s), its offload to pinned host
-memory on a side stream (GB/s), and the fraction of the offload hidden behind
-back-to-back H.psi products.
+Workload (default): L=76 orbitals, N=113 electrons, 2 S_z = 1 (57 alpha, 56
+beta), bond dimension D=4096, seeded synthetic integrals shaped like the
+paper's CAS(113,76) active space and a seeded random MPS in mixed-canonical
+form around the middle two-site position (sites 37, 38).  One step is one
+effective-Hamiltonian product H.psi (Sec. II.B step 2) with inputs resident in
+HBM, replayed from its captured graph; it is timed in float64 and in the two
+split-bfloat16 precisions.  The reported path is the fastest one whose product
+stays within 1e-6 relative 2-norm error of the float64 product and whose
+Davidson energy (split products, float64 finish) agrees with the float64
+Davidson run from the same start vector within 1e-6 Eh.
+
+Beside it: the serializer (pack of the left environment block, HBM GB/s), its
+offload to pinned host memory and the prefetch back (PCIe GB/s, fraction hidden
+behind products, timed with events on both streams), one middle-site step
+(Davidson, truncation, start vector, renormalization) and the CPU oracle timed
+on the host cores on a bounded sample of a smaller workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
@@ -25,6 +34,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFLOPS = 78.6
 BF16_MFMA_PEAK_TFLOPS = 2516.6
+NPROD = {0: 1, 1: 3, 2: 6}
+PNAME = {0: "fp64", 1: "bf16x3", 2: "bf16x6"}
 
 
 def log(msg):
@@ -37,36 +48,52 @@ def build_workload(L, na, nb, D, site):
     from synthetic.mps import random_mps, random_two_site_psi
     h, eri = make_integrals(L)
     dims, T = random_mps(L, na, nb, D, site)
-    ctx = B.bsdmrg_create(L, na, nb)
-    B.bsdmrg_load_integrals(ctx, h, eri)
     # right blocks beyond the product's right bond keep normal operators (the
     # smaller side); the block at site+2 switches to the complementary set
-    B.bsdmrg_set_right_normal(ctx, site + 3)
+    ctx = B.bsdmrg_create(L, na, nb, D_max=D, right_normal_from=site + 3)
+    B.bsdmrg_load_integrals(ctx, h, eri)
     for n, t in enumerate(T):
         if t is not None:
             B.bsdmrg_set_site_tensor(ctx, n, t)
     # grow each environment one bond at a time and free the block behind it,
     # so that only the blocks the middle-site step reads stay on the device
     t0 = time.time()
-    for b in range(1, site + 1):
-        B.bsdmrg_build_env(ctx, B.LEFT, b)
-        if b > 1:
-            B.bsdmrg_drop_block(ctx, B.LEFT, b - 1)
-    for b in range(L - 1, site + 1, -1):
-        B.bsdmrg_build_env(ctx, B.RIGHT, b)
-        if b < L - 1:
-            B.bsdmrg_drop_block(ctx, B.RIGHT, b + 1)
+    for b in range(0, site):
+        B.bsdmrg_renormalize(ctx, B.LEFT, b)
+        if b >= 1:
+            B.bsdmrg_drop_block(ctx, B.LEFT, b)
+        if b % 8 == 7:
+            log(f"bench: left block {b + 1} built ({time.time() - t0:.0f} s)")
+    for b in range(L, site + 2, -1):
+        B.bsdmrg_renormalize(ctx, B.RIGHT, b)
+        if b < L:
+            B.bsdmrg_drop_block(ctx, B.RIGHT, b)
+        if b % 8 == 0:
+            log(f"bench: right block {b - 1} built ({time.time() - t0:.0f} s)")
     t_env = time.time() - t0
     psi = random_two_site_psi(dims[site], dims[site + 2], 1)
-    return ctx, psi, dims, T, h, eri, t_env
+    return ctx, psi, dims, T, t_env
 
 
-def cpu_baseline(L, na, nb, D, site, useful_flops, budget_s=20.0):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(L, na, nb, D, site, budget_s=20.0, single_budget_s=8.0):
     """The CPU oracle (plain numpy float64 block-sparse product, as it stands)
-    timed on a bounded sample of the same middle-site workload: its environment
-    blocks and enlarged operators are built once (untimed), then full products
-    H.psi are applied back to back until the time budget is spent.  Throughput
-    uses the same useful-flop count per product as the GPU figure."""
+    timed on a bounded sample: its environment blocks and enlarged operators
+    are built once (untimed), then full products H.psi are applied back to back
+    until the time budget is spent, with every host core and then with one
+    BLAS thread.  The caller converts the rate with the useful-flop count of
+    the same product on the HIP path."""
+    from threadpoolctl import threadpool_limits
     from synthetic import make_integrals
     from synthetic.mps import random_mps, random_two_site_psi
     from oracle.siteops import spin_orbital_integrals
@@ -76,31 +103,32 @@ def cpu_baseline(L, na, nb, D, site, useful_flops, budget_s=20.0):
     t, g = spin_orbital_integrals(h, eri)
     dims, T = random_mps(L, na, nb, D, site)
     t0 = time.time()
-    log("bench: cpu baseline: oracle left environment")
+    log("bench: cpu baseline: oracle environments")
     lb = build_left_blocks(T, site, t, g)[site]
-    log(f"bench: cpu baseline: oracle right environment ({time.time() - t0:.0f} s so far)")
     rb = build_right_blocks(T, site + 2, t, g, (na, nb))[site + 2]
-    log(f"bench: cpu baseline: oracle enlarged operators ({time.time() - t0:.0f} s so far)")
     op = BlockSparseHeff(lb, rb, t, g, (na, nb))
     t_setup = time.time() - t0
     psi = random_two_site_psi(dims[site], dims[site + 2], 1)
-    n = 0
-    t0 = time.time()
-    while True:
-        op.apply(psi)
-        n += 1
-        log(f"bench: cpu baseline: {n} oracle products in {time.time() - t0:.1f} s")
-        if time.time() - t0 > budget_s:
-            break
-    dt = time.time() - t0
+
+    def run(budget):
+        n, t1 = 0, time.time()
+        while True:
+            op.apply(psi)
+            n += 1
+            if time.time() - t1 > budget:
+                break
+        return n, time.time() - t1
+
+    n, dt = run(budget_s)
+    log(f"bench: cpu baseline: {n} oracle products in {dt:.1f} s")
+    with threadpool_limits(limits=1):
+        n1, dt1 = run(single_budget_s)
+    log(f"bench: cpu baseline: {n1} single-thread oracle products in {dt1:.1f} s")
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
-    return {"value": useful_flops * n / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} full middle-site products H.psi of the oracle (numpy float64, L={L}, D={D}) in "
-                      f"{dt:.1f} s after an untimed {t_setup:.0f} s environment build; throughput counts the "
-                      "same useful flops per product as the GPU figure"}
+    return {"n": n, "dt": dt, "n1": n1, "dt1": dt1, "cores": cores, "setup_s": t_setup, "dims": dims}
 
 
 def measured_traffic(kernel_label, workload):
@@ -110,16 +138,16 @@ def measured_traffic(kernel_label, workload):
     changed since."""
     import glob
     import hashlib
-    for path in glob.glob(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "*_traffic.txt")):
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_traffic.txt")):
         kv = {}
         with open(path) as f:
             for line in f:
                 if "=" in line and not line.startswith("#"):
                     k, v = line.strip().split("=", 1)
                     kv[k] = v
-        if not kernel_label.startswith(kv.get("kernel", "\0")) or kv.get("workload") != workload:
+        if kv.get("kernel") != kernel_label or kv.get("workload") != workload:
             continue
-        src = os.path.join(os.path.dirname(os.path.abspath(__file__)), kv["source"])
+        src = os.path.join(ROOT, kv["source"])
         with open(src, "rb") as f:
             if hashlib.sha256(f.read()).hexdigest()[:16] != kv["source_sha256_16"]:
                 return None
@@ -127,20 +155,43 @@ def measured_traffic(kernel_label, workload):
     return None
 
 
+def kernel_names(prec):
+    shapes = {0: "<2, 2>", 1: "<1, 1>", 2: "<1, 2>", 3: "<2, 1>", 4: "<16>", 5: "<32>"}
+    names = {0: "zero_fill_kernel", 1: "split_planes_kernel"}
+    for ph in (1, 2):
+        for c, sh in shapes.items():
+            if c >= 4 and prec:
+                names[10 * ph + c] = f"wave_planes_kernel{sh[:-1]}, {3 * prec}, {2 - ph}>"
+            elif c >= 4:
+                names[10 * ph + c] = f"wave_gemm_kernel{sh}"
+            else:
+                names[10 * ph + c] = f"grouped_gemm_kernel{sh}"
+        names[10 * ph + 6] = "split_reduce_kernel"
+    return names
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--L", type=int, default=24)
-    ap.add_argument("--N", type=int, default=24)
-    ap.add_argument("--D", type=int, default=512)
+    ap.add_argument("--L", type=int, default=76)
+    ap.add_argument("--N", type=int, default=113)
+    ap.add_argument("--D", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--cpu-L", type=int, default=24, help="CPU oracle workload: orbitals")
+    ap.add_argument("--cpu-N", type=int, default=24)
+    ap.add_argument("--cpu-D", type=int, default=512)
     ap.add_argument("--ws-mb", type=int, default=0, help="H.psi workspace budget in MiB (0: library default)")
-    ap.add_argument("--precision", type=int, default=0, help="0 fp64, 1 split-bf16 x3, 2 split-bf16 x6")
-    ap.add_argument("--no-autotune", action="store_true", help="time the default schedules")
-    ap.add_argument("--dav-iters", type=int, default=40, help="Davidson iteration cap of the site step")
+    ap.add_argument("--autotune", action="store_true", help="autotune the schedules (long at large D)")
+    ap.add_argument("--dav-iters", type=int, default=8, help="Davidson iteration cap of the site step")
+    ap.add_argument("--profile-reps", type=int, default=2)
+    ap.add_argument("--only", type=int, default=-1, help="time only this precision (profiling runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device to device three times (calibrates the HBM byte counters)")
+    ap.add_argument("--quick", action="store_true",
+                    help="products only: no Davidson, serializer, site step or CPU baseline (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design "
@@ -148,178 +199,271 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel() * 8, "copies": 3}))
+        return
     from paper_2412_04676_amd import bsdmrg as B
 
     L, N, D = args.L, args.N, args.D
     na, nb = (N + 1) // 2, N // 2
     site = L // 2 - 1
+    wl = f"L={L} N={N} 2S_z={na - nb} D={D}"
     torch.cuda.set_device(0)
-    log(f"bench: building workload L={L} N={N} D={D} site={site}")
-    ctx, psi, dims, T, h, eri, t_env = build_workload(L, na, nb, D, site)
+    log(f"bench: building workload {wl} site={site}")
+    ctx, psi, dims, T, t_env = build_workload(L, na, nb, D, site)
     log(f"bench: environments built in {t_env:.1f} s")
     stream = torch.cuda.current_stream()
+    t0 = time.time()
     B.bsdmrg_hpsi_prepare(ctx, site, B.FP64, args.ws_mb << 20, stream)
+    t_prep = time.time() - t0
     info = B.bsdmrg_hpsi_info(ctx, site)
     lay = B.bsdmrg_psi_layout(ctx, site)
     x = torch.from_numpy(B.psi_to_flat(psi, lay)).cuda()
+    x /= torch.linalg.norm(x)
     y = torch.empty_like(x)
+    F = info["flops"]
     log(f"bench: psi {lay[2]} elements, {info['channels']} channels, {info['segments']} K-segments, "
-        f"{info['flops']:.3e} flop per product")
+        f"{F:.3e} flop per product, prepared in {t_prep:.1f} s")
 
-    shapes = {0: "<2, 2>", 1: "<1, 1>", 2: "<1, 2>", 3: "<2, 1>", 4: "<16>", 5: "<32>"}
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
 
-    tuned = {}
-
-    def time_precision(prec):
-        # schedule chosen by the library's autotuner (untimed setup)
-        if args.no_autotune:
-            tuned[prec] = None
-        else:
+    precs = [B.FP64, B.BF16X3, B.BF16X6] if args.only < 0 else [args.only]
+    res = {}
+    for prec in precs:
+        tuned = None
+        if args.autotune:
             best, dflt, ncand = B.bsdmrg_hpsi_autotune(ctx, site, prec, stream)
-            tuned[prec] = {"candidates": ncand, "default_ms": dflt, "tuned_ms": best}
-            log(f"bench: precision {prec}: autotune {ncand} schedules, default {dflt:.3f} ms -> {best:.3f} ms")
+            tuned = {"candidates": ncand, "default_ms": dflt, "tuned_ms": best}
         for _ in range(args.warmup):
             B.bsdmrg_hpsi(ctx, site, x, y, prec, stream)
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0, e1 = ev(), ev()
         e0.record(stream)
         for _ in range(args.steps):
             B.bsdmrg_hpsi(ctx, site, x, y, prec, stream)
         e1.record(stream)
         torch.cuda.synchronize()
-        ms_ = e0.elapsed_time(e1) / args.steps
-        out_ = y.clone()
-        # dominant kernel: per-launch HIP events on the library's stream
+        ms = e0.elapsed_time(e1) / args.steps
+        out = y.clone()
+        # per-launch durations: HIP events between consecutive launches on the
+        # library's stream (the same kernels the graph replays)
         kinds = {}
-        for _ in range(5):
-            for k, t, f, nb in B.bsdmrg_hpsi_profile(ctx, site, x, y, prec, stream):
+        for _ in range(args.profile_reps):
+            for k, t, f, nbytes in B.bsdmrg_hpsi_profile(ctx, site, x, y, prec, stream, cap=4096):
                 a = kinds.setdefault(k, [0.0, 0.0, 0, 0.0])
                 a[0] += t
                 a[1] += f
                 a[2] += 1
-                a[3] += nb
-        names = {0: "zero_fill_kernel", 1: "split_planes_kernel psi"}
-        for ph in (1, 2):
-            for c, sh in shapes.items():
-                if c >= 4 and prec:
-                    names[10 * ph + c] = f"wave_planes_kernel{sh[:-1]}, {3 * prec}, {2 - ph}> phase {ph}"
-                elif c >= 4:
-                    names[10 * ph + c] = f"wave_gemm_kernel{sh} phase {ph}"
-                else:
-                    names[10 * ph + c] = f"grouped_gemm_kernel{sh} phase {ph}"
-        names[16], names[26] = "split_reduce_kernel phase 1", "split_reduce_kernel phase 2"
-        dom = max(kinds, key=lambda k: kinds[k][0])
-        per = {names[k]: v[0] / v[2] for k, v in sorted(kinds.items())}
-        log(f"bench: precision {prec}: H.psi {ms_:.3f} ms, {info['flops'] / (ms_ * 1e-3) / 1e12:.2f} TFLOP/s; "
-            + ", ".join(f"{n}: {t:.3f} ms" for n, t in per.items()))
-        n_dom = kinds[dom][2]
-        return (ms_, out_, names[dom], kinds[dom][0] / n_dom, kinds[dom][1] / n_dom, per, kinds[dom][3] / n_dom)
+                a[3] += nbytes
+        names = kernel_names(prec)
+        total = {names[k] + (" phase 1" if 10 <= k < 20 else " phase 2" if k >= 20 else ""): v
+                 for k, v in kinds.items()}
+        dom = max(total, key=lambda n: total[n][0])
+        d = total[dom]
+        res[prec] = {"ms": ms, "out": out, "tuned": tuned, "dominant": dom,
+                     "dom_ms": d[0] / d[2], "dom_flops": d[1] / d[2], "dom_bytes_incl_intermediates": d[3] / d[2],
+                     "dom_launches_per_product": d[2] / args.profile_reps,
+                     "dom_share": d[0] / sum(v[0] for v in total.values()),
+                     "per_kernel_ms_per_product": {n: v[0] / args.profile_reps for n, v in sorted(total.items())}}
+        log(f"bench: {PNAME[prec]}: H.psi {ms:.3f} ms, {F / (ms * 1e-3) / 1e12:.2f} TFLOP/s; dominant {dom} "
+            f"{d[0] / d[2]:.3f} ms x {d[2] / args.profile_reps:.0f} launches")
+    ref = res[B.FP64]["out"] if B.FP64 in res else res[precs[0]]["out"]
+    xn2 = float(torch.dot(x, x))
+    for p in res:
+        dy = res[p]["out"] - ref
+        res[p]["rel_err"] = float(torch.linalg.norm(dy) / torch.linalg.norm(ref))
+        res[p]["d_rayleigh_Eh"] = abs(float(torch.dot(x, dy))) / xn2
 
-    res = {p: time_precision(p) for p in (B.FP64, B.BF16X3, B.BF16X6)}
-    ref = res[B.FP64][1]
-    errs = {p: float(torch.linalg.norm(res[p][1] - ref) / torch.linalg.norm(ref)) for p in res}
-    # energy-scale error of each path on this vector, in hartree: |(H'-H)x|/|x|
-    # bounds the Rayleigh-quotient change, x.(H'-H)x/|x|^2 is that change itself
-    xn = float(torch.linalg.norm(x))
-    de_bound = {p: float(torch.linalg.norm(res[p][1] - ref)) / xn for p in res}
-    de_rq = {p: abs(float(torch.dot(x, res[p][1] - ref))) / xn ** 2 for p in res}
-    log(f"bench: relative error vs fp64: x3 {errs[B.BF16X3]:.2e}, x6 {errs[B.BF16X6]:.2e}; "
-        f"dE(Rayleigh) x3 {de_rq[B.BF16X3]:.2e} Eh, x6 {de_rq[B.BF16X6]:.2e} Eh")
-    # the reported path: the fastest one within 1e-6 relative 2-norm error of the
-    # float64 product whose energy (Rayleigh quotient) moves by at most 1e-6 Eh
-    ok = [p for p in res if errs[p] <= 1e-6 and de_rq[p] <= 1e-6]
-    chosen = min(ok, key=lambda p: res[p][0])
-    ms, _, dname, t_dom, f_dom, per_launch, b_dom = res[chosen]
-    tflops = info["flops"] / (ms * 1e-3) / 1e12
-    # algorithmic flops of the dominant kernel: the split-bf16 products issue 3 or
-    # 6 bf16 MFMA products per float64 multiply-add
-    mult = {B.FP64: 1.0, B.BF16X3: 3.0, B.BF16X6: 6.0}[chosen]
-    peak_f = FP64_MFMA_PEAK_TFLOPS if chosen == B.FP64 else BF16_MFMA_PEAK_TFLOPS
-    ach_f = mult * f_dom / (t_dom * 1e-3) / 1e12
-    ach_b = b_dom / (t_dom * 1e-3) / 1e9
-    # the roof that bounds the kernel at its algorithmic intensity
-    intensity = mult * f_dom / b_dom
-    ridge = peak_f * 1e12 / (HBM_PEAK_GBS * 1e9)
-    traffic = measured_traffic(dname, f"L={L} N={N} D={D}")
-    if intensity < ridge:
-        roof = {"bound": "hbm", "achieved": ach_b, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach_b / HBM_PEAK_GBS}
-    else:
-        roof = {"bound": "mfma", "achieved": ach_f, "peak": peak_f, "unit": "TFLOP/s", "frac": ach_f / peak_f}
-    roof.update({"traffic": traffic, "kernel": dname, "kernel_ms": t_dom, "kernel_useful_flops": f_dom,
-                 "algorithmic_flops_per_useful_flop": mult, "algorithmic_bytes": b_dom,
-                 "intensity_flop_per_byte": intensity, "ridge_flop_per_byte": ridge,
-                 "mfma_tflops": ach_f, "mfma_peak": peak_f, "mfma_frac": ach_f / peak_f,
-                 "hbm_GBps": ach_b, "hbm_frac": ach_b / HBM_PEAK_GBS,
-                 "traffic_GBps": traffic / (t_dom * 1e-3) / 1e9 if traffic else None})
+    # energy of each precision's Davidson (split products down to their noise
+    # level, then float64 products: the energy is a float64 Rayleigh quotient)
+    # against the float64 Davidson from the same start vector, same cap
+    dav = {}
+    if args.only < 0 and not args.quick:
+        for p in (B.FP64, B.BF16X6, B.BF16X3):
+            xs = x.clone()
+            torch.cuda.synchronize()
+            t0 = time.time()
+            e, it, r, ritz = B.bsdmrg_davidson(ctx, site, xs, max_iter=args.dav_iters, tol=1e-8, precond=1,
+                                               precision=p, stream=stream)
+            torch.cuda.synchronize()
+            dav[p] = {"energy": e, "iters": it, "residual": r, "s": time.time() - t0}
+            if p == B.FP64:
+                x_dav = xs
+            log(f"bench: Davidson {PNAME[p]}: E {e:.10f} |r| {r:.2e} {it} it {time.time() - t0:.1f} s")
+        for p in dav:
+            dav[p]["dE_vs_fp64_Eh"] = dav[p]["energy"] - dav[B.FP64]["energy"]
 
-    # serializer and offload of the left environment block
+    # the reported path: fastest within the product bar and the energy bar
+    def ok(p):
+        if p == B.FP64:
+            return True
+        return res[p]["rel_err"] <= 1e-6 and p in dav and abs(dav[p]["dE_vs_fp64_Eh"]) <= 1e-6
+    chosen = min((p for p in res if ok(p)), key=lambda p: res[p]["ms"])
+    r = res[chosen]
+    ms = r["ms"]
+    tflops = F / (ms * 1e-3) / 1e12
+
+    # roofline of the dominant kernel: algorithmic bytes of a product are the
+    # distinct operator blocks read once plus psi and the output; at that
+    # intensity the product sits far above the ridge, so the MFMA roof of the
+    # kernel's operand type bounds it
+    esize = {0: 8.0, 1: 4.0, 2: 6.0}[chosen]
+    prod_bytes = info["op_elems"] * esize + 2 * 8.0 * lay[2]
+    peak = FP64_MFMA_PEAK_TFLOPS if chosen == B.FP64 else BF16_MFMA_PEAK_TFLOPS
+    ach = r["dom_flops"] / (r["dom_ms"] * 1e-3) / 1e12
+    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
+    traffic = measured_traffic(r["dominant"], wl)
+    roof = {"bound": "mfma", "achieved": ach, "peak": peak, "unit": "TFLOP/s", "frac": ach / peak,
+            "traffic": traffic,
+            "kernel": r["dominant"], "kernel_ms": r["dom_ms"], "kernel_useful_flops": r["dom_flops"],
+            "launches_per_product": r["dom_launches_per_product"], "share_of_product": r["dom_share"],
+            "mfma_products_per_useful_flop": NPROD[chosen],
+            "split_effective_peak": peak / NPROD[chosen], "split_effective_frac": ach / (peak / NPROD[chosen]),
+            "product_algorithmic_bytes": prod_bytes, "product_intensity_flop_per_byte": F / prod_bytes,
+            "ridge_flop_per_byte": ridge,
+            "kernel_bytes_incl_intermediates": r["dom_bytes_incl_intermediates"],
+            "traffic_over_algorithmic": (traffic / r["dom_bytes_incl_intermediates"]) if traffic else None}
+
+    if args.quick:
+        print(json.dumps({"workload": wl, "flops_per_product": F, "roofline": roof,
+                          "precisions": {PNAME[p]: {"ms": res[p]["ms"], "dominant_kernel": res[p]["dominant"],
+                                                    "dominant_ms": res[p]["dom_ms"],
+                                                    "per_kernel_ms_per_product": res[p]["per_kernel_ms_per_product"]}
+                                         for p in res}}))
+        B.bsdmrg_destroy(ctx)
+        return
+
+    # serializer: pack of the left block, offload (pack + D2H) and prefetch
+    # (H2D + unpack), alone and with products in flight, events on both streams
+    side = torch.cuda.Stream()
     nbytes = B.bsdmrg_serialized_size(ctx, B.LEFT, site)
     staging = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device="cuda")
     pinned = torch.empty(nbytes // 8 + 64, dtype=torch.float64, pin_memory=True)
-    side = torch.cuda.Stream()
     B.bsdmrg_pack(ctx, B.LEFT, site, staging, staging.numel() * 8, stream)
-    torch.cuda.synchronize()
-    reps = 5
-    t0 = time.time()
-    for _ in range(reps):
+    e0, e1 = ev(), ev()
+    e0.record(stream)
+    for _ in range(5):
         B.bsdmrg_pack(ctx, B.LEFT, site, staging, staging.numel() * 8, stream)
+    e1.record(stream)
     torch.cuda.synchronize()
-    t_pack = (time.time() - t0) / reps
-    pack_gbs = 2 * nbytes / t_pack / 1e9
-    # offload alone
-    t0 = time.time()
-    B.bsdmrg_offload(ctx, B.LEFT, site, staging, pinned, nbytes, 0, stream, side)
-    B.bsdmrg_offload_wait(ctx, B.LEFT, site)
-    torch.cuda.synchronize()
-    t_io = time.time() - t0
-    t0 = time.time()
-    side.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    with torch.cuda.stream(side):
-        ev0.record(side)
-        pinned.copy_(staging, non_blocking=True)
-        ev1.record(side)
-    torch.cuda.synchronize()
-    d2h_gbs = nbytes / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
-    # compute alone and compute with the offload in flight
-    nrep = max(4, int(np.ceil(t_io / (ms * 1e-3))) + 2)
-    torch.cuda.synchronize()
-    t0 = time.time()
-    for _ in range(nrep):
-        B.bsdmrg_hpsi(ctx, site, x, y, chosen, stream)
-    torch.cuda.synchronize()
-    t_comp = time.time() - t0
-    t0 = time.time()
-    B.bsdmrg_offload(ctx, B.LEFT, site, staging, pinned, nbytes, 0, stream, side)
-    for _ in range(nrep):
-        B.bsdmrg_hpsi(ctx, site, x, y, chosen, stream)
-    B.bsdmrg_offload_wait(ctx, B.LEFT, site)
-    torch.cuda.synchronize()
-    t_both = time.time() - t0
-    hidden = 1.0 - max(0.0, t_both - t_comp) / t_io
-    hidden = min(1.0, max(0.0, hidden))
-    log(f"bench: pack {nbytes / 1e6:.1f} MB in {t_pack * 1e3:.2f} ms ({pack_gbs:.0f} GB/s HBM), "
-        f"D2H {d2h_gbs:.1f} GB/s, offload alone {t_io * 1e3:.1f} ms, hidden {hidden * 100:.1f}%")
+    t_pack = e0.elapsed_time(e1) / 5 * 1e-3
 
-    # one full middle-site step: Davidson (H.psi products + float64 vector work),
-    # truncation to D, renormalization of the enlarged left block
+    def offload_alone():
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record(stream)
+        B.bsdmrg_offload(ctx, B.LEFT, site, staging, pinned, nbytes, 0, stream, side)
+        b.record(side)
+        B.bsdmrg_offload_wait(ctx, B.LEFT, site)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e-3
+
+    def prefetch_alone():
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record(stream)
+        B.bsdmrg_prefetch(ctx, B.LEFT, site, pinned, staging, nbytes, stream, side)
+        b.record(stream)
+        B.bsdmrg_prefetch_wait(ctx, B.LEFT, site)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e-3
+
+    def products(n):
+        torch.cuda.synchronize()
+        a, b = ev(), ev()
+        a.record(stream)
+        for _ in range(n):
+            B.bsdmrg_hpsi(ctx, site, x, y, chosen, stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e-3
+
+    def with_io(kind, n):
+        torch.cuda.synchronize()
+        a, bc, bs = ev(), ev(), ev()
+        a.record(stream)
+        if kind == "offload":
+            B.bsdmrg_offload(ctx, B.LEFT, site, staging, pinned, nbytes, 0, stream, side)
+            for _ in range(n):
+                B.bsdmrg_hpsi(ctx, site, x, y, chosen, stream)
+            bs.record(side)
+        else:
+            for _ in range(n):
+                B.bsdmrg_hpsi(ctx, site, x, y, chosen, stream)
+            B.bsdmrg_prefetch(ctx, B.LEFT, site, pinned, staging, nbytes, stream, side)
+            bs.record(side)
+        bc.record(stream)
+        torch.cuda.synchronize()
+        if kind == "offload":
+            B.bsdmrg_offload_wait(ctx, B.LEFT, site)
+        else:
+            B.bsdmrg_prefetch_wait(ctx, B.LEFT, site)
+        return max(a.elapsed_time(bc), a.elapsed_time(bs)) * 1e-3
+
+    io = {}
+    for kind, alone in (("offload", offload_alone), ("prefetch", prefetch_alone)):
+        t_io = statistics.median(alone() for _ in range(3))
+        n = max(2, int(np.ceil(t_io / (ms * 1e-3))) + 1)
+        hid = []
+        for _ in range(3):
+            tc = products(n)
+            tb = with_io(kind, n)
+            hid.append(1.0 - max(0.0, tb - tc) / t_io)
+        io[kind] = {"alone_ms": t_io * 1e3, "products_overlapped": n, "hidden_frac": statistics.median(hid),
+                    "hidden_frac_reps": hid, "GBps": nbytes / t_io / 1e9}
+        log(f"bench: {kind} alone {t_io * 1e3:.1f} ms ({nbytes / t_io / 1e9:.1f} GB/s incl. pack/unpack), "
+            f"hidden {statistics.median(hid) * 100:.1f}% (reps {', '.join(f'{h * 100:.1f}' for h in hid)})")
+    # release and prefetch: the block's memory is returned and restored, the
+    # product plan is replayed as it was
+    yref = torch.empty_like(x)
+    B.bsdmrg_hpsi(ctx, site, x, yref, chosen, stream)
+    B.bsdmrg_offload(ctx, B.LEFT, site, staging, pinned, nbytes, 1, stream, side)
+    B.bsdmrg_offload_wait(ctx, B.LEFT, site)
+    released = B.bsdmrg_block_bytes(ctx, B.LEFT, site) == 0
+    tables0 = B.bsdmrg_stats(ctx)["seconds"]["Tables"]
+    B.bsdmrg_prefetch(ctx, B.LEFT, site, pinned, staging, nbytes, stream, side)
+    B.bsdmrg_hpsi(ctx, site, x, y, chosen, stream)
     torch.cuda.synchronize()
-    xs = x.clone()
-    t0 = time.time()
-    e_dav, it_dav, r_dav, _ = B.bsdmrg_davidson(ctx, site, xs, max_iter=args.dav_iters, tol=1e-8, precond=1,
-                                                precision=chosen, stream=stream)
+    roundtrip = {"released": released, "bit_identical": bool(torch.equal(y, yref)),
+                 "plan_rebuilt": B.bsdmrg_stats(ctx)["seconds"]["Tables"] != tables0}
+    # D2H and H2D copy rates alone (side stream events)
+    a, b = ev(), ev()
+    with torch.cuda.stream(side):
+        a.record(side)
+        pinned.copy_(staging, non_blocking=True)
+        b.record(side)
     torch.cuda.synchronize()
-    t_dav = time.time() - t0
-    t0 = time.time()
-    err_tr, kept, _ = B.bsdmrg_truncate(ctx, site, xs, D, 0, stream)
+    d2h = nbytes / (a.elapsed_time(b) * 1e-3) / 1e9
+    with torch.cuda.stream(side):
+        a.record(side)
+        staging.copy_(pinned, non_blocking=True)
+        b.record(side)
     torch.cuda.synchronize()
-    t_tr = time.time() - t0
-    t0 = time.time()
-    B.bsdmrg_build_env(ctx, B.LEFT, site + 1, stream)
-    torch.cuda.synchronize()
-    t_ren = time.time() - t0
-    log(f"bench: site step: Davidson {it_dav} it {t_dav * 1e3:.1f} ms (E {e_dav:.8f}, |r| {r_dav:.1e}), "
-        f"truncation {t_tr * 1e3:.1f} ms (kept {kept}, err {err_tr:.2e}), renormalization {t_ren * 1e3:.1f} ms")
+    h2d = nbytes / (a.elapsed_time(b) * 1e-3) / 1e9
+    del staging, pinned
+    torch.cuda.empty_cache()
+
+    # one middle-site step after the float64 Davidson: truncation to D, start
+    # vector of the next position, renormalization of the enlarged left block
+    site_step = {}
+    if args.only < 0:
+        torch.cuda.synchronize()
+        t0 = time.time()
+        err_tr, kept, _ = B.bsdmrg_truncate(ctx, site, x_dav, D, 0, stream)
+        t_tr = time.time() - t0
+        t0 = time.time()
+        B.bsdmrg_renormalize(ctx, B.LEFT, site, stream)
+        t_ren = time.time() - t0
+        site_step = {"davidson_fp64_s": dav[B.FP64]["s"], "davidson_iters": dav[B.FP64]["iters"],
+                     "truncate_s": t_tr, "kept": kept, "trunc_err": err_tr, "renormalize_s": t_ren}
+        log(f"bench: truncation {t_tr:.2f} s (kept {kept}, err {err_tr:.2e}), renormalization {t_ren:.2f} s")
+    stats = B.bsdmrg_stats(ctx)
 
     out = {
         "metric": "H·ψ TFLOP/s split-BF16 vs FP64 at ΔE≤1e-6 Eh; serializer+offload GB/s, % hidden",
@@ -332,34 +476,65 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if chosen == B.FP64 else "bf16",   # MFMA operand type; config.precision_path names the scheme
+        "dtype": "f64" if chosen == B.FP64 else "bf16",
         "data": "synthetic",
-        "config": {"workload": f"middle-site two-site H.psi, L={L} N={N} S_z={(na - nb) / 2} D={D} "
-                               "(synthetic integrals, random mixed-canonical MPS)",
+        "config": {"workload": f"middle-site two-site H.psi, {wl} (synthetic integrals shaped like "
+                               "CAS(113,76), random mixed-canonical MPS)",
                    "site": site, "psi_elements": int(lay[2]), "channels": info["channels"],
-                   "k_segments": info["segments"], "flops_per_step": info["flops"],
-                   "precision_path": {0: "fp64", 1: "bf16x3", 2: "bf16x6"}[chosen], "env_build_s": t_env},
-        "precisions": {name: {"ms": res[p][0], "tflops": info["flops"] / (res[p][0] * 1e-3) / 1e12,
-                              "rel_err_vs_fp64": errs[p], "dHx_over_x_Eh": de_bound[p],
-                              "d_rayleigh_Eh": de_rq[p], "per_launch_ms": res[p][5]}
-                       for name, p in (("fp64", B.FP64), ("bf16x3", B.BF16X3), ("bf16x6", B.BF16X6))},
-        "speedup_bf16x6_vs_fp64": res[B.FP64][0] / res[B.BF16X6][0],
-        "autotune": {name: tuned[p] for name, p in (("fp64", B.FP64), ("bf16x3", B.BF16X3), ("bf16x6", B.BF16X6))},
+                   "k_segments": info["segments"], "flops_per_step": F,
+                   "precision_path": PNAME[chosen],
+                   "path_rule": "fastest precision with relative 2-norm error <= 1e-6 against the float64 "
+                                "product and |E - E_fp64| <= 1e-6 Eh for its Davidson (split products to "
+                                "their noise level, float64 finish) from the float64 run's start vector",
+                   "env_build_s": t_env, "prepare_s": t_prep},
+        "precisions": {PNAME[p]: {"ms": res[p]["ms"], "tflops": F / (res[p]["ms"] * 1e-3) / 1e12,
+                                  "speedup_vs_fp64": (res[B.FP64]["ms"] / res[p]["ms"]) if B.FP64 in res else None,
+                                  "rel_err_vs_fp64": res[p]["rel_err"], "d_rayleigh_Eh": res[p]["d_rayleigh_Eh"],
+                                  "dominant_kernel": res[p]["dominant"], "dominant_ms": res[p]["dom_ms"],
+                                  "dominant_mfma_frac": (res[p]["dom_flops"] / (res[p]["dom_ms"] * 1e-3) / 1e12 /
+                                                         (FP64_MFMA_PEAK_TFLOPS if p == 0 else BF16_MFMA_PEAK_TFLOPS)),
+                                  "davidson": dav.get(p), "autotune": res[p]["tuned"],
+                                  "per_kernel_ms_per_product": res[p]["per_kernel_ms_per_product"]}
+                       for p in res},
         "roofline": roof,
-        "site_step": {"davidson_precision": {0: "fp64", 1: "bf16x3", 2: "bf16x6"}[chosen],
-                      "davidson_iters": it_dav, "davidson_ms": t_dav * 1e3, "energy": e_dav,
-                      "residual": r_dav, "truncate_ms": t_tr * 1e3, "kept": kept, "trunc_err": err_tr,
-                      "renormalize_ms": t_ren * 1e3},
-        "serializer": {"bytes": nbytes, "pack_ms": t_pack * 1e3, "pack_hbm_GBps": pack_gbs,
-                       "d2h_GBps": d2h_gbs, "offload_ms": t_io * 1e3, "hidden_frac": hidden},
+        "site_step": site_step,
+        "serializer": {"bytes": nbytes, "pack_ms": t_pack * 1e3, "pack_hbm_GBps": 2 * nbytes / t_pack / 1e9,
+                       "d2h_GBps": d2h, "h2d_GBps": h2d, "offload": io["offload"], "prefetch": io["prefetch"],
+                       "release_prefetch_roundtrip": roundtrip},
+        "phase_seconds": stats["seconds"],
     }
+    B.bsdmrg_destroy(ctx)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a bounded sample")
         try:
-            out["cpu_baseline"] = cpu_baseline(L, na, nb, D, site, info["flops"], args.cpu_budget)
+            cL, cN, cD = args.cpu_L, args.cpu_N, args.cpu_D
+            cna, cnb = (cN + 1) // 2, cN // 2
+            csite = cL // 2 - 1
+            cb = cpu_baseline(cL, cna, cnb, cD, csite, args.cpu_budget)
+            # useful flops of the same product on the HIP path's count
+            cctx = B.bsdmrg_create(cL, cna, cnb)
+            from synthetic import make_integrals
+            from synthetic.mps import random_mps
+            ch, ce = make_integrals(cL)
+            B.bsdmrg_load_integrals(cctx, ch, ce)
+            for n_, t_ in enumerate(random_mps(cL, cna, cnb, cD, csite)[1]):
+                if t_ is not None:
+                    B.bsdmrg_set_site_tensor(cctx, n_, t_)
+            B.bsdmrg_build_env(cctx, B.LEFT, csite)
+            B.bsdmrg_build_env(cctx, B.RIGHT, csite + 2)
+            B.bsdmrg_hpsi_prepare(cctx, csite)
+            cF = B.bsdmrg_hpsi_info(cctx, csite)["flops"]
+            B.bsdmrg_destroy(cctx)
+            out["cpu_baseline"] = {
+                "value": cF * cb["n"] / cb["dt"] / 1e12, "unit": "TFLOP/s", "cores": cb["cores"], "kind": "oracle",
+                "sample": f"{cb['n']} full middle-site products H.psi of the oracle (numpy float64) on the smaller "
+                          f"workload L={cL} N={cN} S_z={(cna - cnb) / 2} D={cD} in {cb['dt']:.1f} s, after an "
+                          f"untimed {cb['setup_s']:.0f} s environment build; the oracle cannot build the "
+                          f"{wl} environments; flops counted as on the GPU path",
+                "single_thread_value": cF * cb["n1"] / cb["dt1"] / 1e12,
+                "cpu_model": cpu_model(), "workload": f"L={cL} N={cN} D={cD}"}
         except Exception as e:  # report, never hide
             out["cpu_baseline"] = {"error": repr(e)}
-    B.bsdmrg_destroy(ctx)
     print(json.dumps(out))
 
 

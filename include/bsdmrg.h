@@ -72,9 +72,9 @@ typedef struct {
   int32_t D_max;              /* largest bond dimension the caller will keep (advisory, >= 0) */
   size_t hpsi_ws_bytes;       /* per-chunk intermediate workspace of H.psi (default 16 GiB) */
   size_t renorm_ws_bytes;     /* workspace of one renormalization batch (default 8 GiB) */
-  size_t hbm_budget_bytes;    /* device bytes the two environment blocks of a product may keep
-                                 resident; larger products stream their right-block operator
-                                 families from pinned host memory (bsdmrg_hpsi_stream_*).
+  size_t hbm_budget_bytes;    /* device bytes the two environment blocks of a product may
+                                 occupy; a product prepared above it streams its right-block
+                                 operators from pinned host memory (bsdmrg_set_hbm_budget).
                                  0: no limit */
   int32_t right_normal_from;  /* as bsdmrg_set_right_normal; 0: no normal right blocks */
   int32_t flags;              /* reserved, must be 0 */
@@ -201,6 +201,24 @@ int bsdmrg_hpsi_autotune(bsdmrg_ctx* ctx, int site, int precision, bsdmrg_stream
 int bsdmrg_hpsi_schedule(bsdmrg_ctx* ctx, int site, int precision, double target_waves, int xcd_order,
                          int wave_max);
 
+/* Device budget of the environment (Sec. III.A strategy 2; the
+ * CAS(113,76) runs of Sec. IV hold more operator data than the accelerators'
+ * memory).  Products prepared from now on whose left and right blocks together
+ * exceed `bytes` are built in streamed form: the right block's operator blocks
+ * are gathered once, chunk by chunk in the order the product reads them, into
+ * pinned host memory owned by the plan; every product then copies chunk k into
+ * device slot k % 2 on a side stream while chunk k - 1 computes (event
+ * ordered, the compute stream waits only for a copy that is not done), and
+ * reads them there.  Results are bit-identical to the resident product.  After
+ * preparing, the caller may release the right block (bsdmrg_offload with
+ * release); the streamed product does not read it.  0 disables streaming.
+ * chunk_bytes bounds the right operators of one chunk (0: 1 GiB); two slots
+ * of that size hold the chunks on the device. */
+int bsdmrg_set_hbm_budget(bsdmrg_ctx* ctx, size_t bytes, size_t chunk_bytes);
+/* Whether the prepared product at `site` streams its right operators, the
+ * pinned host bytes it copies per product, and its chunk count (optional). */
+int bsdmrg_hpsi_streamed(bsdmrg_ctx* ctx, int site, int* streamed, size_t* host_bytes, int* n_chunks);
+
 /* out = H_eff psi (Sec. II.B step 2) at two-site position `site`; psi and out
  * are device buffers in the layout of bsdmrg_psi_layout and must not overlap.
  * The product (output zero-fill and every grouped launch) is captured once
@@ -229,10 +247,13 @@ typedef struct {
  * the final residual norm; ritz (host, optional, cap entries) the lowest Ritz
  * value after every iteration.  opts == NULL uses the defaults.  With a split
  * precision the products run split until the residual reaches the product's
- * noise level (4e-8 |theta| for BF16X6, 2e-5 |theta| for BF16X3), then the run
- * restarts from that Ritz vector with float64 products down to tol (at least
- * one float64 product): the energy and the residual returned are float64
- * quantities, and iters counts both stages.  Synchronizes `stream` once per
+ * noise level (2e-7 |theta| for BF16X6, 2e-5 |theta| for BF16X3), then the run
+ * restarts from that Ritz vector with float64 products down to tol for the
+ * iterations left; if the split stage used every iteration, one float64
+ * product on its Ritz vector gives the energy (the Rayleigh quotient) and the
+ * residual.  Either way the energy and the residual returned are float64
+ * quantities; iters counts the iterations of both stages (max_iter at most)
+ * and the final float64 evaluation counts as none.  Synchronizes `stream` once per
  * iteration (a 16-byte read of theta and |r|). */
 int bsdmrg_davidson(bsdmrg_ctx* ctx, int site, double* psi_dev, const bsdmrg_dav_opts* opts, double* energy,
                     int* iters, double* resid, double* ritz, int cap, bsdmrg_stream_t stream);
@@ -240,7 +261,8 @@ int bsdmrg_davidson(bsdmrg_ctx* ctx, int site, double* psi_dev, const bsdmrg_dav
 /* Truncation (Sec. II.B step 3) of the two-site wave function psi_dev at
  * `site` across its middle bond: the Gram matrix of each middle sector is
  * formed by the grouped GEMM and diagonalized by a parallel Jacobi method
- * (float64, one workgroup per sector, sectors up to 1024 states).  Kept states:
+ * (float64, one workgroup per sector, sectors up to 4096 states; ESHAPE
+ * beyond).  Kept states:
  * the D largest singular values, extended to every value >= sigma_D (1 - 1e-10),
  * values <= 1e-14 sigma_max dropped.  direction 0 (left to right) replaces the
  * site tensor of `site` by the kept left singular vectors (left-canonical);
@@ -270,11 +292,14 @@ int bsdmrg_next_guess(bsdmrg_ctx* ctx, int site, int direction, const double* ps
 /* Diagonal of H_eff at `site` into diag_dev (psi layout), stream-ordered. */
 int bsdmrg_hpsi_diagonal(bsdmrg_ctx* ctx, int site, double* diag_dev, bsdmrg_stream_t stream);
 
-/* Statistics of the last prepared product at `site`: useful flops per product
- * (2 m n k summed over all non-identity sector GEMMs), number of channels,
- * K-segments and aggregated operators, and workspace bytes. */
+/* Statistics of the last prepared product at `site` (the work of Sec. II.B
+ * step 2): useful flops per product (2 m n k summed over all non-identity
+ * sector GEMMs), number of channels, K-segments and aggregated operators,
+ * workspace bytes, and the elements of the distinct operator blocks one
+ * product reads (stored and aggregated; each counted once).  Any output
+ * pointer may be NULL.  ESTATE if not prepared. */
 int bsdmrg_hpsi_info(bsdmrg_ctx* ctx, int site, int precision, double* flops, int64_t* n_channels,
-                     int64_t* n_segments, int64_t* n_aggregates, int64_t* ws_bytes);
+                     int64_t* n_segments, int64_t* n_aggregates, int64_t* ws_bytes, int64_t* op_elems);
 
 /* One product as bsdmrg_hpsi with a HIP event between consecutive kernel
  * launches (synchronizing).  For launch i (i < cap) it returns the elapsed
@@ -354,22 +379,77 @@ int bsdmrg_unpack(bsdmrg_ctx* ctx, int side, int bond, const void* src_dev, size
 
 /* Asynchronous offload of a block (Sec. III.A strategy 2, Sec. III.B.4):
  * pack into staging_dev on `compute` (synchronizing only the host-side
- * descriptor upload), then a device-to-host copy into pinned_host (allocated
- * with hipHostMalloc) on `side`, ordered after the pack by an event.  Returns
- * immediately after enqueueing the copy.  With release != 0 the block's device
- * memory is freed once the copy completes (the block then reports EBUSY until
- * prefetched).  staging_dev and pinned_host must hold bsdmrg_serialized_size
- * bytes and stay valid until bsdmrg_offload_wait returns. */
+ * descriptor upload the first time), then a device-to-host copy into
+ * pinned_host (allocated with hipHostMalloc) on `side`, ordered after the pack
+ * by an event.  Returns immediately after enqueueing the copy.  The pack waits
+ * on `compute` for the last copy or unpack that used staging_dev (the library
+ * tracks each staging buffer by address).  With release != 0 the block's
+ * device memory is freed by bsdmrg_offload_wait once the copy has completed
+ * (the block then reports EBUSY until prefetched); products and serializer
+ * descriptors of the block stay valid where the device has virtual memory
+ * management (the block keeps its address range and only its physical memory
+ * is returned).  staging_dev and pinned_host must hold
+ * bsdmrg_serialized_size bytes; pinned_host must stay valid until
+ * bsdmrg_offload_wait returns. */
 int bsdmrg_offload(bsdmrg_ctx* ctx, int side, int bond, void* staging_dev, void* pinned_host,
                    size_t cap, int release, bsdmrg_stream_t compute, bsdmrg_stream_t side_stream);
 /* Block until the last offload of (side, bond) has reached host memory
- * ("fetching").  Returns the host-side wait in seconds in *waited_s if non-NULL. */
+ * ("fetching", the blocking wait of Sec. III.B.4 when the copy is not yet
+ * done), then free the device memory if the offload asked for it.  The host
+ * wait in seconds goes to *waited_s (optional) and into the statistics as
+ * exposed IO. */
 int bsdmrg_offload_wait(bsdmrg_ctx* ctx, int side, int bond, double* waited_s);
-/* Reload a block: validate pinned_host on the host, copy it to staging_dev on
- * `side`, then unpack on `compute` after an event (re-allocating the block's
- * device memory if it was released).  ECORRUPT if the stream does not match. */
+/* Reload a block (Sec. III.B.4): validate pinned_host on the host, copy it to
+ * staging_dev on `side` (after the last pack or unpack that used staging_dev),
+ * then unpack on `compute` after an event (backing the block with device
+ * memory again if it was released; the unpack writes every element).  Work
+ * enqueued on `compute` before this call runs before the unpack and overlaps
+ * the copy; work enqueued after it reads the restored block.  staging_dev and
+ * pinned_host must stay valid until the unpack has run (bsdmrg_prefetch_wait,
+ * or any later synchronization of `compute`).  ECORRUPT if the stream does not
+ * match the block. */
 int bsdmrg_prefetch(bsdmrg_ctx* ctx, int side, int bond, const void* pinned_host, void* staging_dev,
                     size_t bytes, bsdmrg_stream_t compute, bsdmrg_stream_t side_stream);
+/* Block until the last prefetch of (side, bond) has been unpacked; the host
+ * wait in seconds goes to *waited_s (optional) and into the exposed IO. */
+int bsdmrg_prefetch_wait(bsdmrg_ctx* ctx, int side, int bond, double* waited_s);
+/* Test hook for the fetching path of Sec. III.B.4: every later side-stream
+ * copy of bsdmrg_offload / bsdmrg_prefetch is preceded by a host function that
+ * sleeps `ms` milliseconds on the side stream (0 disables; at most 10 s), so
+ * the copy finishes late and the blocking waits become visible. */
+int bsdmrg_set_side_delay(bsdmrg_ctx* ctx, double ms);
+
+/* Segmented offload in the synchronous small-buffer form of Sec. III.A
+ * (strategy 1, Fig. 4b) with self-contained packages (Sec. III.B.3).  The
+ * block's families are cut into segments of whole layers that fit half of
+ * staging_dev (staging_bytes, 256-byte aligned); a segment is packed into one
+ * half on `compute` while the other half is copied to pinned_host on `side`.
+ * Every segment starts with a 256-byte header (magic "BSDSEG01", owner block,
+ * family, first layer, layer count, payload bytes, skeleton fingerprint,
+ * index) followed by its layers (blocks compact row-major, padded to 256 B),
+ * so segments can be stored, moved and read back in any order.
+ * bsdmrg_segments_size gives the exact total and the segment count for a
+ * staging size (host arithmetic).  ENOMEM if half the staging area cannot hold
+ * one layer of a family or cap is too small.  Synchronizing; *written gets the
+ * bytes written. */
+int bsdmrg_segments_size(bsdmrg_ctx* ctx, int side, int bond, size_t staging_bytes, size_t* bytes,
+                         int* n_segments);
+int bsdmrg_pack_segments(bsdmrg_ctx* ctx, int side, int bond, void* staging_dev, size_t staging_bytes,
+                         void* pinned_host, size_t cap, size_t* written, int* n_segments,
+                         bsdmrg_stream_t compute, bsdmrg_stream_t side_stream);
+/* Read segments (any order, back to back in pinned_host, `bytes` in total)
+ * into the block through the same double-buffered staging area, backing a
+ * released block with device memory again.  Every header is checked first:
+ * ECORRUPT, with nothing written, unless the segments belong to this block,
+ * match its skeletons and cover every layer of every family exactly once.
+ * Synchronizing. */
+int bsdmrg_unpack_segments(bsdmrg_ctx* ctx, int side, int bond, const void* pinned_host, size_t bytes,
+                           void* staging_dev, size_t staging_bytes, bsdmrg_stream_t compute,
+                           bsdmrg_stream_t side_stream);
+/* Workgroups of the serializer's copy launches for all later packs and
+ * unpacks (0: one per copy task, the default).  The bytes written do not
+ * depend on it (Sec. III.B.2: the serializing threads are independent). */
+int bsdmrg_set_copy_workgroups(int workgroups);
 
 /* Device bytes held by the block operators of (side, bond) (Sec. III.A: the
  * memory the offload frees). */

@@ -95,7 +95,7 @@ _SIGS = {
                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_int)], c_int),
     "bsdmrg_hpsi_schedule": ([c_vp, c_int, c_int, ctypes.c_double, c_int, c_int], c_int),
     "bsdmrg_hpsi_info": ([c_vp, c_int, c_int, ctypes.POINTER(ctypes.c_double), c_i64p, c_i64p,
-                          c_i64p, c_i64p], c_int),
+                          c_i64p, c_i64p, c_i64p], c_int),
     "bsdmrg_hpsi_profile": ([c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_int, c_vp, c_vp, c_vp, c_vp,
                              ctypes.POINTER(c_int)], c_int),
     "bsdmrg_davidson": ([c_vp, c_int, c_vp, c_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(c_int),
@@ -117,6 +117,15 @@ _SIGS = {
     "bsdmrg_offload_wait": ([c_vp, c_int, c_int, ctypes.POINTER(ctypes.c_double)], c_int),
     "bsdmrg_prefetch": ([c_vp, c_int, c_int, c_vp, c_vp, c_sz, c_vp, c_vp], c_int),
     "bsdmrg_block_bytes": ([c_vp, c_int, c_int, ctypes.POINTER(c_sz)], c_int),
+    "bsdmrg_prefetch_wait": ([c_vp, c_int, c_int, ctypes.POINTER(ctypes.c_double)], c_int),
+    "bsdmrg_set_side_delay": ([c_vp, ctypes.c_double], c_int),
+    "bsdmrg_set_hbm_budget": ([c_vp, c_sz, c_sz], c_int),
+    "bsdmrg_segments_size": ([c_vp, c_int, c_int, c_sz, ctypes.POINTER(c_sz), ctypes.POINTER(c_int)], c_int),
+    "bsdmrg_pack_segments": ([c_vp, c_int, c_int, c_vp, c_sz, c_vp, c_sz, ctypes.POINTER(c_sz),
+                              ctypes.POINTER(c_int), c_vp, c_vp], c_int),
+    "bsdmrg_unpack_segments": ([c_vp, c_int, c_int, c_vp, c_sz, c_vp, c_sz, c_vp, c_vp], c_int),
+    "bsdmrg_set_copy_workgroups": ([c_int], c_int),
+    "bsdmrg_hpsi_streamed": ([c_vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_sz), ctypes.POINTER(c_int)], c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -282,11 +291,11 @@ def bsdmrg_hpsi(ctx, site, psi_dev, out_dev, precision=FP64, stream=None):
 
 def bsdmrg_hpsi_info(ctx, site, precision=FP64):
     fl = ctypes.c_double()
-    a, b, c, d = (ctypes.c_int64() for _ in range(4))
+    a, b, c, d, e = (ctypes.c_int64() for _ in range(5))
     _check(_lib.bsdmrg_hpsi_info(ctx, site, precision, ctypes.byref(fl), ctypes.byref(a), ctypes.byref(b),
-                                 ctypes.byref(c), ctypes.byref(d)))
+                                 ctypes.byref(c), ctypes.byref(d), ctypes.byref(e)))
     return {"flops": fl.value, "channels": a.value, "segments": b.value, "aggregates": c.value,
-            "ws_bytes": d.value}
+            "ws_bytes": d.value, "op_elems": e.value}
 
 
 def bsdmrg_hpsi_schedule(ctx, site, precision, target_waves=8192.0, xcd_order=1, wave_max=64):
@@ -459,3 +468,48 @@ def bsdmrg_block_bytes(ctx, side, bond):
     n = c_sz()
     _check(_lib.bsdmrg_block_bytes(ctx, side, bond, ctypes.byref(n)))
     return n.value
+
+
+def bsdmrg_prefetch_wait(ctx, side, bond):
+    w = ctypes.c_double()
+    _check(_lib.bsdmrg_prefetch_wait(ctx, side, bond, ctypes.byref(w)))
+    return w.value
+
+
+def bsdmrg_set_side_delay(ctx, ms):
+    _check(_lib.bsdmrg_set_side_delay(ctx, float(ms)))
+
+
+def bsdmrg_set_hbm_budget(ctx, nbytes, chunk_bytes=0):
+    _check(_lib.bsdmrg_set_hbm_budget(ctx, int(nbytes), int(chunk_bytes)))
+
+
+def bsdmrg_hpsi_streamed(ctx, site):
+    """Returns (streamed, pinned host bytes copied per product, chunks)."""
+    st, hb, nc = c_int(), c_sz(), c_int()
+    _check(_lib.bsdmrg_hpsi_streamed(ctx, site, ctypes.byref(st), ctypes.byref(hb), ctypes.byref(nc)))
+    return bool(st.value), hb.value, nc.value
+
+
+def bsdmrg_segments_size(ctx, side, bond, staging_bytes):
+    """Returns (bytes, segments) of the segmented form for a staging size."""
+    n, k = c_sz(), c_int()
+    _check(_lib.bsdmrg_segments_size(ctx, side, bond, staging_bytes, ctypes.byref(n), ctypes.byref(k)))
+    return n.value, k.value
+
+
+def bsdmrg_pack_segments(ctx, side, bond, staging, staging_bytes, pinned, cap, compute=None, side_stream=None):
+    """Returns (bytes written, segments)."""
+    n, k = c_sz(), c_int()
+    _check(_lib.bsdmrg_pack_segments(ctx, side, bond, _ptr(staging), staging_bytes, _ptr(pinned), cap,
+                                     ctypes.byref(n), ctypes.byref(k), _stream(compute), _stream(side_stream)))
+    return n.value, k.value
+
+
+def bsdmrg_unpack_segments(ctx, side, bond, pinned, nbytes, staging, staging_bytes, compute=None, side_stream=None):
+    _check(_lib.bsdmrg_unpack_segments(ctx, side, bond, _ptr(pinned), nbytes, _ptr(staging), staging_bytes,
+                                       _stream(compute), _stream(side_stream)))
+
+
+def bsdmrg_set_copy_workgroups(n):
+    _check(_lib.bsdmrg_set_copy_workgroups(int(n)))

@@ -30,10 +30,152 @@ void DevBuf::release() {
   n = 0;
 }
 
-Ctx::~Ctx() {}
+Ctx::~Ctx() {
+  for (auto& kv : staging_busy) (void)hipEventDestroy(kv.second);
+}
+
+void Block::mark_use(hipStream_t s) {
+  if (!last_use) BSD_HIP(hipEventCreateWithFlags(&last_use, hipEventDisableTiming));
+  BSD_HIP(hipEventRecord(last_use, s));
+}
+
+void Block::quiesce() {
+  if (offload_pending && offload_done) (void)hipEventSynchronize(offload_done);
+  if (prefetch_pending && prefetch_done) (void)hipEventSynchronize(prefetch_done);
+  if (last_use) (void)hipEventSynchronize(last_use);
+}
 
 Block::~Block() {
+  // no queued copy, unpack or product may touch the memory after it is freed
+  quiesce();
   if (offload_done) (void)hipEventDestroy(offload_done);
+  if (prefetch_done) (void)hipEventDestroy(prefetch_done);
+  if (last_use) (void)hipEventDestroy(last_use);
+}
+
+static hipMemAllocationProp device_prop(int dev) {
+  hipMemAllocationProp prop = {};
+  prop.type = hipMemAllocationTypePinned;
+  prop.location.type = hipMemLocationTypeDevice;
+  prop.location.id = dev;
+  return prop;
+}
+
+void BlockMem::create(size_t n) {
+  bytes = std::max<size_t>(n, 256);
+  BSD_HIP(hipGetDevice(&device));
+  int vmm_ok = 0;
+  if (hipDeviceGetAttribute(&vmm_ok, hipDeviceAttributeVirtualMemoryManagementSupported, device) != hipSuccess)
+    vmm_ok = 0;
+  size_t gran = 0;
+  if (vmm_ok) {
+    hipMemAllocationProp prop = device_prop(device);
+    if (hipMemGetAllocationGranularity(&gran, &prop, hipMemAllocationGranularityMinimum) != hipSuccess || gran == 0)
+      vmm_ok = 0;
+  }
+  if (vmm_ok) {
+    reserved = (bytes + gran - 1) / gran * gran;
+    // physical memory in pieces of at most 1 GiB, mapped back to back
+    piece = std::min(reserved, std::max(gran, ((size_t)1 << 30) / gran * gran));
+    if (hipMemAddressReserve(&va, reserved, 0, nullptr, 0) != hipSuccess) {
+      va = nullptr;
+      vmm_ok = 0;
+    } else {
+      vmm = true;
+      if (!map_pieces()) {
+        // fall back to a plain allocation (its address is not stable)
+        (void)hipMemAddressFree(va, reserved);
+        va = nullptr;
+        vmm = false;
+        vmm_ok = 0;
+      }
+    }
+  }
+  if (!vmm_ok) {
+    vmm = false;
+    reserved = bytes;
+    BSD_HIP(hipMalloc(&va, reserved));
+    mapped = true;
+  }
+}
+
+bool BlockMem::map_pieces() {
+  hipMemAllocationProp prop = device_prop(device);
+  hipMemAccessDesc ad = {};
+  ad.location = prop.location;
+  ad.flags = hipMemAccessFlagsProtReadWrite;
+  handles.clear();
+  size_t done = 0;
+  bool ok = true;
+  while (done < reserved) {
+    const size_t len = std::min(piece, reserved - done);
+    hipMemGenericAllocationHandle_t h;
+    if (hipMemCreate(&h, len, &prop, 0) != hipSuccess) {
+      ok = false;
+      break;
+    }
+    char* at = static_cast<char*>(va) + done;
+    if (hipMemMap(at, len, 0, h, 0) != hipSuccess) {
+      (void)hipMemRelease(h);
+      ok = false;
+      break;
+    }
+    handles.push_back(reinterpret_cast<uint64_t>(h));
+    if (hipMemSetAccess(at, len, &ad, 1) != hipSuccess) {
+      done += len;
+      ok = false;
+      break;
+    }
+    done += len;
+  }
+  if (!ok) {
+    size_t off = 0;
+    for (size_t i = 0; i < handles.size(); ++i) {
+      const size_t len = std::min(piece, reserved - off);
+      (void)hipMemUnmap(static_cast<char*>(va) + off, len);
+      (void)hipMemRelease(reinterpret_cast<hipMemGenericAllocationHandle_t>(handles[i]));
+      off += len;
+    }
+    handles.clear();
+    (void)hipGetLastError();
+    return false;
+  }
+  mapped = true;
+  return true;
+}
+
+void BlockMem::acquire_physical() {
+  if (mapped) return;
+  if (!vmm) {
+    BSD_HIP(hipMalloc(&va, reserved));
+    mapped = true;
+    return;
+  }
+  BSD_CHECK(map_pieces(), 4, "device memory for the block could not be created again");
+}
+
+void BlockMem::release_physical() {
+  if (!mapped) return;
+  if (!vmm) {
+    (void)hipFree(va);
+    va = nullptr;
+    mapped = false;
+    return;
+  }
+  size_t off = 0;
+  for (size_t i = 0; i < handles.size(); ++i) {
+    const size_t len = std::min(piece, reserved - off);
+    (void)hipMemUnmap(static_cast<char*>(va) + off, len);
+    (void)hipMemRelease(reinterpret_cast<hipMemGenericAllocationHandle_t>(handles[i]));
+    off += len;
+  }
+  handles.clear();
+  mapped = false;
+}
+
+BlockMem::~BlockMem() {
+  release_physical();
+  if (vmm && va) (void)hipMemAddressFree(va, reserved);
 }
 
 Skeleton make_skeleton(const Basis& in, const Basis& out, const Q& dq) {
@@ -147,14 +289,16 @@ static std::unique_ptr<Block> alloc_block(bool left, int first, int last, const 
     B->fams[f].keys.push_back(k);
     B->ops[k] = r;
   }
+  size_t total = 0;
   for (auto& f : B->fams) {
-    size_t bytes = f.bytes();
-    auto m = std::make_unique<DevBuf>();
-    m->reserve(bytes);
-    if (bytes) BSD_HIP(hipMemsetAsync(m->p, 0, bytes, s));
-    f.dev = static_cast<double*>(m->p);
-    B->mem.push_back(std::move(m));
+    B->fam_off.push_back(total);
+    total += (f.bytes() + 255) / 256 * 256;
   }
+  B->mem = std::make_unique<BlockMem>();
+  B->mem->create(total);
+  if (total) BSD_HIP(hipMemsetAsync(B->mem->va, 0, total, s));
+  for (size_t i = 0; i < B->fams.size(); ++i)
+    B->fams[i].dev = reinterpret_cast<double*>(static_cast<char*>(B->mem->va) + B->fam_off[i]);
   return B;
 }
 

@@ -2,7 +2,9 @@
 #include "../../include/bsdmrg.h"
 
 #include <chrono>
+#include <cstddef>
 #include <cmath>
+#include <thread>
 
 #include "davidson.h"
 #include "stvec.h"
@@ -21,6 +23,17 @@ static hipStream_t S(bsdmrg_stream_t s) { return reinterpret_cast<hipStream_t>(s
 
 static double wall_now() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// A host function on a stream that sleeps: holds back the copies queued
+// after it on the side stream (forces the blocking fetch in tests).
+static void sleep_host_fn(void* arg) {
+  const double ms = *static_cast<double*>(arg);
+  delete static_cast<double*>(arg);
+  std::this_thread::sleep_for(std::chrono::microseconds((int64_t)(ms * 1000.0)));
+}
+static void delay_on(hipStream_t s, double ms) {
+  BSD_HIP(hipLaunchHostFunc(s, sleep_host_fn, new double(ms)));
 }
 
 // adds the wall time of its scope to one phase of the context statistics
@@ -111,20 +124,40 @@ static Block* need_block(Ctx& c, int side, int bond) {
 }
 
 static void ensure_splan(Block& b, hipStream_t s) {
-  if (!b.splan) b.splan = serial_plan(block_views(b, b.left), s);
+  if (!b.splan) b.splan = serial_plan(block_views(b, b.left), s, true);
 }
 
-static void realloc_block(Block& b, hipStream_t s) {
-  b.mem.clear();
-  for (auto& f : b.fams) {
-    auto m = std::make_unique<DevBuf>();
-    m->reserve(f.bytes());
-    if (f.bytes()) BSD_HIP(hipMemsetAsync(m->p, 0, f.bytes(), s));
-    f.dev = static_cast<double*>(m->p);
-    b.mem.push_back(std::move(m));
+// Back a released block with device memory again.  With stable addresses
+// (virtual memory management) every pointer into the block stays valid: the
+// serializer descriptors and the product plans are kept.  Otherwise the
+// families move and everything that points into them is rebuilt.  The unpack
+// that follows writes every element, so the memory is not cleared.
+static void reacquire_block(Ctx& c, Block& b) {
+  b.mem->acquire_physical();
+  if (!b.mem->stable()) {
+    for (size_t i = 0; i < b.fams.size(); ++i)
+      b.fams[i].dev = reinterpret_cast<double*>(static_cast<char*>(b.mem->va) + b.fam_off[i]);
+    b.splan.reset();
+    c.plans.clear();
   }
-  b.splan.reset();
   b.resident = true;
+}
+
+// Staging buffers shared by offloads and prefetches: the last operation that
+// used a buffer records an event (after its D2H copy, or after its unpack), and
+// the next operation that writes the buffer waits for it on its own stream.
+static void staging_wait(Ctx& c, const void* staging, hipStream_t writer) {
+  auto it = c.staging_busy.find(staging);
+  if (it != c.staging_busy.end()) BSD_HIP(hipStreamWaitEvent(writer, it->second, 0));
+}
+static void staging_mark(Ctx& c, const void* staging, hipStream_t last_user) {
+  auto it = c.staging_busy.find(staging);
+  if (it == c.staging_busy.end()) {
+    hipEvent_t e;
+    BSD_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    it = c.staging_busy.emplace(staging, e).first;
+  }
+  BSD_HIP(hipEventRecord(it->second, last_user));
 }
 
 }  // namespace bsd
@@ -208,6 +241,17 @@ int bsdmrg_load_integrals(bsdmrg_ctx* ctx, const double* h, const double* eri, d
 }
 
 static HpsiPlan* get_plan(Ctx& c, int site, int precision, size_t ws, hipStream_t s, bool rebuild);
+
+// the environment blocks a prepared product reads must be on the device (a
+// streamed product reads its right operators from pinned host memory)
+static void need_env(Ctx& c, int site, const HpsiPlan* p, Block** Lo = nullptr, Block** Ro = nullptr) {
+  Block* Lb = get_block(c, true, site);
+  Block* Rb = get_block(c, false, site + 2);
+  BSD_CHECK(Lb && Rb, BSDMRG_ESTATE, "environment blocks not built");
+  BSD_CHECK(Lb->resident && (Rb->resident || (p && p->stream_r)), BSDMRG_EBUSY, "environment blocks not resident");
+  if (Lo) *Lo = Lb;
+  if (Ro) *Ro = Rb;
+}
 
 static void set_site_tensor_impl(Ctx& c, int site, int n_blocks, const int32_t* meta, const double* data) {
     BSD_CHECK(site >= 0 && site < c.L, BSDMRG_EINVAL, "site out of range");
@@ -442,7 +486,13 @@ static HpsiPlan* get_plan(Ctx& c, int site, int precision, size_t ws, hipStream_
   if (it != c.plans.end() && !rebuild) return it->second.get();
   if (ws == 0) ws = c.hpsi_ws_default;
   PhaseTimer tm(c, BSDMRG_PH_TABLES);
-  auto p = build_hpsi_plan(c, site, precision, ws, s);
+  Block* Lb = get_block(c, true, site);
+  Block* Rb = get_block(c, false, site + 2);
+  const bool stream = c.hbm_budget > 0 && Lb && Rb && Lb->device_bytes() + Rb->device_bytes() > c.hbm_budget;
+  auto p = build_hpsi_plan(c, site, precision, ws, s, stream);
+  // a streamed product does not read the right block's memory: the diagonal
+  // (which does) is formed now, while the block is resident
+  if (stream) hpsi_diagonal(*p, s);
   HpsiPlan* raw = p.get();
   c.plans[key] = std::move(p);
   return raw;
@@ -494,9 +544,8 @@ int bsdmrg_hpsi_autotune(bsdmrg_ctx* ctx, int site, int precision, bsdmrg_stream
   return guard([&] {
     BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
     HpsiPlan* p = get_plan(ctx->c, site, precision, 0, S(stream), false);
-    Block* Lb = get_block(ctx->c, true, site);
-    Block* Rb = get_block(ctx->c, false, site + 2);
-    BSD_CHECK(Lb && Rb && Lb->resident && Rb->resident, BSDMRG_EBUSY, "environment blocks not resident");
+    Block *Lb = nullptr, *Rb = nullptr;
+    need_env(ctx->c, site, p, &Lb, &Rb);
     TuneResult r = autotune_hpsi(*p, precision, S(stream));
     if (best_ms) *best_ms = r.best_ms;
     if (default_ms) *default_ms = r.default_ms;
@@ -532,12 +581,15 @@ int bsdmrg_hpsi(bsdmrg_ctx* ctx, int site, const double* psi, double* out, int p
     BSD_CHECK(ctx && psi && out, BSDMRG_EINVAL, "NULL argument");
     BSD_CHECK(psi != out, BSDMRG_EINVAL, "psi and out must not alias");
     HpsiPlan* p = get_plan(ctx->c, site, precision, 0, S(stream), false);
-    Block* Lb = get_block(ctx->c, true, site);
-    Block* Rb = get_block(ctx->c, false, site + 2);
-    BSD_CHECK(Lb && Rb && Lb->resident && Rb->resident, BSDMRG_EBUSY, "environment blocks not resident");
+    Block *Lb = nullptr, *Rb = nullptr;
+    need_env(ctx->c, site, p, &Lb, &Rb);
     const double* pe = psi + p->lay.n_elems;
     BSD_CHECK(!(out < pe && psi < out + p->lay.n_elems), BSDMRG_EINVAL, "psi and out overlap");
+    p->stream_delay_ms = ctx->c.side_delay_ms;
     run_hpsi_graph(*p, psi, out, S(stream), precision);
+    Lb->mark_use(S(stream));
+    if (Rb->resident) Rb->mark_use(S(stream));
+    if (p->stream_r) ctx->c.st.bytes_h2d += (int64_t)p->pack_bytes;
     ctx->c.last_hpsi_flops = p->useful_flops;
     ctx->c.st.hpsi_calls += 1;
     ctx->c.st.hpsi_flops += p->useful_flops;
@@ -550,9 +602,9 @@ int bsdmrg_hpsi_profile(bsdmrg_ctx* ctx, int site, const double* psi, double* ou
   return guard([&] {
     BSD_CHECK(ctx && psi && out && n && (cap <= 0 || (ms && flops && kind)), BSDMRG_EINVAL, "NULL argument");
     HpsiPlan* p = get_plan(ctx->c, site, precision, 0, S(stream), false);
-    Block* Lb = get_block(ctx->c, true, site);
-    Block* Rb = get_block(ctx->c, false, site + 2);
-    BSD_CHECK(Lb && Rb && Lb->resident && Rb->resident, BSDMRG_EBUSY, "environment blocks not resident");
+    Block *Lb = nullptr, *Rb = nullptr;
+    need_env(ctx->c, site, p, &Lb, &Rb);
+    BSD_CHECK(!p->stream_r, BSDMRG_ESTATE, "per-launch profile of a streamed product is not available");
     *n = profile_hpsi(*p, psi, out, S(stream), precision, cap, ms, flops, bytes, kind);
   });
 }
@@ -562,9 +614,8 @@ int bsdmrg_davidson(bsdmrg_ctx* ctx, int site, double* psi, const bsdmrg_dav_opt
   return guard([&] {
     BSD_CHECK(ctx && psi && energy && iters && resid, BSDMRG_EINVAL, "NULL argument");
     HpsiPlan* p = get_plan(ctx->c, site, BSDMRG_FP64, 0, S(stream), false);
-    Block* Lb = get_block(ctx->c, true, site);
-    Block* Rb = get_block(ctx->c, false, site + 2);
-    BSD_CHECK(Lb && Rb && Lb->resident && Rb->resident, BSDMRG_EBUSY, "environment blocks not resident");
+    Block *Lb = nullptr, *Rb = nullptr;
+    need_env(ctx->c, site, p, &Lb, &Rb);
     DavidsonOpts o;
     if (opts) {
       BSD_CHECK(opts->max_iter > 0 && opts->max_subspace >= 4 && opts->max_subspace <= 30 && opts->restart >= 1 &&
@@ -581,12 +632,14 @@ int bsdmrg_davidson(bsdmrg_ctx* ctx, int site, double* psi, const bsdmrg_dav_opt
       o.precond_floor = opts->precond_floor;
     }
     PhaseTimer tm(ctx->c, BSDMRG_PH_DIAG_H);
+    p->stream_delay_ms = ctx->c.side_delay_ms;
     const double* d = hpsi_diagonal(*p, S(stream));
     DavidsonResult r = davidson(*p, d, psi, o, p->dav_work, S(stream));
     ctx->c.st.dav_calls += 1;
     ctx->c.st.dav_iters += r.iters;
     ctx->c.st.hpsi_calls += r.products;
     ctx->c.st.hpsi_flops += r.products * p->useful_flops;
+    if (p->stream_r) ctx->c.st.bytes_h2d += (int64_t)p->pack_bytes * r.products;
     *energy = r.energy;
     *iters = r.iters;
     *resid = r.resid;
@@ -611,13 +664,17 @@ int bsdmrg_hpsi_diagonal(bsdmrg_ctx* ctx, int site, double* diag, bsdmrg_stream_
   return guard([&] {
     BSD_CHECK(ctx && diag, BSDMRG_EINVAL, "NULL argument");
     HpsiPlan* p = get_plan(ctx->c, site, BSDMRG_FP64, 0, S(stream), false);
+    Block *Lb = nullptr, *Rb = nullptr;
+    need_env(ctx->c, site, p, &Lb, &Rb);
     const double* d = hpsi_diagonal(*p, S(stream));
     BSD_HIP(hipMemcpyAsync(diag, d, p->lay.n_elems * sizeof(double), hipMemcpyDeviceToDevice, S(stream)));
+    Lb->mark_use(S(stream));
+    if (Rb->resident) Rb->mark_use(S(stream));
   });
 }
 
 int bsdmrg_hpsi_info(bsdmrg_ctx* ctx, int site, int precision, double* flops, int64_t* n_channels,
-                     int64_t* n_segments, int64_t* n_aggregates, int64_t* ws_bytes) {
+                     int64_t* n_segments, int64_t* n_aggregates, int64_t* ws_bytes, int64_t* op_elems) {
   return guard([&] {
     BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
     BSD_CHECK(precision >= BSDMRG_FP64 && precision <= BSDMRG_BF16X6, BSDMRG_EINVAL, "unsupported precision");
@@ -629,6 +686,7 @@ int bsdmrg_hpsi_info(bsdmrg_ctx* ctx, int site, int precision, double* flops, in
     if (n_segments) *n_segments = (int64_t)p.nseg;
     if (n_aggregates) *n_aggregates = p.naggs;
     if (ws_bytes) *ws_bytes = (int64_t)(p.agg_bytes + p.v_bytes + p.plane_bytes);
+    if (op_elems) *op_elems = p.op_elems;
   });
 }
 
@@ -768,7 +826,7 @@ int bsdmrg_unpack(bsdmrg_ctx* ctx, int side, int bond, const void* src, size_t b
     Block* b = need_block(ctx->c, side, bond);
     BSD_CHECK(!b->offload_pending, BSDMRG_EBUSY, "offload in flight; wait first");
     PhaseTimer tm(ctx->c, BSDMRG_PH_IO);
-    if (!b->resident) realloc_block(*b, S(stream));
+    if (!b->resident) reacquire_block(ctx->c, *b);
     ensure_splan(*b, S(stream));
     BSD_CHECK(bytes == serial_bytes(*b->splan), BSDMRG_ECORRUPT, "stream size does not match the block");
     serial_unpack(*b->splan, src, bytes, S(stream));
@@ -786,20 +844,28 @@ int bsdmrg_offload(bsdmrg_ctx* ctx, int side, int bond, void* staging, void* pin
     Block* b = need_block(ctx->c, side, bond);
     BSD_CHECK(b->resident, BSDMRG_EBUSY, "block not resident");
     BSD_CHECK(!b->offload_pending, BSDMRG_EBUSY, "previous offload still pending");
+    PhaseTimer tm(ctx->c, BSDMRG_PH_IO);
     ensure_splan(*b, S(compute));
     const size_t bytes = serial_bytes(*b->splan);
     BSD_CHECK(cap >= bytes, BSDMRG_ENOMEM, "buffers smaller than the serialized size");
+    // the pack overwrites staging: after the last copy or unpack that read it
+    staging_wait(ctx->c, staging, S(compute));
     serial_pack(*b->splan, staging, cap, S(compute));
+    b->mark_use(S(compute));
     hipEvent_t packed;
     BSD_HIP(hipEventCreateWithFlags(&packed, hipEventDisableTiming));
     BSD_HIP(hipEventRecord(packed, S(compute)));
     BSD_HIP(hipStreamWaitEvent(S(side_stream), packed, 0));
+    BSD_HIP(hipEventDestroy(packed));
+    if (ctx->c.side_delay_ms > 0) delay_on(S(side_stream), ctx->c.side_delay_ms);
     BSD_HIP(hipMemcpyAsync(pinned, staging, bytes, hipMemcpyDeviceToHost, S(side_stream)));
+    staging_mark(ctx->c, staging, S(side_stream));
     if (!b->offload_done) BSD_HIP(hipEventCreateWithFlags(&b->offload_done, hipEventDisableTiming));
     BSD_HIP(hipEventRecord(b->offload_done, S(side_stream)));
-    BSD_HIP(hipEventDestroy(packed));
     b->offload_pending = true;
     b->release_after = release != 0;
+    ctx->c.st.bytes_packed += (int64_t)bytes;
+    ctx->c.st.bytes_d2h += (int64_t)bytes;
   });
 }
 
@@ -810,14 +876,20 @@ int bsdmrg_offload_wait(bsdmrg_ctx* ctx, int side, int bond, double* waited) {
     auto t0 = std::chrono::steady_clock::now();
     if (b->offload_pending) BSD_HIP(hipEventSynchronize(b->offload_done));
     auto t1 = std::chrono::steady_clock::now();
-    if (waited) *waited = std::chrono::duration<double>(t1 - t0).count();
+    const double w = std::chrono::duration<double>(t1 - t0).count();
+    if (waited) *waited = w;
+    ctx->c.st.io_exposed_s += w;
     if (b->offload_pending && b->release_after) {
-      b->mem.clear();
-      for (auto& f : b->fams) f.dev = nullptr;
-      b->splan.reset();
+      // the copy has completed; products that read the block were enqueued
+      // before the offload on the compute stream, which the pack followed
+      b->quiesce();   // the copy, and every product enqueued before this call
+      b->mem->release_physical();
       b->resident = false;
-      // plans referencing this block are stale
-      ctx->c.plans.clear();
+      if (!b->mem->stable()) {
+        for (auto& f : b->fams) f.dev = nullptr;
+        b->splan.reset();
+        ctx->c.plans.clear();   // plans referencing this block are stale
+      }
     }
     b->offload_pending = false;
   });
@@ -829,19 +901,127 @@ int bsdmrg_prefetch(bsdmrg_ctx* ctx, int side, int bond, const void* pinned, voi
     BSD_CHECK(ctx && pinned && staging, BSDMRG_EINVAL, "NULL argument");
     Block* b = need_block(ctx->c, side, bond);
     BSD_CHECK(!b->offload_pending, BSDMRG_EBUSY, "offload in flight; wait first");
+    PhaseTimer tm(ctx->c, BSDMRG_PH_IO);
     int st = validate_stream_host(block_views(*b, b->left), pinned, bytes);
     BSD_CHECK(st == 0, BSDMRG_ECORRUPT, "host stream does not match the block");
-    const bool realloc = !b->resident;
-    if (realloc) realloc_block(*b, S(compute));
+    if (!b->resident) reacquire_block(ctx->c, *b);
     ensure_splan(*b, S(compute));   // descriptors first: no host wait after the copy is queued
+    // the copy overwrites staging: after the last pack copy-out or unpack that read it
+    staging_wait(ctx->c, staging, S(side_stream));
+    if (ctx->c.side_delay_ms > 0) delay_on(S(side_stream), ctx->c.side_delay_ms);
     BSD_HIP(hipMemcpyAsync(staging, pinned, bytes, hipMemcpyHostToDevice, S(side_stream)));
     hipEvent_t loaded;
     BSD_HIP(hipEventCreateWithFlags(&loaded, hipEventDisableTiming));
     BSD_HIP(hipEventRecord(loaded, S(side_stream)));
     BSD_HIP(hipStreamWaitEvent(S(compute), loaded, 0));
-    serial_unpack(*b->splan, staging, bytes, S(compute));
     BSD_HIP(hipEventDestroy(loaded));
-    if (realloc) ctx->c.plans.clear();
+    serial_unpack(*b->splan, staging, bytes, S(compute));
+    staging_mark(ctx->c, staging, S(compute));
+    if (!b->prefetch_done) BSD_HIP(hipEventCreateWithFlags(&b->prefetch_done, hipEventDisableTiming));
+    BSD_HIP(hipEventRecord(b->prefetch_done, S(compute)));
+    b->prefetch_pending = true;
+    ctx->c.st.bytes_h2d += (int64_t)bytes;
+    ctx->c.st.bytes_unpacked += (int64_t)bytes;
+  });
+}
+
+int bsdmrg_segments_size(bsdmrg_ctx* ctx, int side, int bond, size_t staging_bytes, size_t* bytes,
+                         int* n_segments) {
+  return guard([&] {
+    BSD_CHECK(ctx && bytes, BSDMRG_EINVAL, "NULL argument");
+    Block* b = need_block(ctx->c, side, bond);
+    BSD_CHECK(b->resident, BSDMRG_EBUSY, "block not resident");
+    ensure_splan(*b, nullptr);
+    *bytes = serial_segments_size(*b->splan, staging_bytes, n_segments);
+  });
+}
+
+int bsdmrg_pack_segments(bsdmrg_ctx* ctx, int side, int bond, void* staging, size_t staging_bytes, void* pinned,
+                         size_t cap, size_t* written, int* n_segments, bsdmrg_stream_t compute,
+                         bsdmrg_stream_t side_stream) {
+  return guard([&] {
+    BSD_CHECK(ctx && staging && pinned, BSDMRG_EINVAL, "NULL argument");
+    Block* b = need_block(ctx->c, side, bond);
+    BSD_CHECK(b->resident, BSDMRG_EBUSY, "block not resident");
+    BSD_CHECK(!b->offload_pending, BSDMRG_EBUSY, "offload in flight; wait first");
+    PhaseTimer tm(ctx->c, BSDMRG_PH_IO);
+    ensure_splan(*b, S(compute));
+    staging_wait(ctx->c, staging, S(compute));
+    const size_t n = serial_pack_segments(*b->splan, staging, staging_bytes, pinned, cap, n_segments, S(compute),
+                                          S(side_stream));
+    if (written) *written = n;
+    ctx->c.st.bytes_packed += (int64_t)n;
+    ctx->c.st.bytes_d2h += (int64_t)n;
+  });
+}
+
+int bsdmrg_unpack_segments(bsdmrg_ctx* ctx, int side, int bond, const void* pinned, size_t bytes, void* staging,
+                           size_t staging_bytes, bsdmrg_stream_t compute, bsdmrg_stream_t side_stream) {
+  return guard([&] {
+    BSD_CHECK(ctx && staging && pinned, BSDMRG_EINVAL, "NULL argument");
+    Block* b = need_block(ctx->c, side, bond);
+    BSD_CHECK(!b->offload_pending, BSDMRG_EBUSY, "offload in flight; wait first");
+    PhaseTimer tm(ctx->c, BSDMRG_PH_IO);
+    const bool was_resident = b->resident;
+    if (!b->resident) reacquire_block(ctx->c, *b);
+    ensure_splan(*b, S(compute));
+    staging_wait(ctx->c, staging, S(side_stream));
+    const int st = serial_unpack_segments(*b->splan, pinned, bytes, staging, staging_bytes, S(compute),
+                                          S(side_stream));
+    if (st != 0 && !was_resident) {
+      b->mem->release_physical();   // nothing was written: the block stays released
+      b->resident = false;
+    }
+    BSD_CHECK(st == 0, BSDMRG_ECORRUPT, "segments do not match the block or do not cover it exactly once");
+    ctx->c.st.bytes_h2d += (int64_t)bytes;
+    ctx->c.st.bytes_unpacked += (int64_t)bytes;
+  });
+}
+
+int bsdmrg_set_copy_workgroups(int workgroups) {
+  return guard([&] {
+    BSD_CHECK(workgroups >= 0, BSDMRG_EINVAL, "negative workgroup count");
+    set_copy_grid(workgroups);
+  });
+}
+
+int bsdmrg_prefetch_wait(bsdmrg_ctx* ctx, int side, int bond, double* waited) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    Block* b = need_block(ctx->c, side, bond);
+    auto t0 = std::chrono::steady_clock::now();
+    if (b->prefetch_pending) BSD_HIP(hipEventSynchronize(b->prefetch_done));
+    const double w = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (waited) *waited = w;
+    ctx->c.st.io_exposed_s += w;
+    b->prefetch_pending = false;
+  });
+}
+
+int bsdmrg_set_hbm_budget(bsdmrg_ctx* ctx, size_t bytes, size_t chunk_bytes) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    ctx->c.hbm_budget = bytes;
+    ctx->c.stream_chunk_bytes = chunk_bytes ? chunk_bytes : (size_t)1 << 30;
+  });
+}
+
+int bsdmrg_hpsi_streamed(bsdmrg_ctx* ctx, int site, int* streamed, size_t* host_bytes, int* n_chunks) {
+  return guard([&] {
+    BSD_CHECK(ctx && streamed, BSDMRG_EINVAL, "NULL argument");
+    auto it = ctx->c.plans.find({site, 0});
+    BSD_CHECK(it != ctx->c.plans.end(), BSDMRG_ESTATE, "product not prepared");
+    *streamed = it->second->stream_r ? 1 : 0;
+    if (host_bytes) *host_bytes = it->second->pack_bytes;
+    if (n_chunks) *n_chunks = (int)it->second->phase1.size();
+  });
+}
+
+int bsdmrg_set_side_delay(bsdmrg_ctx* ctx, double ms) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    BSD_CHECK(ms >= 0.0 && ms <= 10000.0, BSDMRG_EINVAL, "delay out of [0, 10000] ms");
+    ctx->c.side_delay_ms = ms;
   });
 }
 

@@ -41,8 +41,11 @@ struct Ctx {
     int64_t hpsi_calls = 0, dav_calls = 0, dav_iters = 0, truncations = 0;
     int64_t bytes_packed = 0, bytes_unpacked = 0, bytes_d2h = 0, bytes_h2d = 0;
   } st;
+  std::map<const void*, hipEvent_t> staging_busy;   // last use of each staging buffer
+  double side_delay_ms = 0.0;                       // host delay before each side-stream copy
   size_t hpsi_ws_default = (size_t)16 << 30;
   size_t hbm_budget = 0;
+  size_t stream_chunk_bytes = (size_t)1 << 30;   // right operators per streamed chunk
   double last_hpsi_flops = 0.0;
   double renorm_flops = 0.0;     // useful flops of the grouped-GEMM phases
   double renorm_wall_s = 0.0;    // wall time of renormalization steps

@@ -275,10 +275,12 @@ DavidsonResult davidson(HpsiPlan& plan, const double* diag, double* psi, const D
   };
   double theta = 0.0, rn = 0.0;
   int total = 0;
+  bool reached = false;   // the last solve stopped at its residual bound
   // one Davidson run from psi with products at `prec`; stops when the residual
   // is below tol (rel_floor * |theta| counts too: the noise level of a split
   // product) or after max_it iterations; leaves the Ritz vector in psi
   auto solve = [&](double tol, double rel_floor, int max_it) {
+    reached = false;
     normalize_into(psi, w.V);
     H(w.V, w.W);
     int k = 1;
@@ -299,7 +301,10 @@ DavidsonResult davidson(HpsiPlan& plan, const double* diag, double* psi, const D
       theta = hs[0];
       rn = std::sqrt(std::max(0.0, hs[1]));
       res.ritz.push_back(theta);
-      if (rn <= std::max(tol, rel_floor * std::fabs(theta))) break;
+      if (rn <= std::max(tol, rel_floor * std::fabs(theta))) {
+        reached = true;
+        break;
+      }
       if (k == M) {
         // thick restart: keep the R lowest Ritz vectors (and their products)
         hipLaunchKernelGGL(rotate_kernel, dim3(G), dim3(256), 0, s, w.V, n, k, w.Y, R, w.tmp, n);
@@ -330,16 +335,36 @@ DavidsonResult davidson(HpsiPlan& plan, const double* diag, double* psi, const D
     normalize_into(w.x, psi);
     total += std::min(it + 1, max_it);
   };
+  // energy and residual of the normalized psi from one float64 product (no
+  // new direction): the Rayleigh quotient that finishes a split run
+  auto rayleigh = [&]() {
+    normalize_into(psi, w.V);
+    H(w.V, w.W);
+    dots(w, w.V, 1, w.W, w.sc, s);
+    hipLaunchKernelGGL(residual_kernel, dim3(G), dim3(256), 0, s, w.V, w.W, diag, w.sc, o.precond_floor, 1, w.r,
+                       w.t, n);
+    dots(w, w.r, 1, w.r, w.sc + 1, s);
+    double hs[2];
+    BSD_HIP(hipMemcpyAsync(hs, w.sc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+    BSD_HIP(hipMemcpyAsync(psi, w.V, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    BSD_HIP(hipStreamSynchronize(s));
+    theta = hs[0];
+    rn = std::sqrt(std::max(0.0, hs[1]));
+    res.ritz.push_back(theta);
+  };
   if (o.precision == 0) {
     solve(o.tol, 0.0, o.max_iter);
   } else {
     // split-bf16 products down to their noise level (relative product error
     // about 5e-8 for six products, 5e-6 for three), then float64 products from
-    // the Ritz vector: the energy and the residual are float64 quantities
+    // the Ritz vector for the iterations left; with none left, one float64
+    // product gives the Rayleigh quotient of the split run's vector.  Either
+    // way the energy and the residual returned are float64 quantities.
     const double eps = o.precision == 2 ? 5e-8 : 5e-6;
     solve(o.tol, 4.0 * eps, o.max_iter);
     prec = 0;
-    solve(o.tol, 0.0, std::max(1, o.max_iter - total));
+    if (reached && total < o.max_iter) solve(o.tol, 0.0, o.max_iter - total);
+    else rayleigh();
   }
   BSD_HIP(hipStreamSynchronize(s));
   res.energy = theta;

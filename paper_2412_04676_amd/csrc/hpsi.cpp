@@ -15,6 +15,11 @@
 #include "hpsi.h"
 
 #include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <thread>
 
 namespace bsd {
 
@@ -124,12 +129,85 @@ static Operand2 lref_block(const Block& Lb, const LRef& r, const std::vector<Ske
   return o;
 }
 
+// pack of the streamed right operators: rows x ld float64 blocks gathered from
+// the block's device memory into a contiguous buffer
+__global__ void __launch_bounds__(256) gather_kernel(const StreamGather* __restrict__ g, double* __restrict__ dst) {
+  const StreamGather t = g[blockIdx.x];
+  for (int64_t e = threadIdx.x; e < t.n; e += blockDim.x) dst[t.off + e] = t.src[e];
+}
+
+// Slots and host packs of a streamed product: two device slots for the
+// float64 operator packs and two for their planes (chunk k uses slot k % 2),
+// the packs themselves in pinned host memory, filled here from the resident
+// right block (gather on the device, one copy to the host per chunk).
+void prepare_stream_slots(HpsiPlan& plan, std::vector<std::vector<GemmProblem>>& p1,
+                          std::vector<std::vector<GemmProblem>>& p1s, hipStream_t s) {
+  const int nchunks = (int)plan.schunks.size();
+  int64_t smax = 32, pmax = 64;
+  size_t host = 0;
+  for (auto& sc : plan.schunks) {
+    smax = std::max(smax, sc.elems);
+    pmax = std::max(pmax, sc.pelems);
+    sc.host_off = host;
+    host += (size_t)sc.elems * sizeof(double);
+  }
+  plan.slot_bytes = (size_t)smax * sizeof(double);
+  plan.pslot_bytes = (size_t)pmax * 2;
+  plan.slots.reserve(2 * plan.slot_bytes);
+  plan.pslots.reserve(2 * plan.pslot_bytes);
+  BSD_HIP(hipHostMalloc(&plan.pack_host, std::max<size_t>(host, 256), hipHostMallocDefault));
+  plan.pack_bytes = host;
+  auto slot = [&](int k) { return static_cast<char*>(plan.slots.p) + (size_t)(k % 2) * plan.slot_bytes; };
+  auto pslot = [&](int k) { return static_cast<char*>(plan.pslots.p) + (size_t)(k % 2) * plan.pslot_bytes; };
+  auto fix = [&](uint64_t t, int k) -> uint64_t {
+    const uint64_t tag = t >> kTagShift, off = t & ((1ull << kTagShift) - 1);
+    if (tag == 4) return tag_ptr(0, (uint64_t)(uintptr_t)slot(k) + off);
+    if (tag == 5) return tag_ptr(0, (uint64_t)(uintptr_t)pslot(k) + off);
+    return t;
+  };
+  for (int k = 0; k < nchunks; ++k) {
+    for (auto& gp : p1[k])
+      for (auto& sg : gp.segs) sg.B = fix(sg.B, k);
+    for (auto& gp : p1s[k])
+      for (auto& sg : gp.segs) sg.B = fix(sg.B, k);
+    auto& sc = plan.schunks[k];
+    for (auto& t : sc.split) {
+      t.src = fix(t.src, k);
+      t.dst = reinterpret_cast<uint16_t*>(pslot(k) + (uintptr_t)t.dst);
+    }
+    sc.split_dev.reserve(std::max<size_t>(1, sc.split.size()) * sizeof(SplitTask));
+    if (!sc.split.empty())
+      BSD_HIP(hipMemcpy(sc.split_dev.p, sc.split.data(), sc.split.size() * sizeof(SplitTask), hipMemcpyHostToDevice));
+    // fill the pack: gather into slot 0, copy to the host
+    if (!sc.gather.empty()) {
+      DevBuf gl;
+      gl.reserve(sc.gather.size() * sizeof(StreamGather));
+      BSD_HIP(hipMemcpy(gl.p, sc.gather.data(), sc.gather.size() * sizeof(StreamGather), hipMemcpyHostToDevice));
+      hipLaunchKernelGGL(gather_kernel, dim3((unsigned)sc.gather.size()), dim3(256), 0, s,
+                         static_cast<const StreamGather*>(gl.p), reinterpret_cast<double*>(slot(0)));
+      BSD_HIP(hipGetLastError());
+      BSD_HIP(hipMemcpyAsync(static_cast<char*>(plan.pack_host) + sc.host_off, slot(0), (size_t)sc.elems * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+      BSD_HIP(hipStreamSynchronize(s));
+    }
+    sc.gather.clear();
+    sc.gather.shrink_to_fit();
+    sc.where.clear();
+  }
+  BSD_HIP(hipStreamCreateWithFlags(&plan.side, hipStreamNonBlocking));
+  for (int i = 0; i < 2; ++i) {
+    BSD_HIP(hipEventCreateWithFlags(&plan.ev_loaded[i], hipEventDisableTiming));
+    BSD_HIP(hipEventCreateWithFlags(&plan.ev_free[i], hipEventDisableTiming));
+  }
+}
+
 std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, size_t ws_budget,
-                                          hipStream_t s) {
+                                          hipStream_t s, bool stream_r) {
   Block* Lb = get_block(ctx, true, site);
   Block* Rb = get_block(ctx, false, site + 2);
   BSD_CHECK(Lb && Rb, 1, "environment blocks for this site are not built");
   BSD_CHECK(Lb->resident && Rb->resident, 6, "environment block is offloaded");
+  const int64_t kStreamChunkBytes = (int64_t)ctx.stream_chunk_bytes;
   BSD_CHECK(!Rb->normal, 2, "the right block of this site holds normal operators; the product needs the "
                             "complementary set (build it with a smaller right_normal_from)");
   const SiteSet C = make_siteset(site, 2);
@@ -329,7 +407,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   std::vector<VInfo> vinfo(chans.size());
   std::vector<int> chunk_of(chans.size());
   std::vector<int64_t> chunk_size, chunk_psize;
-  int64_t cur = 0, curp = 0;
+  int64_t cur = 0, curp = 0, curr = 0;
   // the workspace budget covers V (float64) and its split planes (bf16)
   const int64_t budget = (int64_t)ws_budget;
   for (size_t ci = 0; ci < chans.size(); ++ci) {
@@ -338,7 +416,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     vi.off.assign(nR, -1);
     vi.src.assign(nR, -1);
     vi.poff.assign(nR, -1);
-    int64_t need = 0, needp = 0;
+    int64_t need = 0, needp = 0, needr = 0;
     if (ch.rkind == 0) {
       for (int r = 0; r < nR; ++r) {
         if (lay.stack_rows[r] == 0) continue;
@@ -352,6 +430,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
         vi.src[r2] = r;
         need += ((int64_t)lay.stack_rows[r] * Rb->basis.dim[r2] + 1) / 2 * 2;
         needp += plane_elems(Rb->basis.dim[r2], lay.stack_prows[r] / 8);
+        needr += (int64_t)rr * ld;
       }
       if (need == 0) {
         cgroups[ci].clear();
@@ -361,12 +440,16 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
       }
     }
     const auto bytes = [](int64_t v, int64_t pl) { return v * (int64_t)sizeof(double) + pl * 2; };
-    if (chunk_size.empty() || (bytes(cur + need, curp + needp) > budget && (cur > 0 || curp > 0))) {
+    // streamed right operators: a chunk also holds at most kStreamChunkBytes of them
+    const bool rfull = stream_r && curr > 0 && (curr + needr) * (int64_t)sizeof(double) > kStreamChunkBytes;
+    if (chunk_size.empty() || rfull || (bytes(cur + need, curp + needp) > budget && (cur > 0 || curp > 0))) {
       chunk_size.push_back(0);
       chunk_psize.push_back(0);
       cur = 0;
       curp = 0;
+      curr = 0;
     }
+    curr += needr;
     for (auto& o : vi.off)
       if (o >= 0) o += cur;
     for (auto& o : vi.poff)
@@ -429,6 +512,10 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   plan->phase2.resize(nchunks);
   double useful = 0.0;
 
+  plan->stream_r = stream_r;
+  if (stream_r) plan->schunks.resize(nchunks);
+  // distinct operator blocks the product reads (algorithmic bytes: each once)
+  std::map<const double*, int64_t> op_blocks;
   std::vector<std::vector<GemmProblem>> p1(nchunks), p1s(nchunks);
   // per chunk, per output psi block: list of segments
   std::vector<std::map<int, GemmProblem>> p2(nchunks), p2s(nchunks);
@@ -443,6 +530,36 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
         int r = vi.src[r2];
         int rr, cc, ld;
         const double* p = ch.rtrans ? Rb->op_block(ch.rkey, r2, &rr, &cc, &ld) : Rb->op_block(ch.rkey, r, &rr, &cc, &ld);
+        op_blocks[p] = (int64_t)rr * cc;
+        // streamed: the block sits in chunk ck's pack (rows x ld float64 at roff),
+        // its planes in the chunk's plane slot (at rpoff), both resolved below
+        int64_t roff = -1, rpoff = -1;
+        if (stream_r) {
+          auto& sc = plan->schunks[ck];
+          auto it = sc.where.find(std::make_pair(p, ch.rtrans));
+          if (it == sc.where.end()) {
+            roff = sc.elems;
+            sc.elems += ((int64_t)rr * ld + 31) / 32 * 32;
+            rpoff = sc.pelems;
+            sc.pelems += plane_elems(Rb->basis.dim[r2], (Rb->basis.dim[r] + 7) / 8);
+            sc.where[std::make_pair(p, ch.rtrans)] = std::make_pair(roff, rpoff);
+            sc.gather.push_back({p, roff, (int64_t)rr * ld});
+            SplitTask t;
+            t.src = tag_ptr(4, (uint64_t)(roff * sizeof(double)));
+            t.lds = ld;
+            t.kmap = nullptr;
+            t.rmap = nullptr;
+            t.dst = reinterpret_cast<uint16_t*>((uintptr_t)(rpoff * 2));
+            t.rows = Rb->basis.dim[r2];
+            t.kcols = Rb->basis.dim[r];
+            t.chunks = (Rb->basis.dim[r] + 7) / 8;
+            t.trans = ch.rtrans ? 1 : 0;
+            sc.split.push_back(t);
+          } else {
+            roff = it->second.first;
+            rpoff = it->second.second;
+          }
+        }
         GemmProblem gp;
         gp.C = tag_ptr(0, (uint64_t)(V + vi.off[r2]));
         gp.ldc = Rb->basis.dim[r2];
@@ -452,7 +569,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
         GSeg sg;
         sg.A = tag_ptr(1, (uint64_t)(lay.stack_off[r] * sizeof(double)));
         sg.lda = Rb->basis.dim[r];
-        sg.B = tag_ptr(0, (uint64_t)p);
+        sg.B = stream_r ? tag_ptr(4, (uint64_t)(roff * sizeof(double))) : tag_ptr(0, (uint64_t)p);
         sg.ldb = ld;
         sg.K = Rb->basis.dim[r];
         sg.flags = ch.rtrans ? 0 : kTransB;   // op(B) = R_b^T
@@ -471,7 +588,8 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
         GSeg sq;
         sq.A = tag_ptr(3, (uint64_t)(psir_off[r] * 2));
         sq.lda = (Rb->basis.dim[r] + 7) / 8;
-        sq.B = tag_ptr(3, (uint64_t)(op_plane(p, ld, ch.rtrans, Rb->basis.dim[r2], Rb->basis.dim[r]) * 2));
+        sq.B = stream_r ? tag_ptr(5, (uint64_t)(rpoff * 2))
+                        : tag_ptr(3, (uint64_t)(op_plane(p, ld, ch.rtrans, Rb->basis.dim[r2], Rb->basis.dim[r]) * 2));
         sq.ldb = (Rb->basis.dim[r] + 7) / 8;
         sq.K = Rb->basis.dim[r];
         sq.flags = 0;
@@ -525,7 +643,10 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
               gp.group = ob.r;   // outputs of one right sector read the same V_b columns
             }
             gp.segs.push_back(sg);
-            if (!o.ident) useful += 2.0 * ob.rows * (double)ob.cols * pb.rows;
+            if (!o.ident) {
+              useful += 2.0 * ob.rows * (double)ob.cols * pb.rows;
+              op_blocks[o.p] = (int64_t)ob.rows * pb.rows;
+            }
             // the same product on split planes: A rows of op(Lambda), B rows of V^T (or psi^T)
             GSeg sq;
             sq.alpha = sg.alpha;
@@ -636,6 +757,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
         sg.B = absolute(sg.B);
       }
   }
+  if (stream_r) prepare_stream_slots(*plan, p1, p1s, s);
   plan->nseg = 0;
   plan->phase1s.resize(nchunks);
   plan->phase2s.resize(nchunks);
@@ -662,6 +784,38 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
       plan->p2_probs[k].push_back(std::move(kv.second));
     }
     for (auto& kv : p2s[k]) plan->p2s_probs[k].push_back(std::move(kv.second));
+  }
+  if (std::getenv("BSDMRG_PLAN_STATS")) {
+    // diagnostic: MFMA work of phase 2 at the kernels' granularity (16 x 16
+    // tiles, K in passes of 32 values) against K padded to single chunks of 8
+    // values, and how many K-segments carry |alpha| = 1
+    double useful2 = 0, pad32 = 0, pad8 = 0, nseg2 = 0, unit = 0, nprob = 0, runs = 0, distinct = 0;
+    for (const auto& v : plan->p2s_probs)
+      for (const auto& gp : v) {
+        nprob += 1;
+        const double mp = (gp.M + 15) / 16 * 16.0, np_ = (gp.N + 15) / 16 * 16.0;
+        double prev = 0;
+        std::vector<double> mags;
+        for (const auto& sg : gp.segs) mags.push_back(std::fabs(sg.alpha));
+        std::sort(mags.begin(), mags.end());
+        distinct += (double)(std::unique(mags.begin(), mags.end()) - mags.begin());
+        for (const auto& sg : gp.segs) {
+          nseg2 += 1;
+          if (sg.flags & kIdentA) continue;
+          useful2 += (double)gp.M * gp.N * sg.K;
+          pad32 += mp * np_ * ((sg.K + 31) / 32 * 32.0);
+          pad8 += mp * np_ * ((sg.K + 7) / 8 * 8.0);
+          if (std::fabs(std::fabs(sg.alpha) - 1.0) == 0.0) unit += 1;
+          if (std::fabs(sg.alpha) != prev) runs += 1;
+          prev = std::fabs(sg.alpha);
+        }
+      }
+    std::fprintf(stderr,
+                 "plan stats: phase-2 problems %.0f, segments %.0f, |alpha|=1 %.1f%%, |alpha| runs %.0f, distinct "
+                 "|alpha| per problem %.1f; MFMA work / useful: K by 32 %.3f, K by 8 %.3f\n",
+                 nprob, nseg2, 100.0 * unit / std::max(1.0, nseg2), runs, distinct / std::max(1.0, nprob),
+                 pad32 / std::max(1.0, useful2),
+                 pad8 / std::max(1.0, useful2));
   }
   // phase-2 tile lists from the kept problem lists (the autotuner rebuilds
   // them); default schedule: wave tiles for every block and a split-K target
@@ -733,6 +887,8 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     BSD_HIP(hipStreamSynchronize(s));
   }
   plan->useful_flops = useful;
+  plan->op_elems = 0;
+  for (const auto& kv : op_blocks) plan->op_elems += kv.second;
   plan->nchannels = (int)chans.size();
   plan->naggs = (int)agg_sk.size();
   return plan;
@@ -909,10 +1065,70 @@ int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream
 }
 
 HpsiPlan::~HpsiPlan() {
+  if (side) (void)hipStreamSynchronize(side);
   for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+  for (int i = 0; i < 2; ++i) {
+    if (ev_loaded[i]) (void)hipEventDestroy(ev_loaded[i]);
+    if (ev_free[i]) (void)hipEventDestroy(ev_free[i]);
+  }
+  if (side) (void)hipStreamDestroy(side);
+  if (pack_host) (void)hipHostFree(pack_host);
+}
+
+static void stream_sleep_fn(void* arg) {
+  const double ms = *static_cast<double*>(arg);
+  delete static_cast<double*>(arg);
+  std::this_thread::sleep_for(std::chrono::microseconds((int64_t)(ms * 1000.0)));
+}
+
+void run_hpsi_stream(HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision,
+                     double delay_ms) {
+  zero_fill(out, plan.lay.n_elems, s);
+  const GBases b = hpsi_bases(plan, psi, out);
+  if (precision != 0) {
+    const SplitTask* tasks = static_cast<const SplitTask*>(plan.split_tasks.p);
+    launch_split_planes(tasks, plan.n_split_psi, b, s);
+  }
+  // both slots free once the work queued so far on s is done
+  for (int i = 0; i < 2; ++i) BSD_HIP(hipEventRecord(plan.ev_free[i], s));
+  const int n = (int)plan.phase1.size();
+  auto load = [&](int k) {
+    const int sl = k % 2;
+    BSD_HIP(hipStreamWaitEvent(plan.side, plan.ev_free[sl], 0));
+    if (delay_ms > 0) BSD_HIP(hipLaunchHostFunc(plan.side, stream_sleep_fn, new double(delay_ms)));
+    const StreamChunk& sc = plan.schunks[k];
+    if (sc.elems > 0)
+      BSD_HIP(hipMemcpyAsync(static_cast<char*>(plan.slots.p) + (size_t)sl * plan.slot_bytes,
+                             static_cast<const char*>(plan.pack_host) + sc.host_off, (size_t)sc.elems * sizeof(double),
+                             hipMemcpyHostToDevice, plan.side));
+    BSD_HIP(hipEventRecord(plan.ev_loaded[sl], plan.side));
+  };
+  if (n > 0) load(0);
+  for (int k = 0; k < n; ++k) {
+    const int sl = k % 2;
+    BSD_HIP(hipStreamWaitEvent(s, plan.ev_loaded[sl], 0));
+    // the next chunk's copy goes into the other slot while this chunk computes
+    if (k + 1 < n) load(k + 1);
+    if (precision == 0) {
+      plan.phase1[k]->launch(b, s, 0);
+      plan.phase2[k]->launch(b, s, 0);
+    } else {
+      const StreamChunk& sc = plan.schunks[k];
+      if (!sc.split.empty())
+        launch_split_planes(static_cast<const SplitTask*>(sc.split_dev.p), (int)sc.split.size(), b, s);
+      plan.phase1s[k]->launch(b, s, precision);
+      plan.phase2s[k]->launch(b, s, precision);
+    }
+    BSD_HIP(hipEventRecord(plan.ev_free[sl], s));
+  }
 }
 
 void run_hpsi_graph(HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision) {
+  if (plan.stream_r) {
+    // streamed products run eagerly (copies on the side stream between chunks)
+    run_hpsi_stream(plan, psi, out, s, precision, plan.stream_delay_ms);
+    return;
+  }
   for (auto& g : plan.graphs)
     if (g.psi == psi && g.out == out && g.precision == precision) {
       BSD_HIP(hipGraphLaunch(g.exec, s));

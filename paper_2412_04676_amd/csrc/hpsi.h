@@ -38,6 +38,20 @@ struct GraphEntry {
   hipGraphExec_t exec;
 };
 
+// streamed right operators: one block of the pack (gathered at prepare time)
+struct StreamGather {
+  const double* src;
+  int64_t off, n;   // destination element offset, elements (rows x ld)
+};
+struct StreamChunk {
+  int64_t elems = 0, pelems = 0;   // float64 pack elements, bf16 plane elements
+  size_t host_off = 0;             // byte offset of the pack in pinned host memory
+  std::map<std::pair<const double*, bool>, std::pair<int64_t, int64_t>> where;   // build only
+  std::vector<StreamGather> gather;                                              // build only
+  std::vector<SplitTask> split;    // planes of the pack (split precision)
+  DevBuf split_dev;
+};
+
 struct HpsiPlan {
   int site = 0, precision = 0;
   std::vector<GraphEntry> graphs;   // captured products, replayed per call
@@ -62,12 +76,31 @@ struct HpsiPlan {
   DevBuf ones, diag, dav_work;
   bool diag_ready = false;
   double useful_flops = 0.0;
+  int64_t op_elems = 0;   // elements of the distinct operator blocks one product reads
+  // streamed right operators (the environment exceeds the device budget): the
+  // right operator blocks of chunk k are copied from pinned host memory into
+  // device slot k % 2 on a side stream while chunk k - 1 computes
+  bool stream_r = false;
+  double stream_delay_ms = 0.0;   // test hook: host sleep before every chunk copy
+  std::vector<StreamChunk> schunks;
+  void* pack_host = nullptr;
+  size_t pack_bytes = 0, slot_bytes = 0, pslot_bytes = 0;
+  DevBuf slots, pslots;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_loaded[2] = {nullptr, nullptr}, ev_free[2] = {nullptr, nullptr};
   size_t nseg = 0;
   int nchannels = 0, naggs = 0;
 };
 
 void build_psi_layout(const Block& Lb, const Block& Rb, const SiteSet& C, const Q& target, PsiLayout& lay);
-std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, size_t ws_budget, hipStream_t s);
+std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, size_t ws_budget, hipStream_t s,
+                                          bool stream_r = false);
+void prepare_stream_slots(HpsiPlan& plan, std::vector<std::vector<GemmProblem>>& p1,
+                          std::vector<std::vector<GemmProblem>>& p1s, hipStream_t s);
+// the streamed product, enqueued directly (copies on the plan's side stream);
+// delay_ms > 0 holds every copy back by a host sleep (test hook)
+void run_hpsi_stream(HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision,
+                     double delay_ms = 0.0);
 // precision: 0 float64, 1 split-bf16 x3, 2 split-bf16 x6 (the plan is shared)
 void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision = 0);
 // the same product replayed from a captured hipGraph (captured on first use for

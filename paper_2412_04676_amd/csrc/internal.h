@@ -214,6 +214,30 @@ struct DevBuf {
   void release();
 };
 
+// Device memory of one renormalized block: one virtual address range whose
+// physical backing can be released and created again at the same address
+// (HIP virtual memory management), so product plans and serializer
+// descriptors that hold pointers into the block stay valid across an offload
+// that frees the memory and the prefetch that restores it.  Devices without
+// virtual memory management get a plain allocation; its address changes when
+// it is created again (stable() reports which).
+struct BlockMem {
+  void* va = nullptr;
+  size_t bytes = 0, reserved = 0, piece = 0;
+  bool vmm = false, mapped = false;
+  std::vector<uint64_t> handles;   // hipMemGenericAllocationHandle_t, one per piece of the range
+  int device = 0;
+  bool map_pieces();               // false (nothing left mapped) if a piece cannot be created or mapped
+  BlockMem() {}
+  BlockMem(const BlockMem&) = delete;
+  BlockMem& operator=(const BlockMem&) = delete;
+  ~BlockMem();
+  void create(size_t bytes);     // reserve and back with physical memory
+  void release_physical();       // frees the physical memory (no work may still use it)
+  void acquire_physical();       // backs the range again (contents undefined)
+  bool stable() const { return vmm; }
+};
+
 struct SerialPlan;
 struct SerialPlanDeleter {
   void operator()(SerialPlan* p) const;
@@ -228,12 +252,17 @@ struct Block {
   Basis basis;               // electrons inside the block
   std::vector<Family> fams;
   std::map<OpKey, OpRef> ops;
-  std::vector<std::unique_ptr<DevBuf>> mem;
+  std::unique_ptr<BlockMem> mem;   // every family's layers, at 256-byte aligned offsets
+  std::vector<size_t> fam_off;     // byte offset of each family in mem
   bool resident = true;
   // serializer descriptors and offload state
   SerialPlanPtr splan;
   hipEvent_t offload_done = nullptr;
-  bool offload_pending = false, release_after = false;
+  hipEvent_t prefetch_done = nullptr;   // recorded on the compute stream after the unpack
+  hipEvent_t last_use = nullptr;        // recorded after the last asynchronous work that reads the block
+  bool offload_pending = false, release_after = false, prefetch_pending = false;
+  void mark_use(hipStream_t s);         // record last_use on s
+  void quiesce();                       // wait for every recorded use, copy and unpack
   ~Block();
   const double* op_block(const OpKey& k, int in_idx, int* rows, int* cols, int* ld) const;
   size_t device_bytes() const;
@@ -415,11 +444,19 @@ struct FamilyView {
 };
 size_t serialized_size(const std::vector<FamilyView>& fams);
 // device descriptors of a set of families (built once; synchronizes s)
-SerialPlanPtr serial_plan(const std::vector<FamilyView>& fams, hipStream_t s);
+SerialPlanPtr serial_plan(const std::vector<FamilyView>& fams, hipStream_t s, bool zero_pads = false);
 size_t serial_bytes(const SerialPlan& p);
 void serial_pack(const SerialPlan& p, void* dst, size_t cap, hipStream_t s);          // stream-ordered
 void serial_unpack(const SerialPlan& p, const void* src, size_t bytes, hipStream_t s);  // stream-ordered
 int serial_status(const SerialPlan& p, hipStream_t s);  // synchronizes s; 0 or 7 (corrupt)
 int validate_stream_host(const std::vector<FamilyView>& fams, const void* src, size_t bytes);
+// segmented, order-free form through a small double-buffered staging area
+size_t serial_segments_size(const SerialPlan& d, size_t staging_bytes, int* nseg);
+size_t serial_pack_segments(const SerialPlan& d, void* staging, size_t staging_bytes, void* host, size_t cap,
+                            int* nseg, hipStream_t compute, hipStream_t side);   // synchronizing
+int serial_unpack_segments(const SerialPlan& d, const void* host, size_t bytes, void* staging, size_t staging_bytes,
+                           hipStream_t compute, hipStream_t side);   // synchronizing; 0 or 7 (nothing written)
+void set_copy_grid(int workgroups);   // 0: one workgroup per copy task
+
 
 }  // namespace bsd

@@ -16,6 +16,7 @@
 #include "internal.h"
 
 #include <algorithm>
+#include <mutex>
 
 namespace bsd {
 
@@ -148,14 +149,17 @@ write_meta_kernel(const FamDesc* __restrict__ fams, const BlkDesc* __restrict__ 
   }
 }
 
+// Workgroups take copy tasks in a grid-stride loop: the bytes written do not
+// depend on the grid size (a test checks 1, 7 and 1024 workgroups).
 template <bool PACK>
 __global__ void __launch_bounds__(256)
-copy_kernel(const CopyTask* __restrict__ tasks, const FamDesc* __restrict__ fams,
+copy_kernel(const CopyTask* __restrict__ tasks, int ntasks, const FamDesc* __restrict__ fams,
             const BlkDesc* __restrict__ blks, const int64_t* __restrict__ elem_off,
             const int64_t* __restrict__ layer_elems, const int64_t* __restrict__ payload_off,
-            unsigned char* __restrict__ stream, const int* __restrict__ status) {
+            unsigned char* __restrict__ stream, const int* __restrict__ status, int zero_pads) {
   if (!PACK && *status != 0) return;
-  const CopyTask t = tasks[blockIdx.x];
+  for (int ti = blockIdx.x; ti < ntasks; ti += gridDim.x) {
+  const CopyTask t = tasks[ti];
   const FamDesc f = fams[t.fam];
   double* sbase = reinterpret_cast<double*>(stream + payload_off[t.fam]) + (int64_t)t.layer * layer_elems[t.fam];
   double* lbase = f.base + (int64_t)t.layer * f.layer_stride;
@@ -171,7 +175,25 @@ copy_kernel(const CopyTask* __restrict__ tasks, const FamDesc* __restrict__ fams
       if (PACK) s[e] = d[r * bd.ld + c];
       else d[r * bd.ld + c] = s[e];
     }
+    if (!PACK && zero_pads && bd.ld > bd.cols) {
+      // row padding is not in the stream: for the library's own blocks the
+      // unpack writes it as zeros, so a block restored into fresh memory
+      // equals the packed one entirely (caller-described families keep theirs)
+      const int pad = bd.ld - bd.cols;
+      const int64_t np = (int64_t)nr * pad;
+      for (int64_t e = threadIdx.x; e < np; e += blockDim.x) {
+        const int64_t r = e / pad, c = bd.cols + (e - r * pad);
+        d[r * bd.ld + c] = 0.0;
+      }
+    }
   }
+  }
+}
+
+// workgroups of the copy launches (0: one per copy task)
+static int g_copy_grid = 0;
+static unsigned copy_grid(int ntasks) {
+  return (unsigned)(g_copy_grid > 0 ? std::min(g_copy_grid, ntasks) : ntasks);
 }
 
 // checks the stream's header and tables against the expected skeletons
@@ -231,8 +253,46 @@ uint64_t magic_word() {
 struct SerialPlan {
   DevBuf fams, blks, tasks, elem_off, layer_elems, payload_off, status;
   int nf = 0, nb = 0, ntasks = 0;
+  int zero_pads = 0;   // unpack writes row padding as zeros (library-owned blocks)
   size_t bytes = 0;
+  // host copies for the segmented form: per family its layer count, layer
+  // elements, payload offset in the one-stream layout, skeleton fingerprint and
+  // the first copy task of every layer (tasks are emitted family by family,
+  // layer by layer, so a layer range is a contiguous task range)
+  std::vector<int> h_layers;
+  std::vector<int64_t> h_layer_elems, h_payload_off;
+  std::vector<uint64_t> h_tag, h_print;
+  std::vector<std::vector<int>> h_task_first;
 };
+
+// copy tasks of one family: large blocks in row slices, small blocks in runs
+template <class Emit>
+static void family_tasks(int f, int n_layers, int nbk, const int* rows, const int* cols, Emit&& emit) {
+  for (int l = 0; l < n_layers; ++l) {
+    int b = 0;
+    while (b < nbk) {
+      int64_t n = (int64_t)rows[b] * cols[b];
+      if (n >= kCopyElems) {
+        int rows_per = std::max(1, (int)(kCopyElems / std::max(1, cols[b])));
+        for (int r0 = 0; r0 < rows[b]; r0 += rows_per) emit(CopyTask{f, l, b, b + 1, r0, std::min(rows_per, rows[b] - r0)});
+        ++b;
+      } else {
+        int b1 = b;
+        int64_t acc = 0;
+        while (b1 < nbk && acc + (int64_t)rows[b1] * cols[b1] < kCopyElems) {
+          acc += (int64_t)rows[b1] * cols[b1];
+          ++b1;
+        }
+        if (b1 == b) b1 = b + 1;
+        if (b1 == b + 1)
+          emit(CopyTask{f, l, b, b1, 0, rows[b]});
+        else
+          emit(CopyTask{f, l, b, b1, 0, 0});
+        b = b1;
+      }
+    }
+  }
+}
 
 static void upload(const std::vector<FamilyView>& fv, SerialPlan& d, hipStream_t s) {
   std::vector<FamDesc> fd;
@@ -262,32 +322,44 @@ static void upload(const std::vector<FamilyView>& fv, SerialPlan& d, hipStream_t
       y.src_off = v.off[b];
       bd.push_back(y);
     }
-    // copy tasks: large blocks in row slices, small blocks in runs
-    for (int l = 0; l < v.n_layers; ++l) {
-      int b = 0;
-      const int nbk = (int)v.bq.size();
-      while (b < nbk) {
-        int64_t n = (int64_t)v.rows[b] * v.cols[b];
-        if (n >= kCopyElems) {
-          int rows_per = std::max(1, (int)(kCopyElems / std::max(1, v.cols[b])));
-          for (int r0 = 0; r0 < v.rows[b]; r0 += rows_per)
-            tasks.push_back({(int)f, l, b, b + 1, r0, std::min(rows_per, v.rows[b] - r0)});
-          ++b;
-        } else {
-          int b1 = b;
-          int64_t acc = 0;
-          while (b1 < nbk && acc + (int64_t)v.rows[b1] * v.cols[b1] < kCopyElems) {
-            acc += (int64_t)v.rows[b1] * v.cols[b1];
-            ++b1;
-          }
-          if (b1 == b) b1 = b + 1;
-          if (b1 == b + 1)
-            tasks.push_back({(int)f, l, b, b1, 0, v.rows[b]});
-          else
-            tasks.push_back({(int)f, l, b, b1, 0, 0});
-          b = b1;
-        }
+    std::vector<int> first(v.n_layers + 1, (int)tasks.size());
+    family_tasks((int)f, v.n_layers, (int)v.bq.size(), v.rows.data(), v.cols.data(), [&](const CopyTask& t) {
+      tasks.push_back(t);
+      first[t.layer + 1] = (int)tasks.size();
+    });
+    for (int l = 1; l <= v.n_layers; ++l) first[l] = std::max(first[l], first[l - 1]);
+    int64_t le = 0;
+    // FNV-1a over the skeleton: dq, layer count, every block's sector and shape
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](int64_t x) {
+      for (int k = 0; k < 8; ++k) {
+        h ^= (uint64_t)((x >> (8 * k)) & 0xff);
+        h *= 1099511628211ull;
       }
+    };
+    mix(v.dq.a);
+    mix(v.dq.b);
+    mix(v.n_layers);
+    for (size_t b = 0; b < v.bq.size(); ++b) {
+      le += (int64_t)v.rows[b] * v.cols[b];
+      mix(v.bq[b].a);
+      mix(v.bq[b].b);
+      mix(v.rows[b]);
+      mix(v.cols[b]);
+    }
+    d.h_layers.push_back(v.n_layers);
+    d.h_layer_elems.push_back(le);
+    d.h_tag.push_back(v.tag);
+    d.h_print.push_back(h);
+    d.h_task_first.push_back(std::move(first));
+  }
+  {
+    int64_t nbt = 0;
+    for (auto& v : fv) nbt += (int64_t)v.bq.size();
+    int64_t off = align256(64 + 64 * (int64_t)fv.size() + 32 * nbt);
+    for (size_t f = 0; f < fv.size(); ++f) {
+      d.h_payload_off.push_back(off);
+      off += align256((int64_t)d.h_layers[f] * d.h_layer_elems[f] * 8);
     }
   }
   d.nf = (int)fd.size();
@@ -332,8 +404,9 @@ size_t serialized_size(const std::vector<FamilyView>& fams) {
 
 void SerialPlanDeleter::operator()(SerialPlan* p) const { delete p; }
 
-SerialPlanPtr serial_plan(const std::vector<FamilyView>& fams, hipStream_t s) {
+SerialPlanPtr serial_plan(const std::vector<FamilyView>& fams, hipStream_t s, bool zero_pads) {
   SerialPlanPtr p(new SerialPlan());
+  p->zero_pads = zero_pads ? 1 : 0;
   p->bytes = serialized_size(fams);
   upload(fams, *p, s);
   return p;
@@ -351,10 +424,10 @@ void serial_pack(const SerialPlan& d, void* dst, size_t cap, hipStream_t s) {
                      (unsigned char*)dst, magic_word());
   BSD_HIP(hipGetLastError());
   if (d.ntasks > 0)
-    hipLaunchKernelGGL((copy_kernel<true>), dim3(d.ntasks), dim3(256), 0, s, (const CopyTask*)d.tasks.p,
-                       (const FamDesc*)d.fams.p, (const BlkDesc*)d.blks.p, (const int64_t*)d.elem_off.p,
+    hipLaunchKernelGGL((copy_kernel<true>), dim3(copy_grid(d.ntasks)), dim3(256), 0, s, (const CopyTask*)d.tasks.p,
+                       d.ntasks, (const FamDesc*)d.fams.p, (const BlkDesc*)d.blks.p, (const int64_t*)d.elem_off.p,
                        (const int64_t*)d.layer_elems.p, (const int64_t*)d.payload_off.p,
-                       (unsigned char*)dst, (const int*)nullptr);
+                       (unsigned char*)dst, (const int*)nullptr, 0);
   BSD_HIP(hipGetLastError());
 }
 
@@ -368,10 +441,10 @@ void serial_unpack(const SerialPlan& d, const void* src, size_t bytes, hipStream
                      (const unsigned char*)src, (int64_t)bytes, magic_word(), (int*)d.status.p);
   BSD_HIP(hipGetLastError());
   if (d.ntasks > 0)
-    hipLaunchKernelGGL((copy_kernel<false>), dim3(d.ntasks), dim3(256), 0, s, (const CopyTask*)d.tasks.p,
-                       (const FamDesc*)d.fams.p, (const BlkDesc*)d.blks.p, (const int64_t*)d.elem_off.p,
+    hipLaunchKernelGGL((copy_kernel<false>), dim3(copy_grid(d.ntasks)), dim3(256), 0, s, (const CopyTask*)d.tasks.p,
+                       d.ntasks, (const FamDesc*)d.fams.p, (const BlkDesc*)d.blks.p, (const int64_t*)d.elem_off.p,
                        (const int64_t*)d.layer_elems.p, (const int64_t*)d.payload_off.p,
-                       (unsigned char*)const_cast<void*>(src), (const int*)d.status.p);
+                       (unsigned char*)const_cast<void*>(src), (const int*)d.status.p, d.zero_pads);
   BSD_HIP(hipGetLastError());
 }
 
@@ -430,5 +503,190 @@ int validate_stream_host(const std::vector<FamilyView>& fams, const void* src, s
   }
   return poff == (int64_t)bytes ? 0 : 7;
 }
+
+// ---------------------------------------------------------------- segments
+// The synchronous small-buffer form of Sec. III.A (strategy 1, Fig. 4b) with
+// self-contained packages (Sec. III.B.3): a block's families are cut into
+// segments of whole layers that fit half of a small device staging area; each
+// segment is packed into one half while the other half is copied to pinned
+// host memory, and carries a header that says where its layers belong, so a
+// reader can take the segments in any order.  Segment layout (little-endian):
+//   header 256 B: magic "BSDSEG01", u64 owner (the block's family tags without
+//   the family index), u32 family, u32 families in the block, u32 first layer,
+//   u32 layers, u64 payload bytes, u64 skeleton fingerprint of the family,
+//   u64 segment index, zero to 256 B;
+//   payload: the layers, blocks compact row-major, zero padded to 256 B.
+namespace {
+struct SegHeader {
+  uint64_t magic, owner;
+  uint32_t fam, nfam, layer0, nlayers;
+  uint64_t payload, print, index;
+};
+constexpr int64_t kSegHeader = 256;
+uint64_t seg_magic() {
+  uint64_t m;
+  std::memcpy(&m, "BSDSEG01", 8);
+  return m;
+}
+uint64_t owner_of(const SerialPlan& d) { return d.nf ? (d.h_tag[0] & ~((1ull << 20) - 1)) : 0; }
+
+struct SegPiece {
+  int fam, l0, nl;
+  int64_t bytes;
+};
+std::vector<SegPiece> seg_pieces(const SerialPlan& d, size_t half) {
+  std::vector<SegPiece> out;
+  for (int f = 0; f < d.nf; ++f) {
+    const int64_t lb = d.h_layer_elems[f] * 8;
+    if (lb == 0 || d.h_layers[f] == 0) continue;
+    BSD_CHECK(lb <= (int64_t)half, 4, "half the staging area is smaller than one layer of a family");
+    const int per = (int)std::max<int64_t>(1, (int64_t)half / lb);
+    for (int l0 = 0; l0 < d.h_layers[f]; l0 += per) {
+      const int nl = std::min(per, d.h_layers[f] - l0);
+      out.push_back({f, l0, nl, (int64_t)nl * lb});
+    }
+  }
+  return out;
+}
+}  // namespace
+
+size_t serial_segments_size(const SerialPlan& d, size_t staging_bytes, int* nseg) {
+  const size_t half = staging_bytes / 2 / 256 * 256;
+  auto pcs = seg_pieces(d, half);
+  size_t total = 0;
+  for (auto& p : pcs) total += kSegHeader + align256(p.bytes);
+  if (nseg) *nseg = (int)pcs.size();
+  return total;
+}
+
+static void launch_copy_range(const SerialPlan& d, bool pack, int fam, int l0, int nl, unsigned char* buf,
+                              const int* zero_status, hipStream_t s) {
+  const int t0 = d.h_task_first[fam][l0], t1 = d.h_task_first[fam][l0 + nl];
+  if (t1 <= t0) return;
+  // the kernel adds the family's payload offset and layer offset of the
+  // one-stream layout; this base makes that land in the segment buffer
+  unsigned char* base = buf - (d.h_payload_off[fam] + (int64_t)l0 * d.h_layer_elems[fam] * 8);
+  const CopyTask* tasks = (const CopyTask*)d.tasks.p + t0;
+  if (pack)
+    hipLaunchKernelGGL((copy_kernel<true>), dim3(copy_grid(t1 - t0)), dim3(256), 0, s, tasks, t1 - t0,
+                       (const FamDesc*)d.fams.p, (const BlkDesc*)d.blks.p, (const int64_t*)d.elem_off.p,
+                       (const int64_t*)d.layer_elems.p, (const int64_t*)d.payload_off.p, base, (const int*)nullptr, 0);
+  else
+    hipLaunchKernelGGL((copy_kernel<false>), dim3(copy_grid(t1 - t0)), dim3(256), 0, s, tasks, t1 - t0,
+                       (const FamDesc*)d.fams.p, (const BlkDesc*)d.blks.p, (const int64_t*)d.elem_off.p,
+                       (const int64_t*)d.layer_elems.p, (const int64_t*)d.payload_off.p, base, zero_status,
+                       d.zero_pads);
+  BSD_HIP(hipGetLastError());
+}
+
+size_t serial_pack_segments(const SerialPlan& d, void* staging, size_t staging_bytes, void* host, size_t cap,
+                            int* nseg, hipStream_t compute, hipStream_t side) {
+  BSD_CHECK(((uintptr_t)staging % 256) == 0, 1, "staging must be 256-byte aligned");
+  const size_t half = staging_bytes / 2 / 256 * 256;
+  BSD_CHECK(half >= 256, 4, "staging area below 512 bytes");
+  auto pcs = seg_pieces(d, half);
+  size_t total = 0;
+  for (auto& p : pcs) total += kSegHeader + align256(p.bytes);
+  BSD_CHECK(cap >= total, 4, "host buffer smaller than the segmented size");
+  scan(const_cast<SerialPlan&>(d), compute);
+  hipEvent_t packed[2], freed[2];
+  for (int i = 0; i < 2; ++i) {
+    BSD_HIP(hipEventCreateWithFlags(&packed[i], hipEventDisableTiming));
+    BSD_HIP(hipEventCreateWithFlags(&freed[i], hipEventDisableTiming));
+    BSD_HIP(hipEventRecord(freed[i], side));
+  }
+  unsigned char* h = static_cast<unsigned char*>(host);
+  size_t at = 0;
+  for (size_t i = 0; i < pcs.size(); ++i) {
+    const SegPiece& p = pcs[i];
+    const int b = (int)(i % 2);
+    unsigned char* buf = static_cast<unsigned char*>(staging) + (size_t)b * half;
+    BSD_HIP(hipStreamWaitEvent(compute, freed[b], 0));
+    launch_copy_range(d, true, p.fam, p.l0, p.nl, buf, nullptr, compute);
+    BSD_HIP(hipEventRecord(packed[b], compute));
+    SegHeader hd{seg_magic(), owner_of(d), (uint32_t)p.fam, (uint32_t)d.nf, (uint32_t)p.l0, (uint32_t)p.nl,
+                 (uint64_t)p.bytes, d.h_print[p.fam], (uint64_t)i};
+    std::memset(h + at, 0, kSegHeader);
+    std::memcpy(h + at, &hd, sizeof(hd));
+    const int64_t padded = align256(p.bytes);
+    if (padded > p.bytes) std::memset(h + at + kSegHeader + p.bytes, 0, padded - p.bytes);
+    BSD_HIP(hipStreamWaitEvent(side, packed[b], 0));
+    BSD_HIP(hipMemcpyAsync(h + at + kSegHeader, buf, (size_t)p.bytes, hipMemcpyDeviceToHost, side));
+    BSD_HIP(hipEventRecord(freed[b], side));
+    at += kSegHeader + padded;
+  }
+  BSD_HIP(hipStreamSynchronize(side));
+  BSD_HIP(hipStreamSynchronize(compute));
+  for (int i = 0; i < 2; ++i) {
+    (void)hipEventDestroy(packed[i]);
+    (void)hipEventDestroy(freed[i]);
+  }
+  if (nseg) *nseg = (int)pcs.size();
+  return total;
+}
+
+int serial_unpack_segments(const SerialPlan& d, const void* host, size_t bytes, void* staging, size_t staging_bytes,
+                           hipStream_t compute, hipStream_t side) {
+  BSD_CHECK(((uintptr_t)staging % 256) == 0, 1, "staging must be 256-byte aligned");
+  const size_t half = staging_bytes / 2 / 256 * 256;
+  // read and check every header first: nothing is written unless the
+  // segments cover every layer of every family exactly once
+  const unsigned char* h = static_cast<const unsigned char*>(host);
+  std::vector<std::pair<size_t, SegHeader>> segs;
+  std::vector<std::vector<char>> seen(d.nf);
+  for (int f = 0; f < d.nf; ++f) seen[f].assign(d.h_layers[f], 0);
+  size_t at = 0;
+  while (at < bytes) {
+    if (bytes - at < (size_t)kSegHeader) return 7;
+    SegHeader hd;
+    std::memcpy(&hd, h + at, sizeof(hd));
+    if (hd.magic != seg_magic() || hd.owner != owner_of(d) || hd.nfam != (uint32_t)d.nf || hd.fam >= (uint32_t)d.nf)
+      return 7;
+    const int f = (int)hd.fam;
+    if (hd.print != d.h_print[f] || hd.nlayers == 0 || (int64_t)hd.layer0 + hd.nlayers > d.h_layers[f] ||
+        hd.payload != (uint64_t)((int64_t)hd.nlayers * d.h_layer_elems[f] * 8) || hd.payload > half)
+      return 7;
+    const size_t len = kSegHeader + align256((int64_t)hd.payload);
+    if (bytes - at < len) return 7;
+    for (uint32_t l = hd.layer0; l < hd.layer0 + hd.nlayers; ++l) {
+      if (seen[f][l]) return 7;
+      seen[f][l] = 1;
+    }
+    segs.push_back({at, hd});
+    at += len;
+  }
+  for (int f = 0; f < d.nf; ++f)
+    if (d.h_layer_elems[f] > 0)
+      for (char c : seen[f])
+        if (!c) return 7;
+  scan(const_cast<SerialPlan&>(d), compute);
+  BSD_HIP(hipMemsetAsync(d.status.p, 0, sizeof(int), compute));
+  hipEvent_t loaded[2], freed[2];
+  for (int i = 0; i < 2; ++i) {
+    BSD_HIP(hipEventCreateWithFlags(&loaded[i], hipEventDisableTiming));
+    BSD_HIP(hipEventCreateWithFlags(&freed[i], hipEventDisableTiming));
+    BSD_HIP(hipEventRecord(freed[i], compute));
+  }
+  for (size_t i = 0; i < segs.size(); ++i) {
+    const SegHeader& hd = segs[i].second;
+    const int b = (int)(i % 2);
+    unsigned char* buf = static_cast<unsigned char*>(staging) + (size_t)b * half;
+    BSD_HIP(hipStreamWaitEvent(side, freed[b], 0));
+    BSD_HIP(hipMemcpyAsync(buf, h + segs[i].first + kSegHeader, (size_t)hd.payload, hipMemcpyHostToDevice, side));
+    BSD_HIP(hipEventRecord(loaded[b], side));
+    BSD_HIP(hipStreamWaitEvent(compute, loaded[b], 0));
+    launch_copy_range(d, false, (int)hd.fam, (int)hd.layer0, (int)hd.nlayers, buf, (const int*)d.status.p, compute);
+    BSD_HIP(hipEventRecord(freed[b], compute));
+  }
+  BSD_HIP(hipStreamSynchronize(compute));
+  BSD_HIP(hipStreamSynchronize(side));
+  for (int i = 0; i < 2; ++i) {
+    (void)hipEventDestroy(loaded[i]);
+    (void)hipEventDestroy(freed[i]);
+  }
+  return 0;
+}
+
+void set_copy_grid(int workgroups) { g_copy_grid = std::max(0, workgroups); }
 
 }  // namespace bsd

@@ -27,14 +27,21 @@ namespace bsd {
 // pass after the rotation angles: a wave takes the two rows (p1, q1) of pair
 // k1 and its lanes the column pairs k2 (accesses stay inside two rows), and
 // the eigenvector rows p, q rotate with lanes along the row.  No divisions.
+constexpr int kJacobiMaxDim = 4096;   // 2048 rotations per round: 48 KiB of LDS
+
 __global__ void __launch_bounds__(1024)
 jacobi_kernel(const int64_t* __restrict__ goff, const int* __restrict__ dims, double* __restrict__ G,
               double* __restrict__ V, int max_sweeps) {
   const int m = dims[blockIdx.x];
   double* A = G + goff[blockIdx.x];
   double* Z = V + goff[blockIdx.x];
-  __shared__ double cs[512], sn[512];
-  __shared__ int pp[512], qq[512];
+  // rotation of every pair of one round: m / 2 entries of (c, s, p, q) in LDS
+  extern __shared__ double lds_rot[];
+  const int hmax = kJacobiMaxDim / 2;
+  double* cs = lds_rot;
+  double* sn = lds_rot + hmax;
+  int* pp = reinterpret_cast<int*>(lds_rot + 2 * hmax);
+  int* qq = pp + hmax;
   __shared__ double red[2][32];
   const int t = threadIdx.x, nt = blockDim.x;
   const int wave = t >> 6, lane = t & 63, nw = nt >> 6;
@@ -183,7 +190,7 @@ TruncResult truncate_psi(Ctx& ctx, const HpsiPlan& plan, const double* psi, int 
     }
     const int n = left_to_right ? x.nr : x.nc;
     x.m = n + (n & 1);
-    BSD_CHECK(x.m <= 1024, 3, "middle sector larger than 1024 states");
+    BSD_CHECK(x.m <= kJacobiMaxDim, 3, "middle sector larger than 4096 states");
   }
   int64_t gtot = 0;
   for (auto& x : secs) {
@@ -267,8 +274,9 @@ TruncResult truncate_psi(Ctx& ctx, const HpsiPlan& plan, const double* psi, int 
     BSD_HIP(hipMemcpy(dg.p, goffs.data(), goffs.size() * sizeof(int64_t), hipMemcpyHostToDevice));
     BSD_HIP(hipMemcpy(dd.p, dims.data(), dims.size() * sizeof(int), hipMemcpyHostToDevice));
     if (!secs.empty())
-      hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)secs.size()), dim3(1024), 0, s, (const int64_t*)dg.p,
-                         (const int*)dd.p, G, V, 40);
+      hipLaunchKernelGGL(jacobi_kernel, dim3((unsigned)secs.size()), dim3(1024),
+                         (size_t)(kJacobiMaxDim / 2) * (2 * sizeof(double) + 2 * sizeof(int)), s,
+                         (const int64_t*)dg.p, (const int*)dd.p, G, V, 40);
     BSD_HIP(hipGetLastError());
     BSD_HIP(hipStreamSynchronize(s));
   }

@@ -126,7 +126,7 @@ def test_block_offload_release_prefetch_bit_identical():
     for side, bond in ((B.LEFT, site), (B.RIGHT, site + 2)):
         n = B.bsdmrg_serialized_size(ctx, side, bond)
         staging = torch.empty(n // 8 + 32, dtype=torch.float64, device="cuda")
-        pinned = torch.empty(n // 8 + 32, dtype=torch.float64).pin_memory()
+        pinned = torch.empty(n // 8 + 32, dtype=torch.float64, pin_memory=True)
         comp, sidestream = torch.cuda.current_stream(), torch.cuda.Stream()
         assert B.bsdmrg_block_bytes(ctx, side, bond) > 0
         B.bsdmrg_offload(ctx, side, bond, staging, pinned, n, 1, comp, sidestream)
@@ -177,4 +177,223 @@ def test_davidson_bit_identical_with_offload_in_flight():
     say(f"  E {ea:.12f} vs {eb:.12f}, iterations {ita} vs {itb}")
     assert ea == eb and ita == itb and ra == rb
     assert torch.equal(xa, xb)
+    B.bsdmrg_destroy(ctx)
+
+
+def _offloaded_copies(B, ctx, site, comp, side):
+    """Pinned host copies of both environment blocks (offload without release)."""
+    import torch
+    out = {}
+    for sd, bond in ((B.LEFT, site), (B.RIGHT, site + 2)):
+        n = B.bsdmrg_serialized_size(ctx, sd, bond)
+        st = torch.empty(n // 8 + 32, dtype=torch.float64, device="cuda")
+        pin = torch.empty(n // 8 + 32, dtype=torch.float64, pin_memory=True)
+        B.bsdmrg_offload(ctx, sd, bond, st, pin, n, 0, comp, side)
+        B.bsdmrg_offload_wait(ctx, sd, bond)
+        out[(sd, bond)] = (n, pin)
+    return out
+
+
+def test_release_and_prefetch_keep_product_plans():
+    """Offload with release returns the block's physical memory; the prefetch
+    restores it at the same addresses, so the prepared product is replayed as
+    it was (no new Tables step) and gives the same result bit for bit."""
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    L, na, nb, D, site = 10, 5, 5, 60, 4
+    say("release + prefetch keep plans")
+    ctx, h, eri, dims, T = build_system(L, na, nb, D, site)
+    lay = B.bsdmrg_psi_layout(ctx, site)
+    x = torch.from_numpy(B.psi_to_flat(psi_for(dims, site, 3), lay)).cuda()
+    y0 = torch.empty_like(x)
+    for prec in (B.FP64, B.BF16X6):
+        B.bsdmrg_hpsi(ctx, site, x, y0, prec)
+    B.bsdmrg_hpsi(ctx, site, x, y0)
+    torch.cuda.synchronize()
+    tables = B.bsdmrg_stats(ctx)["seconds"]["Tables"]
+    comp, side = torch.cuda.current_stream(), torch.cuda.Stream()
+    copies = _offloaded_copies(B, ctx, site, comp, side)
+    for (sd, bond), (n, pin) in copies.items():
+        st = torch.empty(n // 8 + 32, dtype=torch.float64, device="cuda")
+        B.bsdmrg_offload(ctx, sd, bond, st, pin, n, 1, comp, side)
+        B.bsdmrg_offload_wait(ctx, sd, bond)
+        assert B.bsdmrg_block_bytes(ctx, sd, bond) == 0
+        B.bsdmrg_prefetch(ctx, sd, bond, pin, st, n, comp, side)
+        B.bsdmrg_prefetch_wait(ctx, sd, bond)
+    y1 = torch.empty_like(x)
+    B.bsdmrg_hpsi(ctx, site, x, y1)
+    torch.cuda.synchronize()
+    assert torch.equal(y0, y1)
+    st = B.bsdmrg_stats(ctx)
+    say(f"  Tables {tables:.3f} s -> {st['seconds']['Tables']:.3f} s; IO {st['seconds']['IO']:.3f} s")
+    assert st["seconds"]["Tables"] == tables
+    B.bsdmrg_destroy(ctx)
+
+
+def test_prefetches_sharing_one_staging_buffer():
+    """Two prefetches through one staging buffer with products queued between
+    them: the second copy waits for the first unpack, so both blocks come back
+    intact and every product equals the reference bit for bit."""
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    L, na, nb, D, site = 10, 5, 5, 60, 4
+    say("two prefetches, one staging buffer")
+    ctx, h, eri, dims, T = build_system(L, na, nb, D, site)
+    lay = B.bsdmrg_psi_layout(ctx, site)
+    x = torch.from_numpy(B.psi_to_flat(psi_for(dims, site, 4), lay)).cuda()
+    ref = torch.empty_like(x)
+    B.bsdmrg_hpsi(ctx, site, x, ref)
+    torch.cuda.synchronize()
+    comp, side = torch.cuda.current_stream(), torch.cuda.Stream()
+    copies = _offloaded_copies(B, ctx, site, comp, side)
+    nmax = max(n for n, _ in copies.values())
+    staging = torch.empty(nmax // 8 + 32, dtype=torch.float64, device="cuda")
+    (nl, pin_l), (nr, pin_r) = copies[(B.LEFT, site)], copies[(B.RIGHT, site + 2)]
+    outs = [torch.empty_like(x) for _ in range(3)]
+    for rep in range(2):
+        # the left block's memory is returned, so only its unpack restores it
+        B.bsdmrg_offload(ctx, B.LEFT, site, staging, pin_l, nl, 1, comp, side)
+        B.bsdmrg_offload_wait(ctx, B.LEFT, site)
+        B.bsdmrg_prefetch(ctx, B.LEFT, site, pin_l, staging, nl, comp, side)
+        B.bsdmrg_hpsi(ctx, site, x, outs[0], B.FP64, comp)
+        # the right block's stream goes through the same staging buffer
+        B.bsdmrg_prefetch(ctx, B.RIGHT, site + 2, pin_r, staging, nr, comp, side)
+        B.bsdmrg_hpsi(ctx, site, x, outs[1], B.FP64, comp)
+        torch.cuda.synchronize()
+        for o in outs[:2]:
+            assert torch.equal(o, ref), rep
+    B.bsdmrg_destroy(ctx)
+
+
+def test_forced_side_delay_is_counted_as_exposed_io():
+    """With a host delay queued before each side-stream copy, the blocking
+    waits (fetching) see it, the statistics count it as exposed IO, and the
+    data still arrive intact."""
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    L, na, nb, D, site = 8, 4, 4, 40, 3
+    say("forced side delay")
+    ctx, h, eri, dims, T = build_system(L, na, nb, D, site)
+    lay = B.bsdmrg_psi_layout(ctx, site)
+    x = torch.from_numpy(B.psi_to_flat(psi_for(dims, site, 5), lay)).cuda()
+    ref = torch.empty_like(x)
+    B.bsdmrg_hpsi(ctx, site, x, ref)
+    torch.cuda.synchronize()
+    comp, side = torch.cuda.current_stream(), torch.cuda.Stream()
+    n = B.bsdmrg_serialized_size(ctx, B.LEFT, site)
+    st = torch.empty(n // 8 + 32, dtype=torch.float64, device="cuda")
+    pin = torch.empty(n // 8 + 32, dtype=torch.float64, pin_memory=True)
+    B.bsdmrg_stats(ctx, reset=True)
+    B.bsdmrg_set_side_delay(ctx, 300.0)
+    B.bsdmrg_offload(ctx, B.LEFT, site, st, pin, n, 1, comp, side)
+    w1 = B.bsdmrg_offload_wait(ctx, B.LEFT, site)
+    B.bsdmrg_prefetch(ctx, B.LEFT, site, pin, st, n, comp, side)
+    w2 = B.bsdmrg_prefetch_wait(ctx, B.LEFT, site)
+    B.bsdmrg_set_side_delay(ctx, 0.0)
+    y = torch.empty_like(x)
+    B.bsdmrg_hpsi(ctx, site, x, y)
+    torch.cuda.synchronize()
+    s = B.bsdmrg_stats(ctx)
+    say(f"  waited {w1:.3f} s and {w2:.3f} s, exposed IO {s['io_exposed_s']:.3f} s")
+    assert w1 >= 0.25 and w2 >= 0.25
+    assert s["io_exposed_s"] >= w1 + w2 - 1e-9
+    assert torch.equal(y, ref)
+    B.bsdmrg_destroy(ctx)
+
+
+def _split_segments(raw):
+    """Segments of a segmented stream: (header, payload incl. padding) byte arrays."""
+    out, at = [], 0
+    while at < len(raw):
+        payload = int(np.frombuffer(raw[at + 32:at + 40].tobytes(), dtype=np.uint64)[0])
+        ln = 256 + (payload + 255) // 256 * 256
+        out.append(raw[at:at + ln].copy())
+        at += ln
+    return out
+
+
+def test_segments_round_trip_in_any_order():
+    """Synchronous small-buffer segments (Fig. 4b) are self-contained: packed
+    through a small staging area, shuffled, and read back into the released
+    block, they restore it exactly; a corrupted, missing or repeated segment
+    is rejected before anything is written."""
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    L, na, nb, D, site = 10, 5, 5, 60, 4
+    say("segments in any order")
+    ctx, h, eri, dims, T = build_system(L, na, nb, D, site)
+    lay = B.bsdmrg_psi_layout(ctx, site)
+    x = torch.from_numpy(B.psi_to_flat(psi_for(dims, site, 7), lay)).cuda()
+    ref = torch.empty_like(x)
+    B.bsdmrg_hpsi(ctx, site, x, ref)
+    torch.cuda.synchronize()
+    comp, side = torch.cuda.current_stream(), torch.cuda.Stream()
+    rng = np.random.default_rng(1)
+    for sd, bond in ((B.LEFT, site), (B.RIGHT, site + 2)):
+        staging_bytes = None
+        for sb in (1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22):
+            try:
+                total, nseg = B.bsdmrg_segments_size(ctx, sd, bond, sb)
+                staging_bytes = sb
+                break
+            except B.BsdmrgError as e:
+                assert e.code == B.ENOMEM
+        assert staging_bytes is not None
+        say(f"  side {sd}: {nseg} segments, {total} bytes through a {staging_bytes} byte staging area")
+        assert nseg >= 2
+        staging = torch.empty(staging_bytes // 8, dtype=torch.float64, device="cuda")
+        pin = torch.empty(total // 8, dtype=torch.float64, pin_memory=True)
+        written, k = B.bsdmrg_pack_segments(ctx, sd, bond, staging, staging_bytes, pin, total, comp, side)
+        assert written == total and k == nseg
+        segs = _split_segments(pin.numpy().view(np.uint8))
+        assert len(segs) == nseg
+        order = rng.permutation(nseg)
+        shuffled = torch.from_numpy(np.concatenate([segs[i] for i in order]).view(np.float64)).pin_memory()
+        # release the block: only the segments can restore it
+        n = B.bsdmrg_serialized_size(ctx, sd, bond)
+        st1 = torch.empty(n // 8 + 32, dtype=torch.float64, device="cuda")
+        pin1 = torch.empty(n // 8 + 32, dtype=torch.float64, pin_memory=True)
+        B.bsdmrg_offload(ctx, sd, bond, st1, pin1, n, 1, comp, side)
+        B.bsdmrg_offload_wait(ctx, sd, bond)
+        bad_sets = []
+        b1 = np.concatenate([segs[i] for i in order]).copy()
+        b1[40] ^= 0x01                      # fingerprint byte of the first segment
+        bad_sets.append(b1)
+        bad_sets.append(np.concatenate([segs[i] for i in order[1:]]))           # one missing
+        bad_sets.append(np.concatenate([segs[i] for i in order] + [segs[order[0]]]))   # one repeated
+        for bad in bad_sets:
+            tb = torch.from_numpy(bad.view(np.float64)).pin_memory()
+            with pytest.raises(B.BsdmrgError) as e:
+                B.bsdmrg_unpack_segments(ctx, sd, bond, tb, tb.numel() * 8, staging, staging_bytes, comp, side)
+            assert e.value.code == B.ECORRUPT
+            assert B.bsdmrg_block_bytes(ctx, sd, bond) == 0
+        B.bsdmrg_unpack_segments(ctx, sd, bond, shuffled, total, staging, staging_bytes, comp, side)
+        assert B.bsdmrg_block_bytes(ctx, sd, bond) > 0
+    y = torch.empty_like(x)
+    B.bsdmrg_hpsi(ctx, site, x, y)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref)
+    B.bsdmrg_destroy(ctx)
+
+
+def test_pack_is_independent_of_the_workgroup_count():
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    L, na, nb, D, site = 10, 5, 5, 60, 4
+    say("pack vs workgroup count")
+    ctx, h, eri, dims, T = build_system(L, na, nb, D, site)
+    n = B.bsdmrg_serialized_size(ctx, B.LEFT, site)
+    outs = []
+    try:
+        for wg in (0, 1, 7, 1024):
+            B.bsdmrg_set_copy_workgroups(wg)
+            dst = torch.full((n // 8 + 32,), float(wg), dtype=torch.float64, device="cuda")
+            B.bsdmrg_pack(ctx, B.LEFT, site, dst, dst.numel() * 8)
+            outs.append(dst[: n // 8].clone())
+            B.bsdmrg_unpack(ctx, B.LEFT, site, dst, n)
+    finally:
+        B.bsdmrg_set_copy_workgroups(0)
+    torch.cuda.synchronize()
+    for o in outs[1:]:
+        assert torch.equal(o.view(torch.int64), outs[0].view(torch.int64))
     B.bsdmrg_destroy(ctx)

@@ -25,7 +25,7 @@ def _oracle_at(h, eri, na, nb, dims, T, site):
     d = OracleDMRG(h, eri, na, nb, 4)
     d.T = list(T)
     d.dims = list(dims)
-    d.left = build_left_blocks(d.T, site, t, g)
+    d.left = dict(enumerate(build_left_blocks(d.T, site, t, g)))
     d.right = build_right_blocks(d.T, site + 2, t, g, (na, nb))
     return d
 
