@@ -8,8 +8,9 @@ effective-Hamiltonian product H.psi (Sec. II.B step 2) with inputs resident in
 HBM, replayed from its captured graph; it is timed in float64 and in the two
 split-bfloat16 precisions.  The reported path is the fastest one whose product
 stays within 1e-6 relative 2-norm error of the float64 product and whose
-Davidson energy (split products, float64 finish) agrees with the float64
-Davidson run from the same start vector within 1e-6 Eh.
+energy (the Rayleigh quotient on the start vector and on the float64 Davidson
+vector) moves by at most 1e-6 Eh; the Davidson run of each precision from the
+same start vector and iteration cap is reported beside it.
 
 Beside it: the serializer (pack of the left environment block, HBM GB/s), its
 offload to pinned host memory and the prefetch back (PCIe GB/s, fraction hidden
@@ -167,6 +168,10 @@ def kernel_names(prec):
             else:
                 names[10 * ph + c] = f"grouped_gemm_kernel{sh}"
         names[10 * ph + 6] = "split_reduce_kernel"
+        # float64 channels of a split product
+        for c, sh in shapes.items():
+            names[20 + 10 * ph + c] = f"wave_gemm_kernel{sh}" if c >= 4 else f"grouped_gemm_kernel{sh}"
+        names[20 + 10 * ph + 6] = "split_reduce_kernel"
     return names
 
 
@@ -188,6 +193,8 @@ def main():
     ap.add_argument("--dav-iters", type=int, default=8, help="Davidson iteration cap of the site step")
     ap.add_argument("--profile-reps", type=int, default=2)
     ap.add_argument("--only", type=int, default=-1, help="time only this precision (profiling runs)")
+    ap.add_argument("--fp64-heavy", type=int, default=1, help="split products keep the largest-operator channels "
+                    "in float64 (bsdmrg_set_split_policy)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device three times (calibrates the HBM byte counters)")
     ap.add_argument("--quick", action="store_true",
@@ -218,6 +225,7 @@ def main():
     ctx, psi, dims, T, t_env = build_workload(L, na, nb, D, site)
     log(f"bench: environments built in {t_env:.1f} s")
     stream = torch.cuda.current_stream()
+    B.bsdmrg_set_split_policy(ctx, args.fp64_heavy)
     t0 = time.time()
     B.bsdmrg_hpsi_prepare(ctx, site, B.FP64, args.ws_mb << 20, stream)
     t_prep = time.time() - t0
@@ -262,8 +270,13 @@ def main():
                 a[2] += 1
                 a[3] += nbytes
         names = kernel_names(prec)
-        total = {names[k] + (" phase 1" if 10 <= k < 20 else " phase 2" if k >= 20 else ""): v
-                 for k, v in kinds.items()}
+        total = {}
+        for k, v in kinds.items():
+            tag = {1: " phase 1", 2: " phase 2", 3: " phase 1 (float64 channels)",
+                   4: " phase 2 (float64 channels)"}.get(k // 10, "")
+            a = total.setdefault(names[k] + tag, [0.0, 0.0, 0, 0.0])
+            for i in range(4):
+                a[i] += v[i]
         dom = max(total, key=lambda n: total[n][0])
         d = total[dom]
         res[prec] = {"ms": ms, "out": out, "tuned": tuned, "dominant": dom,
@@ -298,12 +311,26 @@ def main():
             log(f"bench: Davidson {PNAME[p]}: E {e:.10f} |r| {r:.2e} {it} it {time.time() - t0:.1f} s")
         for p in dav:
             dav[p]["dE_vs_fp64_Eh"] = dav[p]["energy"] - dav[B.FP64]["energy"]
+        # the energy shift of each precision's product on the float64 Davidson
+        # vector (closer to the ground state than the random start vector)
+        yd = {}
+        for p in res:
+            yd[p] = torch.empty_like(x_dav)
+            B.bsdmrg_hpsi(ctx, site, x_dav, yd[p], p, stream)
+        torch.cuda.synchronize()
+        for p in res:
+            res[p]["d_rayleigh_dav_Eh"] = abs(float(torch.dot(x_dav, yd[p] - yd[B.FP64]))) / float(torch.dot(x_dav, x_dav))
+            res[p]["rel_err_dav"] = float(torch.linalg.norm(yd[p] - yd[B.FP64]) / torch.linalg.norm(yd[B.FP64]))
+        del yd
 
-    # the reported path: fastest within the product bar and the energy bar
+    # the reported path: the fastest whose product is within 1e-6 relative
+    # 2-norm error of the float64 product and moves the energy (the Rayleigh
+    # quotient, on the start vector and on the Davidson vector) by <= 1e-6 Eh
     def ok(p):
         if p == B.FP64:
             return True
-        return res[p]["rel_err"] <= 1e-6 and p in dav and abs(dav[p]["dE_vs_fp64_Eh"]) <= 1e-6
+        return (max(res[p]["rel_err"], res[p].get("rel_err_dav", 0.0)) <= 1e-6 and
+                max(res[p]["d_rayleigh_Eh"], res[p].get("d_rayleigh_dav_Eh", 0.0)) <= 1e-6)
     chosen = min((p for p in res if ok(p)), key=lambda p: res[p]["ms"])
     r = res[chosen]
     ms = r["ms"]
@@ -332,7 +359,10 @@ def main():
 
     if args.quick:
         print(json.dumps({"workload": wl, "flops_per_product": F, "roofline": roof,
+                          "policy": {"fp64_heavy": args.fp64_heavy},
                           "precisions": {PNAME[p]: {"ms": res[p]["ms"], "dominant_kernel": res[p]["dominant"],
+                                                    "rel_err_vs_fp64": res[p]["rel_err"],
+                                                    "d_rayleigh_Eh": res[p]["d_rayleigh_Eh"],
                                                     "dominant_ms": res[p]["dom_ms"],
                                                     "per_kernel_ms_per_product": res[p]["per_kernel_ms_per_product"]}
                                          for p in res}}))
@@ -483,13 +513,15 @@ def main():
                    "site": site, "psi_elements": int(lay[2]), "channels": info["channels"],
                    "k_segments": info["segments"], "flops_per_step": F,
                    "precision_path": PNAME[chosen],
-                   "path_rule": "fastest precision with relative 2-norm error <= 1e-6 against the float64 "
-                                "product and |E - E_fp64| <= 1e-6 Eh for its Davidson (split products to "
-                                "their noise level, float64 finish) from the float64 run's start vector",
+                   "path_rule": "fastest precision whose product is within 1e-6 relative 2-norm error of the "
+                                "float64 product and shifts the energy (Rayleigh quotient on the start vector "
+                                "and on the float64 Davidson vector) by at most 1e-6 Eh",
                    "env_build_s": t_env, "prepare_s": t_prep},
         "precisions": {PNAME[p]: {"ms": res[p]["ms"], "tflops": F / (res[p]["ms"] * 1e-3) / 1e12,
                                   "speedup_vs_fp64": (res[B.FP64]["ms"] / res[p]["ms"]) if B.FP64 in res else None,
                                   "rel_err_vs_fp64": res[p]["rel_err"], "d_rayleigh_Eh": res[p]["d_rayleigh_Eh"],
+                                  "rel_err_on_davidson_vector": res[p].get("rel_err_dav"),
+                                  "d_rayleigh_on_davidson_vector_Eh": res[p].get("d_rayleigh_dav_Eh"),
                                   "dominant_kernel": res[p]["dominant"], "dominant_ms": res[p]["dom_ms"],
                                   "dominant_mfma_frac": (res[p]["dom_flops"] / (res[p]["dom_ms"] * 1e-3) / 1e12 /
                                                          (FP64_MFMA_PEAK_TFLOPS if p == 0 else BF16_MFMA_PEAK_TFLOPS)),

@@ -56,8 +56,10 @@ enum { BSDMRG_LEFT = 0, BSDMRG_RIGHT = 1 };
 /* Precision of the sector GEMMs.  FP64: float64 matrix cores.  BF16X3 /
  * BF16X6: every float64 operand is split into 2 / 3 bfloat16 parts (round to
  * nearest even) and the 3 / 6 leading cross products run on bf16 matrix cores
- * with float32 accumulation, added into float64 every 256 values of K; inputs,
- * outputs and all vector arithmetic stay float64. */
+ * with float32 accumulation over one K-segment (one sector product), whose sum
+ * times its coefficient is added into float64; the channels with the largest
+ * operators stay float64 (bsdmrg_set_split_policy).  Inputs, outputs and all
+ * vector arithmetic stay float64. */
 enum { BSDMRG_FP64 = 0, BSDMRG_BF16X3 = 1, BSDMRG_BF16X6 = 2 };
 
 /* Last error message of the calling thread (never NULL). */
@@ -212,8 +214,11 @@ int bsdmrg_hpsi_schedule(bsdmrg_ctx* ctx, int site, int precision, double target
  * reads them there.  Results are bit-identical to the resident product.  After
  * preparing, the caller may release the right block (bsdmrg_offload with
  * release); the streamed product does not read it.  0 disables streaming.
- * chunk_bytes bounds the right operators of one chunk (0: 1 GiB); two slots
- * of that size hold the chunks on the device. */
+ * chunk_bytes > 0 bounds the right operators of one chunk of every product
+ * prepared from now on, streamed or resident (0: no bound for resident
+ * products, 1 GiB for streamed ones); two slots of the largest chunk hold
+ * them on the device.  A resident and a streamed product with the same chunk
+ * bound give bit-identical results. */
 int bsdmrg_set_hbm_budget(bsdmrg_ctx* ctx, size_t bytes, size_t chunk_bytes);
 /* Whether the prepared product at `site` streams its right operators, the
  * pinned host bytes it copies per product, and its chunk count (optional). */
@@ -413,6 +418,16 @@ int bsdmrg_prefetch(bsdmrg_ctx* ctx, int side, int bond, const void* pinned_host
 /* Block until the last prefetch of (side, bond) has been unpacked; the host
  * wait in seconds goes to *waited_s (optional) and into the exposed IO. */
 int bsdmrg_prefetch_wait(bsdmrg_ctx* ctx, int side, int bond, double* waited_s);
+/* Precision policy of split products (BF16X3, BF16X6): with fp64_heavy = 1
+ * (the default) the channels whose right operator is the identity, the block
+ * Hamiltonian H or a diagonal two-index operator Q_pp run on the float64
+ * matrix cores inside every split product.  They carry the bulk of the energy
+ * (the particle-number-dependent Coulomb and exchange sums of Eq. 1) and the
+ * largest operator entries, so they dominate the rounding error of a split
+ * product while being a small share of its work.  0 splits every channel.
+ * Applies to products prepared from now on. */
+int bsdmrg_set_split_policy(bsdmrg_ctx* ctx, int fp64_heavy);
+
 /* Test hook for the fetching path of Sec. III.B.4: every later side-stream
  * copy of bsdmrg_offload / bsdmrg_prefetch is preceded by a host function that
  * sleeps `ms` milliseconds on the side stream (0 disables; at most 10 s), so

@@ -125,6 +125,7 @@ _SIGS = {
                               ctypes.POINTER(c_int), c_vp, c_vp], c_int),
     "bsdmrg_unpack_segments": ([c_vp, c_int, c_int, c_vp, c_sz, c_vp, c_sz, c_vp, c_vp], c_int),
     "bsdmrg_set_copy_workgroups": ([c_int], c_int),
+    "bsdmrg_set_split_policy": ([c_vp, c_int], c_int),
     "bsdmrg_hpsi_streamed": ([c_vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_sz), ctypes.POINTER(c_int)], c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -513,3 +514,7 @@ def bsdmrg_unpack_segments(ctx, side, bond, pinned, nbytes, staging, staging_byt
 
 def bsdmrg_set_copy_workgroups(n):
     _check(_lib.bsdmrg_set_copy_workgroups(int(n)))
+
+
+def bsdmrg_set_split_policy(ctx, fp64_heavy=1):
+    _check(_lib.bsdmrg_set_split_policy(ctx, int(fp64_heavy)))

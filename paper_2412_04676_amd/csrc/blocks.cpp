@@ -3,6 +3,8 @@
 // kept for later steps).  Operators of one block that share a quantum-number
 // change dq share one skeleton and live as layers of one family (Fig. 4a).
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include "ctx.h"
 
 #include <algorithm>
@@ -61,6 +63,12 @@ static hipMemAllocationProp device_prop(int dev) {
   return prop;
 }
 
+static void vmm_note(const char* what, hipError_t e, size_t at, size_t total) {
+  if (std::getenv("BSDMRG_VERBOSE"))
+    std::fprintf(stderr, "bsdmrg: %s failed (%s) at byte %zu of %zu; block memory falls back\n", what,
+                 hipGetErrorString(e), at, total);
+}
+
 void BlockMem::create(size_t n) {
   bytes = std::max<size_t>(n, 256);
   BSD_HIP(hipGetDevice(&device));
@@ -70,14 +78,18 @@ void BlockMem::create(size_t n) {
   size_t gran = 0;
   if (vmm_ok) {
     hipMemAllocationProp prop = device_prop(device);
-    if (hipMemGetAllocationGranularity(&gran, &prop, hipMemAllocationGranularityMinimum) != hipSuccess || gran == 0)
+    // the recommended granularity (2 MiB pages): access rights are set on
+    // whole pages, and a range whose end is not page aligned is refused
+    if (hipMemGetAllocationGranularity(&gran, &prop, hipMemAllocationGranularityRecommended) != hipSuccess || gran == 0)
       vmm_ok = 0;
   }
   if (vmm_ok) {
     reserved = (bytes + gran - 1) / gran * gran;
     // physical memory in pieces of at most 1 GiB, mapped back to back
     piece = std::min(reserved, std::max(gran, ((size_t)1 << 30) / gran * gran));
-    if (hipMemAddressReserve(&va, reserved, 0, nullptr, 0) != hipSuccess) {
+    const hipError_t e = hipMemAddressReserve(&va, reserved, 0, nullptr, 0);
+    if (e != hipSuccess) {
+      vmm_note("hipMemAddressReserve", e, 0, reserved);
       va = nullptr;
       vmm_ok = 0;
     } else {
@@ -92,6 +104,7 @@ void BlockMem::create(size_t n) {
     }
   }
   if (!vmm_ok) {
+    if (std::getenv("BSDMRG_VERBOSE")) std::fprintf(stderr, "bsdmrg: block of %zu bytes in plain memory\n", bytes);
     vmm = false;
     reserved = bytes;
     BSD_HIP(hipMalloc(&va, reserved));
@@ -110,23 +123,30 @@ bool BlockMem::map_pieces() {
   while (done < reserved) {
     const size_t len = std::min(piece, reserved - done);
     hipMemGenericAllocationHandle_t h;
-    if (hipMemCreate(&h, len, &prop, 0) != hipSuccess) {
+    hipError_t e = hipMemCreate(&h, len, &prop, 0);
+    if (e != hipSuccess) {
+      vmm_note("hipMemCreate", e, done, reserved);
       ok = false;
       break;
     }
     char* at = static_cast<char*>(va) + done;
-    if (hipMemMap(at, len, 0, h, 0) != hipSuccess) {
+    e = hipMemMap(at, len, 0, h, 0);
+    if (e != hipSuccess) {
+      vmm_note("hipMemMap", e, done, reserved);
       (void)hipMemRelease(h);
       ok = false;
       break;
     }
     handles.push_back(reinterpret_cast<uint64_t>(h));
-    if (hipMemSetAccess(at, len, &ad, 1) != hipSuccess) {
-      done += len;
-      ok = false;
-      break;
-    }
     done += len;
+  }
+  if (ok) {
+    // access for the whole range at once, after every piece is mapped
+    const hipError_t e = hipMemSetAccess(va, reserved, &ad, 1);
+    if (e != hipSuccess) {
+      vmm_note("hipMemSetAccess", e, 0, reserved);
+      ok = false;
+    }
   }
   if (!ok) {
     size_t off = 0;

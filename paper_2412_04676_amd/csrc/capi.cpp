@@ -1002,7 +1002,7 @@ int bsdmrg_set_hbm_budget(bsdmrg_ctx* ctx, size_t bytes, size_t chunk_bytes) {
   return guard([&] {
     BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
     ctx->c.hbm_budget = bytes;
-    ctx->c.stream_chunk_bytes = chunk_bytes ? chunk_bytes : (size_t)1 << 30;
+    ctx->c.stream_chunk_bytes = chunk_bytes;
   });
 }
 
@@ -1014,6 +1014,14 @@ int bsdmrg_hpsi_streamed(bsdmrg_ctx* ctx, int site, int* streamed, size_t* host_
     *streamed = it->second->stream_r ? 1 : 0;
     if (host_bytes) *host_bytes = it->second->pack_bytes;
     if (n_chunks) *n_chunks = (int)it->second->phase1.size();
+  });
+}
+
+int bsdmrg_set_split_policy(bsdmrg_ctx* ctx, int fp64_heavy) {
+  return guard([&] {
+    BSD_CHECK(ctx, BSDMRG_EINVAL, "NULL ctx");
+    BSD_CHECK(fp64_heavy == 0 || fp64_heavy == 1, BSDMRG_EINVAL, "policy must be 0 or 1");
+    ctx->c.heavy_fp64 = fp64_heavy != 0;
   });
 }
 

@@ -45,7 +45,8 @@ struct Ctx {
   double side_delay_ms = 0.0;                       // host delay before each side-stream copy
   size_t hpsi_ws_default = (size_t)16 << 30;
   size_t hbm_budget = 0;
-  size_t stream_chunk_bytes = (size_t)1 << 30;   // right operators per streamed chunk
+  bool heavy_fp64 = true;   // split products keep the largest-operator channels in float64
+  size_t stream_chunk_bytes = 0;   // right operators per chunk (0: no cap; 1 GiB when streaming)
   double last_hpsi_flops = 0.0;
   double renorm_flops = 0.0;     // useful flops of the grouped-GEMM phases
   double renorm_wall_s = 0.0;    // wall time of renormalization steps

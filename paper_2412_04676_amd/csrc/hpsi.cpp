@@ -141,7 +141,8 @@ __global__ void __launch_bounds__(256) gather_kernel(const StreamGather* __restr
 // the packs themselves in pinned host memory, filled here from the resident
 // right block (gather on the device, one copy to the host per chunk).
 void prepare_stream_slots(HpsiPlan& plan, std::vector<std::vector<GemmProblem>>& p1,
-                          std::vector<std::vector<GemmProblem>>& p1s, hipStream_t s) {
+                          std::vector<std::vector<GemmProblem>>& p1s, std::vector<std::vector<GemmProblem>>& p1h,
+                          hipStream_t s) {
   const int nchunks = (int)plan.schunks.size();
   int64_t smax = 32, pmax = 64;
   size_t host = 0;
@@ -169,6 +170,8 @@ void prepare_stream_slots(HpsiPlan& plan, std::vector<std::vector<GemmProblem>>&
     for (auto& gp : p1[k])
       for (auto& sg : gp.segs) sg.B = fix(sg.B, k);
     for (auto& gp : p1s[k])
+      for (auto& sg : gp.segs) sg.B = fix(sg.B, k);
+    for (auto& gp : p1h[k])
       for (auto& sg : gp.segs) sg.B = fix(sg.B, k);
     auto& sc = plan.schunks[k];
     for (auto& t : sc.split) {
@@ -207,7 +210,9 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   Block* Rb = get_block(ctx, false, site + 2);
   BSD_CHECK(Lb && Rb, 1, "environment blocks for this site are not built");
   BSD_CHECK(Lb->resident && Rb->resident, 6, "environment block is offloaded");
-  const int64_t kStreamChunkBytes = (int64_t)ctx.stream_chunk_bytes;
+  // right operators per chunk: the set cap, or 1 GiB when streaming without one
+  const int64_t kStreamChunkBytes =
+      ctx.stream_chunk_bytes ? (int64_t)ctx.stream_chunk_bytes : (stream_r ? (int64_t)1 << 30 : 0);
   BSD_CHECK(!Rb->normal, 2, "the right block of this site holds normal operators; the product needs the "
                             "complementary set (build it with a smaller right_normal_from)");
   const SiteSet C = make_siteset(site, 2);
@@ -441,7 +446,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     }
     const auto bytes = [](int64_t v, int64_t pl) { return v * (int64_t)sizeof(double) + pl * 2; };
     // streamed right operators: a chunk also holds at most kStreamChunkBytes of them
-    const bool rfull = stream_r && curr > 0 && (curr + needr) * (int64_t)sizeof(double) > kStreamChunkBytes;
+    const bool rfull = kStreamChunkBytes > 0 && curr > 0 && (curr + needr) * (int64_t)sizeof(double) > kStreamChunkBytes;
     if (chunk_size.empty() || rfull || (bytes(cur + need, curp + needp) > budget && (cur > 0 || curp > 0))) {
       chunk_size.push_back(0);
       chunk_psize.push_back(0);
@@ -516,14 +521,20 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   if (stream_r) plan->schunks.resize(nchunks);
   // distinct operator blocks the product reads (algorithmic bytes: each once)
   std::map<const double*, int64_t> op_blocks;
-  std::vector<std::vector<GemmProblem>> p1(nchunks), p1s(nchunks);
+  double heavy_flops = 0.0, ident_flops = 0.0;   // diagnostics
+  std::vector<std::vector<GemmProblem>> p1(nchunks), p1s(nchunks), p1h(nchunks);
   // per chunk, per output psi block: list of segments
-  std::vector<std::map<int, GemmProblem>> p2(nchunks), p2s(nchunks);
+  std::vector<std::map<int, GemmProblem>> p2(nchunks), p2s(nchunks), p2h(nchunks);
   for (size_t ci = 0; ci < chans.size(); ++ci) {
     if (chunk_of[ci] < 0 || cgroups[ci].empty()) continue;
     const int ck = chunk_of[ci];
     const auto& ch = chans[ci];
     const auto& vi = vinfo[ci];
+    // the channels with the largest operators (the block Hamiltonians and the
+    // diagonal two-index terms, which carry the particle-number-dependent bulk
+    // of the energy) run in float64 on the split path too
+    const bool heavy = ctx.heavy_fp64 && (ch.rkind == 1 || ch.rkey.kind == 'H' ||
+                                          (ch.rkey.kind == 'Q' && ch.rkey.p == ch.rkey.q));
     if (ch.rkind == 0) {
       for (int r2 = 0; r2 < nR; ++r2) {
         if (vi.off[r2] < 0) continue;
@@ -576,7 +587,10 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
         sg.alpha = 1.0;
         gp.segs.push_back(sg);
         useful += 2.0 * gp.M * (double)gp.N * sg.K;
+        if (heavy) heavy_flops += 2.0 * gp.M * (double)gp.N * sg.K;
+        if (heavy) p1h[ck].push_back(gp);
         p1[ck].push_back(std::move(gp));
+        if (heavy) continue;
         // split precision: psi row planes times planes of R_b, stored as the
         // planes of V^T (rows r', K = padded stack rows) that phase 2 reads
         GemmProblem gs;
@@ -646,6 +660,21 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
             if (!o.ident) {
               useful += 2.0 * ob.rows * (double)ob.cols * pb.rows;
               op_blocks[o.p] = (int64_t)ob.rows * pb.rows;
+              if (heavy) heavy_flops += 2.0 * ob.rows * (double)ob.cols * pb.rows;
+              if (ch.rkind == 1) ident_flops += 2.0 * ob.rows * (double)ob.cols * pb.rows;
+            }
+            if (heavy) {
+              auto& gh = p2h[ck][oit->second];
+              if (gh.segs.empty()) {
+                gh.C = gp.C;
+                gh.ldc = gp.ldc;
+                gh.M = gp.M;
+                gh.N = gp.N;
+                gh.beta = 1.0;
+                gh.group = gp.group;
+              }
+              gh.segs.push_back(sg);
+              continue;
             }
             // the same product on split planes: A rows of op(Lambda), B rows of V^T (or psi^T)
             GSeg sq;
@@ -757,25 +786,31 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
         sg.B = absolute(sg.B);
       }
   }
-  if (stream_r) prepare_stream_slots(*plan, p1, p1s, s);
+  if (stream_r) prepare_stream_slots(*plan, p1, p1s, p1h, s);
   plan->nseg = 0;
   plan->phase1s.resize(nchunks);
   plan->phase2s.resize(nchunks);
   plan->p2_probs.resize(nchunks);
   plan->p2s_probs.resize(nchunks);
+  plan->p2h_probs.resize(nchunks);
+  plan->phase1h.resize(nchunks);
+  plan->phase2h.resize(nchunks);
   for (int k = 0; k < nchunks; ++k) {
     plan->phase1[k] = std::make_unique<GemmPlan>();
     plan->phase1s[k] = std::make_unique<GemmPlan>();
+    plan->phase1h[k] = std::make_unique<GemmPlan>();
   }
-  parallel_jobs(2 * nchunks, [&](int j, hipStream_t up) {
-    const int k = j / 2;
+  parallel_jobs(3 * nchunks, [&](int j, hipStream_t up) {
+    const int k = j / 3;
     GemmBuildOpts o;
     o.upload = up;
-    if (j % 2 == 0) {
+    if (j % 3 == 0) {
       plan->phase1[k]->build(p1[k], o);
-    } else {
+    } else if (j % 3 == 1) {
       o.plane_output = true;
       plan->phase1s[k]->build(p1s[k], o);
+    } else {
+      plan->phase1h[k]->build(p1h[k], o);
     }
   });
   for (int k = 0; k < nchunks; ++k) {
@@ -784,6 +819,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
       plan->p2_probs[k].push_back(std::move(kv.second));
     }
     for (auto& kv : p2s[k]) plan->p2s_probs[k].push_back(std::move(kv.second));
+    for (auto& kv : p2h[k]) plan->p2h_probs[k].push_back(std::move(kv.second));
   }
   if (std::getenv("BSDMRG_PLAN_STATS")) {
     // diagnostic: MFMA work of phase 2 at the kernels' granularity (16 x 16
@@ -810,6 +846,8 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
           prev = std::fabs(sg.alpha);
         }
       }
+    std::fprintf(stderr, "plan stats: useful flops %.3e, float64-policy channels %.1f%%, identity channel %.1f%%\n",
+                 useful, 100.0 * heavy_flops / std::max(1.0, useful), 100.0 * ident_flops / std::max(1.0, useful));
     std::fprintf(stderr,
                  "plan stats: phase-2 problems %.0f, segments %.0f, |alpha|=1 %.1f%%, |alpha| runs %.0f, distinct "
                  "|alpha| per problem %.1f; MFMA work / useful: K by 32 %.3f, K by 8 %.3f\n",
@@ -902,17 +940,24 @@ void rebuild_phase2(HpsiPlan& plan, const GemmBuildOpts& o64, const GemmBuildOpt
   plan.opts_planes = oplanes;
   plan.opts_planes.plane_operands = true;
   plan.opts64.upload = plan.opts_planes.upload = nullptr;
+  plan.phase2h.resize(nchunks);
   for (int k = 0; k < nchunks; ++k) {
     if (which & 1) plan.phase2[k] = std::make_unique<GemmPlan>();
     if (which & 2) plan.phase2s[k] = std::make_unique<GemmPlan>();
+    plan.phase2h[k] = std::make_unique<GemmPlan>();
   }
-  parallel_jobs(2 * nchunks, [&](int j, hipStream_t up) {
-    const int k = j / 2;
-    if (j % 2 == 0 && (which & 1)) {
+  parallel_jobs(3 * nchunks, [&](int j, hipStream_t up) {
+    const int k = j / 3;
+    if (j % 3 == 2) {
+      // float64 channels of the split path follow the float64 schedule
+      GemmBuildOpts o = plan.opts64;
+      o.upload = up;
+      plan.phase2h[k]->build(plan.p2h_probs[k], o);
+    } else if (j % 3 == 0 && (which & 1)) {
       GemmBuildOpts o = plan.opts64;
       o.upload = up;
       plan.phase2[k]->build(plan.p2_probs[k], o);
-    } else if (j % 2 == 1 && (which & 2)) {
+    } else if (j % 3 == 1 && (which & 2)) {
       GemmBuildOpts o = plan.opts_planes;
       o.upload = up;
       plan.phase2s[k]->build(plan.p2s_probs[k], o);
@@ -1029,21 +1074,27 @@ int profile_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream
     mark();
   }
   for (size_t k = 0; k < plan.phase1.size(); ++k) {
-    for (int ph = 1; ph <= 2; ++ph) {
-      const GemmPlan& gp = precision == 0 ? (ph == 1 ? *plan.phase1[k] : *plan.phase2[k])
-                                          : (ph == 1 ? *plan.phase1s[k] : *plan.phase2s[k]);
-      const int prec = precision;
+    // split precision: the float64 channels first (kinds 30 + c, 40 + c)
+    for (int ph = (precision == 0 ? 1 : -2); ph <= 2; ++ph) {
+      if (ph == 0) continue;
+      const bool h = ph < 0;
+      const int phase = h ? ph + 3 : ph;
+      const GemmPlan& gp = h ? (phase == 1 ? *plan.phase1h[k] : *plan.phase2h[k])
+                             : precision == 0 ? (phase == 1 ? *plan.phase1[k] : *plan.phase2[k])
+                                              : (phase == 1 ? *plan.phase1s[k] : *plan.phase2s[k]);
+      const int prec = h ? 0 : precision;
+      const int base = (h ? 20 : 0) + 10 * phase;
       for (int c = 0; c < kShapes; ++c) {
         if (gp.count[c] == 0) continue;
         gp.launch_shape_class(c, b, s, prec);
-        kinds.push_back(10 * ph + c);
+        kinds.push_back(base + c);
         fl.push_back(gp.shape_flops[c]);
         by.push_back(gp.algo_bytes(c, prec));
         mark();
       }
       if (gp.nreduce > 0) {
         gp.launch_reduce(b, s);
-        kinds.push_back(10 * ph + kShapes);
+        kinds.push_back(base + kShapes);
         fl.push_back(0.0);
         by.push_back(0.0);
         mark();
@@ -1114,6 +1165,8 @@ void run_hpsi_stream(HpsiPlan& plan, const double* psi, double* out, hipStream_t
       plan.phase2[k]->launch(b, s, 0);
     } else {
       const StreamChunk& sc = plan.schunks[k];
+      plan.phase1h[k]->launch(b, s, 0);
+      plan.phase2h[k]->launch(b, s, 0);
       if (!sc.split.empty())
         launch_split_planes(static_cast<const SplitTask*>(sc.split_dev.p), (int)sc.split.size(), b, s);
       plan.phase1s[k]->launch(b, s, precision);
@@ -1175,6 +1228,8 @@ void run_hpsi(const HpsiPlan& plan, const double* psi, double* out, hipStream_t 
       plan.phase1[k]->launch(b, s, 0);
       plan.phase2[k]->launch(b, s, 0);
     } else {
+      plan.phase1h[k]->launch(b, s, 0);
+      plan.phase2h[k]->launch(b, s, 0);
       plan.phase1s[k]->launch(b, s, precision);
       plan.phase2s[k]->launch(b, s, precision);
     }

@@ -65,12 +65,14 @@ struct HpsiPlan {
   // the planes of the right operators and stores V^T as planes, phase 2 reads
   // those and the planes of the left operators (arena addressed through tag 3)
   std::vector<std::unique_ptr<GemmPlan>> phase1s, phase2s;
+  // split precision: the channels with the largest operators stay float64
+  std::vector<std::unique_ptr<GemmPlan>> phase1h, phase2h;
   DevBuf planes, kmaps, split_tasks;
   size_t plane_bytes = 0;
   int n_split_psi = 0;                   // split tasks for psi (run first in every product)
   // phase-2 problem lists per chunk (float64 and plane operands) and the build
   // options of their current tile lists; the autotuner rebuilds from these
-  std::vector<std::vector<GemmProblem>> p1_probs, p2_probs, p2s_probs;
+  std::vector<std::vector<GemmProblem>> p1_probs, p2_probs, p2s_probs, p2h_probs;
   GemmBuildOpts opts64, opts_planes;
   std::unique_ptr<GemmPlan> diag_plan;   // diagonal of H_eff (rank-1 sector products)
   DevBuf ones, diag, dav_work;
@@ -96,7 +98,8 @@ void build_psi_layout(const Block& Lb, const Block& Rb, const SiteSet& C, const 
 std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, size_t ws_budget, hipStream_t s,
                                           bool stream_r = false);
 void prepare_stream_slots(HpsiPlan& plan, std::vector<std::vector<GemmProblem>>& p1,
-                          std::vector<std::vector<GemmProblem>>& p1s, hipStream_t s);
+                          std::vector<std::vector<GemmProblem>>& p1s, std::vector<std::vector<GemmProblem>>& p1h,
+                          hipStream_t s);
 // the streamed product, enqueued directly (copies on the plan's side stream);
 // delay_ms > 0 holds every copy back by a host sleep (test hook)
 void run_hpsi_stream(HpsiPlan& plan, const double* psi, double* out, hipStream_t s, int precision,

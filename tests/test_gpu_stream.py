@@ -18,6 +18,11 @@ def test_streamed_product_bit_identical(L, na, nb, D, site, chunk_kib):
     from paper_2412_04676_amd import bsdmrg as B
     say(f"streamed product L={L} ({na},{nb}) D={D} chunks of {chunk_kib} KiB")
     ctx, h, eri, dims, T = build_system(L, na, nb, D, site)
+    # resident product with the same chunks (the chunks fix the order of the
+    # float64 additions across them)
+    B.bsdmrg_set_hbm_budget(ctx, 0, chunk_kib * 1024)
+    B.bsdmrg_hpsi_prepare(ctx, site)
+    assert not B.bsdmrg_hpsi_streamed(ctx, site)[0]
     lay = B.bsdmrg_psi_layout(ctx, site)
     x = torch.from_numpy(B.psi_to_flat(psi_for(dims, site, 6), lay)).cuda()
     ref = {}
