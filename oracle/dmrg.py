@@ -12,7 +12,10 @@ sweep runs the cut left to right over every position and then right to left.
 Truncation rule (the paper fixes none): sort the singular values of all
 sectors together, keep the D largest, extend the kept set to every value
 >= sigma_D (1 - 1e-10) so exact degeneracies are never split, and drop values
-<= 1e-14 sigma_max.  The truncation error is the discarded weight sum sigma^2.
+<= 1e-6 sigma_max (weight 1e-12 of the largest): below that a singular value
+is not determined by a wave function that the eigensolver fixes only to its
+residual tolerance, so whether such a state is kept would depend on rounding.
+The truncation error is the discarded weight sum sigma^2.
 """
 
 import numpy as np
@@ -105,7 +108,7 @@ def split(psi, dl, dr, D):
         cut = sig[D - 1] * (1.0 - 1e-10)
     else:
         cut = -1.0
-    floor = 1e-14 * smax
+    floor = 1e-6 * smax
     keep = {}
     err = 0.0
     for qm, (rows, cols, roff, coff, U, s, Vt) in svd.items():

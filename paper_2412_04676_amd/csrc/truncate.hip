@@ -9,7 +9,11 @@
 // state, and diagonalized by a parallel round-robin Jacobi method in one
 // workgroup per sector.  Singular values are sqrt of the eigenvalues.  The
 // kept states follow one global rule: the D largest, extended to every value
-// >= sigma_D (1 - 1e-10), values <= 1e-14 sigma_max dropped.
+// >= sigma_D (1 - 1e-10), values <= 1e-6 sigma_max dropped.  A sector has at
+// most min(rows, cols) nonzero singular values; the Gram matrix of its larger
+// side carries the others as rounding-level eigenvalues, which never count.
+// The floor sits well above what the Gram route resolves (sigma down to about
+// sqrt(eps) sigma_max) and above the eigensolver's noise in psi.
 #include "truncate.h"
 
 #include <algorithm>
@@ -27,7 +31,8 @@ namespace bsd {
 // pass after the rotation angles: a wave takes the two rows (p1, q1) of pair
 // k1 and its lanes the column pairs k2 (accesses stay inside two rows), and
 // the eigenvector rows p, q rotate with lanes along the row.  No divisions.
-constexpr int kJacobiMaxDim = 4096;   // 2048 rotations per round: 48 KiB of LDS
+constexpr int kJacobiMaxDim = 4096;
+constexpr double kSigmaFloor = 1e-6;   // relative to sigma_max: numerically zero below   // 2048 rotations per round: 48 KiB of LDS
 
 __global__ void __launch_bounds__(1024)
 jacobi_kernel(const int64_t* __restrict__ goff, const int* __restrict__ dims, double* __restrict__ G,
@@ -289,23 +294,33 @@ TruncResult truncate_psi(Ctx& ctx, const HpsiPlan& plan, const double* psi, int 
     int sec, col;
   };
   std::vector<SV> all;
+  std::vector<SV> beyond_rank;
   for (int k = 0; k < (int)secs.size(); ++k) {
     const auto& x = secs[k];
     const int n = left_to_right ? x.nr : x.nc;
-    for (int j = 0; j < n; ++j) all.push_back({std::max(0.0, Gh[x.goff + (int64_t)j * x.m + j]), k, j});
+    std::vector<SV> sec;
+    for (int j = 0; j < n; ++j) sec.push_back({std::max(0.0, Gh[x.goff + (int64_t)j * x.m + j]), k, j});
+    // the rank bound: only the min(rows, cols) largest can be nonzero
+    std::sort(sec.begin(), sec.end(), [](const SV& a, const SV& b) { return a.lam > b.lam; });
+    const size_t rank = (size_t)std::min(x.nr, x.nc);
+    for (size_t j = 0; j < sec.size(); ++j) (j < rank ? all : beyond_rank).push_back(sec[j]);
   }
   std::sort(all.begin(), all.end(), [](const SV& a, const SV& b) { return a.lam > b.lam; });
   TruncResult res;
   double total = 0.0;
   for (auto& a : all) total += a.lam;
+  double disc = 0.0;
+  for (auto& a : beyond_rank) {
+    total += a.lam;
+    disc += a.lam;
+  }
   const double smax = all.empty() ? 0.0 : std::sqrt(all[0].lam);
   double cut = -1.0;
   if ((int)all.size() > D && D > 0) cut = std::sqrt(all[D - 1].lam) * (1.0 - 1e-10);
   std::vector<std::vector<int>> kept(secs.size());
-  double disc = 0.0;
   for (auto& a : all) {
     const double sg = std::sqrt(a.lam);
-    if (sg >= cut && sg > 1e-14 * smax) {
+    if (sg >= cut && sg > kSigmaFloor * smax) {
       kept[a.sec].push_back(a.col);
       res.sv.push_back(sg);
     } else {

@@ -143,13 +143,19 @@ def test_split_keeps_degenerate_pair_across_sectors():
 
 
 def test_split_drops_values_below_floor():
-    """Values at or below 1e-14 sigma_max are dropped even when fewer than D
-    states exist, and a sector left with nothing disappears from the kept set."""
-    spectrum = {(1, 0): [0.9, 1e-16], (0, 1): [0.4, 0.0], (1, 1): [1e-17]}
+    """Values at or below 1e-6 sigma_max are dropped even when fewer than D
+    states exist, and a sector left with nothing disappears from the kept set;
+    a value just above the floor stays."""
+    spectrum = {(1, 0): [0.9, 8e-7], (0, 1): [0.4, 0.0], (1, 1): [1e-17]}
     psi = _psi_from_spectrum(_DL, _DR, spectrum, 3)
     svd, keep, err = split(psi, _DL, _DR, 64)
     assert keep == {(1, 0): 1, (0, 1): 1}
-    assert err < 1e-30
+    assert abs(err - 8e-7 ** 2) < 1e-20      # sigma to ~1e-16 absolute
+    spectrum = {(1, 0): [0.9, 1e-6], (0, 1): [0.4, 0.0], (1, 1): [2e-6]}
+    psi = _psi_from_spectrum(_DL, _DR, spectrum, 3)
+    svd, keep, err = split(psi, _DL, _DR, 64)
+    assert keep == {(1, 0): 2, (0, 1): 1, (1, 1): 1}
+    assert err < 1e-24
 
 
 @pytest.mark.parametrize("direction,D", [(1, 400), (-1, 400), (1, 6), (-1, 6)])
