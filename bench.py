@@ -197,6 +197,8 @@ def main():
                     "in float64 (bsdmrg_set_split_policy)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device three times (calibrates the HBM byte counters)")
+    ap.add_argument("--no-streamed", action="store_true",
+                    help="skip the product with right operators streamed from pinned host memory")
     ap.add_argument("--quick", action="store_true",
                     help="products only: no Davidson, serializer, site step or CPU baseline (profiling runs)")
     args = ap.parse_args()
@@ -362,6 +364,7 @@ def main():
                           "policy": {"fp64_heavy": args.fp64_heavy},
                           "precisions": {PNAME[p]: {"ms": res[p]["ms"], "dominant_kernel": res[p]["dominant"],
                                                     "rel_err_vs_fp64": res[p]["rel_err"],
+                                                    "autotune": res[p]["tuned"],
                                                     "d_rayleigh_Eh": res[p]["d_rayleigh_Eh"],
                                                     "dominant_ms": res[p]["dom_ms"],
                                                     "per_kernel_ms_per_product": res[p]["per_kernel_ms_per_product"]}
@@ -493,6 +496,42 @@ def main():
         site_step = {"davidson_fp64_s": dav[B.FP64]["s"], "davidson_iters": dav[B.FP64]["iters"],
                      "truncate_s": t_tr, "kept": kept, "trunc_err": err_tr, "renormalize_s": t_ren}
         log(f"bench: truncation {t_tr:.2f} s (kept {kept}, err {err_tr:.2e}), renormalization {t_ren:.2f} s")
+    # the same product under a device budget below the two environment blocks:
+    # the right operators stream from pinned host memory chunk by chunk while
+    # the previous chunk computes (the form for environments beyond HBM)
+    streamed = {}
+    if args.only < 0 and not args.no_streamed:
+        if site_step:
+            B.bsdmrg_drop_block(ctx, B.LEFT, site + 1)
+            torch.cuda.empty_cache()
+        lbytes = B.bsdmrg_block_bytes(ctx, B.LEFT, site)
+        rbytes = B.bsdmrg_block_bytes(ctx, B.RIGHT, site + 2)
+        B.bsdmrg_set_hbm_budget(ctx, lbytes + rbytes // 2)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        B.bsdmrg_hpsi_prepare(ctx, site, chosen, args.ws_mb << 20, stream)
+        t_sprep = time.time() - t0
+        is_st, host_bytes, nchunks = B.bsdmrg_hpsi_streamed(ctx, site)
+        ys = torch.empty_like(x)
+        B.bsdmrg_hpsi(ctx, site, x, ys, chosen, stream)
+        torch.cuda.synchronize()
+        e0, e1 = ev(), ev()
+        e0.record(stream)
+        for _ in range(3):
+            B.bsdmrg_hpsi(ctx, site, x, ys, chosen, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_s = e0.elapsed_time(e1) / 3
+        streamed = {"streamed": is_st, "device_budget_bytes": lbytes + rbytes // 2,
+                    "left_block_bytes": lbytes, "right_block_bytes": rbytes,
+                    "host_bytes_per_product": host_bytes, "chunks": nchunks, "ms": ms_s,
+                    "ms_resident": ms, "host_GBps": host_bytes / (ms_s * 1e-3) / 1e9, "prepare_s": t_sprep,
+                    "rel_diff_vs_resident": float(torch.linalg.norm(ys - r["out"]) / torch.linalg.norm(r["out"]))}
+        log(f"bench: streamed right operators: {ms_s:.1f} ms per product ({host_bytes / 1e9:.1f} GB in "
+            f"{nchunks} chunks, {host_bytes / (ms_s * 1e-3) / 1e9:.1f} GB/s from pinned memory), "
+            f"resident {ms:.1f} ms; prepared in {t_sprep:.1f} s")
+        B.bsdmrg_set_hbm_budget(ctx, 0)
+        del ys
     stats = B.bsdmrg_stats(ctx)
 
     out = {
@@ -530,6 +569,7 @@ def main():
                        for p in res},
         "roofline": roof,
         "site_step": site_step,
+        "streamed_right_operators": streamed,
         "serializer": {"bytes": nbytes, "pack_ms": t_pack * 1e3, "pack_hbm_GBps": 2 * nbytes / t_pack / 1e9,
                        "d2h_GBps": d2h, "h2d_GBps": h2d, "offload": io["offload"], "prefetch": io["prefetch"],
                        "release_prefetch_roundtrip": roundtrip},
