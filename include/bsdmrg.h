@@ -376,6 +376,22 @@ int bsdmrg_pack_desc(int n, const bsdmrg_family_desc* fams, void* dst_dev, size_
 int bsdmrg_unpack_desc(int n, const bsdmrg_family_desc* fams, const void* src_dev, size_t bytes,
                        bsdmrg_stream_t stream);
 
+/* bsdmrg_pack_desc for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): allocates nothing.  The descriptor tables go through a
+ * file-scope host array into a file-scope device array of
+ * bsdmrg_noalloc_scratch_bytes() bytes (16 MiB) that each GPU holds until the
+ * process ends; EINVAL, before any launch, if the tables of the given
+ * families exceed it (about 32 bytes per block plus 24 per copy task).  The
+ * caller passes the families and dst_dev as for bsdmrg_pack_desc; the bytes
+ * written are identical.  Every call on one GPU uses that GPU's array and
+ * leaves its tables there; two calls that overlapped would race on it, so
+ * calls are serialized (a mutex across host threads) and each synchronizes
+ * `stream` before returning. */
+int bsdmrg_pack_desc_noalloc(int n, const bsdmrg_family_desc* fams, void* dst_dev, size_t cap,
+                             bsdmrg_stream_t stream);
+int bsdmrg_noalloc_scratch_bytes(size_t* bytes);
+
 /* The same for all operator families of a renormalized block. */
 int bsdmrg_serialized_size(bsdmrg_ctx* ctx, int side, int bond, size_t* bytes);
 int bsdmrg_pack(bsdmrg_ctx* ctx, int side, int bond, void* dst_dev, size_t cap, bsdmrg_stream_t stream);

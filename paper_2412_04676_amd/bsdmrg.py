@@ -126,6 +126,8 @@ _SIGS = {
     "bsdmrg_unpack_segments": ([c_vp, c_int, c_int, c_vp, c_sz, c_vp, c_sz, c_vp, c_vp], c_int),
     "bsdmrg_set_copy_workgroups": ([c_int], c_int),
     "bsdmrg_set_split_policy": ([c_vp, c_int], c_int),
+    "bsdmrg_pack_desc_noalloc": ([c_int, c_vp, c_vp, c_sz, c_vp], c_int),
+    "bsdmrg_noalloc_scratch_bytes": ([ctypes.POINTER(c_sz)], c_int),
     "bsdmrg_hpsi_streamed": ([c_vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_sz), ctypes.POINTER(c_int)], c_int),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -428,6 +430,17 @@ def bsdmrg_serialized_size_desc(fams):
 def bsdmrg_pack_desc(fams, dst, cap, stream=None):
     arr, keep = make_family_descs(fams)
     _check(_lib.bsdmrg_pack_desc(len(fams), arr, _ptr(dst), cap, _stream(stream)))
+
+
+def bsdmrg_pack_desc_noalloc(fams, dst, cap, stream=None):
+    arr, keep = make_family_descs(fams)
+    _check(_lib.bsdmrg_pack_desc_noalloc(len(fams), arr, _ptr(dst), cap, _stream(stream)))
+
+
+def bsdmrg_noalloc_scratch_bytes():
+    n = c_sz()
+    _check(_lib.bsdmrg_noalloc_scratch_bytes(ctypes.byref(n)))
+    return n.value
 
 
 def bsdmrg_unpack_desc(fams, src, nbytes, stream=None):

@@ -787,6 +787,24 @@ int bsdmrg_pack_desc(int n, const bsdmrg_family_desc* fams, void* dst, size_t ca
   });
 }
 
+static_assert(sizeof(FamilyDescIn) == sizeof(bsdmrg_family_desc), "family descriptor layouts differ");
+static_assert(offsetof(FamilyDescIn, data) == offsetof(bsdmrg_family_desc, data), "family descriptor layouts differ");
+static_assert(offsetof(FamilyDescIn, layer_stride) == offsetof(bsdmrg_family_desc, layer_stride),
+              "family descriptor layouts differ");
+
+int bsdmrg_pack_desc_noalloc(int n, const bsdmrg_family_desc* fams, void* dst, size_t cap, bsdmrg_stream_t stream) {
+  return guard([&] {
+    pack_desc_noalloc(n, reinterpret_cast<const FamilyDescIn*>(fams), dst, cap, S(stream));
+  });
+}
+
+int bsdmrg_noalloc_scratch_bytes(size_t* bytes) {
+  return guard([&] {
+    BSD_CHECK(bytes, BSDMRG_EINVAL, "NULL bytes");
+    *bytes = noalloc_scratch_bytes();
+  });
+}
+
 int bsdmrg_unpack_desc(int n, const bsdmrg_family_desc* fams, const void* src, size_t bytes, bsdmrg_stream_t stream) {
   return guard([&] {
     BSD_CHECK(src, BSDMRG_EINVAL, "NULL source");

@@ -457,6 +457,22 @@ size_t serial_pack_segments(const SerialPlan& d, void* staging, size_t staging_b
 int serial_unpack_segments(const SerialPlan& d, const void* host, size_t bytes, void* staging, size_t staging_bytes,
                            hipStream_t compute, hipStream_t side);   // synchronizing; 0 or 7 (nothing written)
 void set_copy_grid(int workgroups);   // 0: one workgroup per copy task
-
+// The caller-described family of the C ABI (same layout as bsdmrg_family_desc).
+struct FamilyDescIn {
+  uint64_t tag;
+  int32_t dq[2];
+  int32_t n_layers, n_blocks;
+  const int32_t* block_q;
+  const int32_t* rows;
+  const int32_t* cols;
+  const int32_t* ld;
+  const int64_t* elem_offset;
+  int64_t layer_stride;
+  void* data;
+};
+// Pack without any allocation (device tables in a file-scope array of
+// noalloc_scratch_bytes()); synchronizes s.
+void pack_desc_noalloc(int n, const FamilyDescIn* fams, void* dst, size_t cap, hipStream_t s);
+size_t noalloc_scratch_bytes();
 
 }  // namespace bsd

@@ -689,4 +689,129 @@ int serial_unpack_segments(const SerialPlan& d, const void* host, size_t bytes, 
 
 void set_copy_grid(int workgroups) { g_copy_grid = std::max(0, workgroups); }
 
+// ---------------------------------------------------------------- no-allocation pack
+// A pack of caller-described families that allocates nothing: the descriptor
+// tables live in a file-scope device array (one per GPU, kept until the
+// process ends) and are staged through a file-scope host array.  Calls are
+// serialized by a mutex and synchronize their stream before returning, so
+// every call finds the array free; the kernels overwrite every table entry
+// they read, so nothing has to start at zero.
+namespace {
+constexpr size_t kNoAllocScratch = (size_t)16 << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+std::mutex g_noalloc_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+alignas(256) unsigned char g_noalloc_host[kNoAllocScratch];
+
+size_t al256(size_t n) { return (n + 255) / 256 * 256; }
+}  // namespace
+
+size_t noalloc_scratch_bytes() { return kNoAllocScratch; }
+
+// the device address of this GPU's copy of `scratch` (looked up once per device)
+static void* scratch_on_current_device() {
+  int dev = 0;
+  BSD_HIP(hipGetDevice(&dev));
+  BSD_CHECK(dev >= 0 && dev < kMaxDevices, 1, "device index out of range");
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    BSD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    BSD_CHECK(p != nullptr, 5, "no device address for the scratch array");
+    g_scratch_dev[dev] = p;
+  }
+  return g_scratch_dev[dev];
+}
+
+void pack_desc_noalloc(int nf, const FamilyDescIn* fams, void* dst, size_t cap, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  BSD_CHECK(nf >= 0 && (nf == 0 || fams != nullptr), 1, "bad family list");
+  BSD_CHECK(dst != nullptr && ((uintptr_t)dst % 256) == 0, 1, "destination must be 256-byte aligned");
+  // sizes first: blocks, copy tasks and the exact stream size
+  int64_t nb = 0, nt = 0, payload = 0;
+  for (int f = 0; f < nf; ++f) {
+    const FamilyDescIn& x = fams[f];
+    BSD_CHECK(x.n_layers >= 0 && x.n_blocks >= 0, 1, "negative family sizes");
+    BSD_CHECK(x.n_blocks == 0 || (x.block_q && x.rows && x.cols && x.ld && x.elem_offset), 1, "missing block arrays");
+    BSD_CHECK(x.n_layers == 0 || x.n_blocks == 0 || x.data != nullptr, 1, "missing data pointer");
+    BSD_CHECK(((uintptr_t)x.data % 16) == 0, 1, "family data must be 16-byte aligned");
+    int64_t le = 0, maxend = 0;
+    for (int b = 0; b < x.n_blocks; ++b) {
+      BSD_CHECK(x.rows[b] >= 0 && x.cols[b] >= 0 && x.ld[b] >= x.cols[b] && x.elem_offset[b] >= 0, 1,
+                "bad block geometry");
+      le += (int64_t)x.rows[b] * x.cols[b];
+      if (x.rows[b] > 0)
+        maxend = std::max<int64_t>(maxend, x.elem_offset[b] + (int64_t)(x.rows[b] - 1) * x.ld[b] + x.cols[b]);
+    }
+    BSD_CHECK(x.n_layers <= 1 || x.layer_stride >= maxend, 1, "layers overlap");
+    nb += x.n_blocks;
+    payload += align256((int64_t)x.n_layers * le * 8);
+    family_tasks(f, x.n_layers, x.n_blocks, x.rows, x.cols, [&](const CopyTask&) { ++nt; });
+  }
+  const size_t bytes = (size_t)(align256(64 + 64 * (int64_t)nf + 32 * nb) + payload);
+  BSD_CHECK(cap >= bytes, 4, "destination smaller than the serialized size");
+  const size_t o_b = al256((size_t)nf * sizeof(FamDesc));
+  const size_t o_t = o_b + al256((size_t)nb * sizeof(BlkDesc));
+  const size_t o_eo = o_t + al256((size_t)nt * sizeof(CopyTask));
+  const size_t o_le = o_eo + al256((size_t)nb * sizeof(int64_t));
+  const size_t o_po = o_le + al256((size_t)nf * sizeof(int64_t));
+  const size_t end = o_po + al256((size_t)nf * sizeof(int64_t));
+  BSD_CHECK(end <= kNoAllocScratch, 1,
+            "descriptor tables (" + std::to_string(end) + " bytes) exceed the no-allocation scratch of " +
+                std::to_string(kNoAllocScratch) + " bytes; use bsdmrg_pack_desc");
+  unsigned char* dev = static_cast<unsigned char*>(scratch_on_current_device());
+  FamDesc* fd = reinterpret_cast<FamDesc*>(g_noalloc_host);
+  BlkDesc* bd = reinterpret_cast<BlkDesc*>(g_noalloc_host + o_b);
+  CopyTask* td = reinterpret_cast<CopyTask*>(g_noalloc_host + o_t);
+  int64_t bi = 0, ti = 0;
+  for (int f = 0; f < nf; ++f) {
+    const FamilyDescIn& x = fams[f];
+    FamDesc y;
+    y.tag = x.tag;
+    y.dqa = x.dq[0];
+    y.dqb = x.dq[1];
+    y.n_layers = x.n_layers;
+    y.n_blocks = x.n_blocks;
+    y.blk0 = (int)bi;
+    y.pad = 0;
+    y.base = static_cast<double*>(x.data);
+    y.layer_stride = x.layer_stride;
+    fd[f] = y;
+    for (int b = 0; b < x.n_blocks; ++b) {
+      BlkDesc z;
+      z.qa = x.block_q[2 * b];
+      z.qb = x.block_q[2 * b + 1];
+      z.rows = x.rows[b];
+      z.cols = x.cols[b];
+      z.ld = x.ld[b];
+      z.pad = 0;
+      z.src_off = x.elem_offset[b];
+      bd[bi++] = z;
+    }
+    family_tasks(f, x.n_layers, x.n_blocks, x.rows, x.cols, [&](const CopyTask& t) { td[ti++] = t; });
+  }
+  if (o_eo > 0) BSD_HIP(hipMemcpyAsync(dev, g_noalloc_host, o_eo, hipMemcpyHostToDevice, s));
+  const FamDesc* dfd = reinterpret_cast<const FamDesc*>(dev);
+  const BlkDesc* dbd = reinterpret_cast<const BlkDesc*>(dev + o_b);
+  const CopyTask* dtd = reinterpret_cast<const CopyTask*>(dev + o_t);
+  int64_t* eo = reinterpret_cast<int64_t*>(dev + o_eo);
+  int64_t* le = reinterpret_cast<int64_t*>(dev + o_le);
+  int64_t* po = reinterpret_cast<int64_t*>(dev + o_po);
+  if (nf > 0) {
+    hipLaunchKernelGGL(scan_blocks_kernel, dim3(nf), dim3(256), 0, s, dfd, dbd, eo, le);
+    BSD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(family_offsets_kernel, dim3(1), dim3(64), 0, s, dfd, nf, (int)nb, (const int64_t*)le, po);
+    BSD_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(write_meta_kernel, dim3(1), dim3(256), 0, s, dfd, dbd, nf, (int)nb, (const int64_t*)eo,
+                     (const int64_t*)le, (const int64_t*)po, (unsigned char*)dst, magic_word());
+  BSD_HIP(hipGetLastError());
+  if (nt > 0)
+    hipLaunchKernelGGL((copy_kernel<true>), dim3(copy_grid((int)nt)), dim3(256), 0, s, dtd, (int)nt, dfd, dbd,
+                       (const int64_t*)eo,
+                       (const int64_t*)le, (const int64_t*)po, (unsigned char*)dst, (const int*)nullptr, 0);
+  BSD_HIP(hipGetLastError());
+  BSD_HIP(hipStreamSynchronize(s));
+}
+
 }  // namespace bsd
