@@ -163,6 +163,8 @@ def kernel_names(prec):
         for c, sh in shapes.items():
             if c >= 4 and prec:
                 names[10 * ph + c] = f"wave_planes_kernel{sh[:-1]}, {3 * prec}, {2 - ph}>"
+            elif c == 0 and prec:
+                names[10 * ph + c] = f"wg_planes_kernel<{3 * prec}>"
             elif c >= 4:
                 names[10 * ph + c] = f"wave_gemm_kernel{sh}"
             else:
@@ -522,7 +524,9 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         ms_s = e0.elapsed_time(e1) / 3
+        t_h2d = host_bytes / (h2d * 1e9) * 1e3   # the same bytes copied alone at the measured H2D rate
         streamed = {"streamed": is_st, "device_budget_bytes": lbytes + rbytes // 2,
+                    "h2d_alone_ms": t_h2d, "hidden_frac": 1.0 - max(0.0, ms_s - ms) / t_h2d,
                     "left_block_bytes": lbytes, "right_block_bytes": rbytes,
                     "host_bytes_per_product": host_bytes, "chunks": nchunks, "ms": ms_s,
                     "ms_resident": ms, "host_GBps": host_bytes / (ms_s * 1e-3) / 1e9, "prepare_s": t_sprep,

@@ -196,9 +196,11 @@ int bsdmrg_hpsi_autotune(bsdmrg_ctx* ctx, int site, int precision, bsdmrg_stream
 
 /* Set the schedule of the prepared product at `site` for `precision` directly
  * (one candidate of bsdmrg_hpsi_autotune): the split-K target of waves per
- * launch (256 .. 2^20), XCD placement of locality groups (0/1) and, for
- * float64, the largest block dimension given wave tiles (>= 16; larger blocks
- * use workgroup tiles).  Rebuilds the phase-2 tile lists; results are
+ * launch (256 .. 2^20), XCD placement of locality groups (0/1) and the
+ * largest block dimension given wave tiles (>= 16): for float64 larger blocks
+ * use workgroup tiles; for the split precisions blocks larger in both
+ * dimensions use 64 x 64 workgroup tiles whose operands go through LDS (the
+ * default is 32; 2^30 keeps wave tiles everywhere).  Rebuilds the phase-2 tile lists; results are
  * identical up to the order of float64 additions.  ESTATE if not prepared. */
 int bsdmrg_hpsi_schedule(bsdmrg_ctx* ctx, int site, int precision, double target_waves, int xcd_order,
                          int wave_max);

@@ -571,6 +571,7 @@ int bsdmrg_hpsi_schedule(bsdmrg_ctx* ctx, int site, int precision, double target
     } else {
       b.target_waves = target_waves;
       b.xcd_order = xcd_order != 0;
+      b.wave_max = wave_max;
     }
     rebuild_phase2(p, a, b, precision == BSDMRG_FP64 ? 1 : 2);
   });

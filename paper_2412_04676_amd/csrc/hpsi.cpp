@@ -861,6 +861,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   // 8192 to 131072 waves): small products lose more to the part reduction
   // than they gain in parallelism, large ones the reverse
   plan->opts64.wave_max = 1 << 30;
+  plan->opts_planes.wave_max = 32;   // blocks above 32 x 32: 64 x 64 workgroup tiles
   plan->opts64.target_waves = plan->opts_planes.target_waves =
       std::min(131072.0, std::max(8192.0, (double)plan->nseg / 128.0));
   rebuild_phase2(*plan, plan->opts64, plan->opts_planes, 3);
@@ -997,9 +998,10 @@ TuneResult autotune_hpsi(HpsiPlan& plan, int precision, hipStream_t s) {
           a.xcd_order = xcd;
           a.wave_max = wm;
         } else {
-          if (wm != 64) continue;   // planes always use wave tiles
+          if (wm != 32 && wm != (1 << 30)) continue;   // workgroup tiles above 32, or wave tiles only
           b.target_waves = tw;
           b.xcd_order = xcd;
+          b.wave_max = wm;
         }
         cand.push_back({a, b});
       }

@@ -355,8 +355,8 @@ struct SplitTask {
 void launch_split_planes(const SplitTask* tasks, int n, const GBases& b, hipStream_t s);
 
 struct GemmBuildOpts {
-  bool wave_tiles = true;      // float64 lists: blocks up to wave_max x wave_max get wave tiles
-  int wave_max = 64;
+  bool wave_tiles = true;      // float64 lists: blocks up to wave_max x wave_max get wave tiles;
+  int wave_max = 64;           // plane lists: blocks above wave_max in both dimensions get 64 x 64 workgroup tiles
   bool split_k = true;         // cut long tiles so that every launch fills the device
   double target_waves = 8192;  // split-K: about this many waves per launch ...
   double min_part_work = 640;  // ... with parts of at least this work (sum of K + 16 per segment)

@@ -557,6 +557,165 @@ wave_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __
       }
 }
 
+// ---------------------------------------------------------------- workgroup tiles on planes
+// One 64 x 64 tile of a float64 output (C = beta C + sum) per workgroup of four
+// waves.  Wave w computes the 32 x 32 quadrant (w / 2, w % 2) as in
+// wave_planes_kernel, but the operands of a step (four 16-row panels of A and
+// four 16-column panels of B, every bf16 part) are fetched once for the four
+// waves: each wave copies two panels straight from global memory into a ring
+// of LDS stages (global_load_lds, 16 bytes per lane, no registers), kStages - 1
+// steps ahead of the step being multiplied.  A lane past the block, past K or
+// on an identity operand copies from a zero page instead, so every wave issues
+// the same number of copies per step and a fixed vmcnt bound tells when its
+// copies of a step have landed.  One barrier per step: after it, every copy of
+// the step is in LDS and every wave has finished reading the stage the next
+// copies overwrite.
+__device__ __attribute__((aligned(16))) unsigned char g_zero_page[1024];
+
+template <int NPL>
+struct WgRing {
+  static constexpr int kStages = NPL == 2 ? 4 : 3;
+  static constexpr int kCopies = 2 * NPL;                // per wave and step
+  static constexpr int kStage = 8 * NPL * 1024;          // 4 A + 4 B panels, every part
+};
+
+// s_waitcnt vmcnt(n) (expcnt and lgkmcnt left alone), then lgkmcnt(0) and a
+// workgroup barrier; the memory clobber keeps the compiler from moving LDS
+// accesses across it
+template <int N>
+__device__ __forceinline__ void wg_step_barrier() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <int NPROD>
+__global__ void __launch_bounds__(256)
+wg_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __restrict__ segs_g, GBases bases) {
+  constexpr int NPL = NPROD == 6 ? 3 : 2;
+  typedef WgRing<NPL> R;
+  constexpr int S = R::kStages;
+  __shared__ __attribute__((aligned(16))) unsigned char ring[S * R::kStage];
+  const cseg_ptr segs = (cseg_ptr)segs_g;
+  const ctile_ptr tiles = (ctile_ptr)tiles_g;
+  const int ti = blockIdx.x;
+  if (ti >= ntiles) return;   // the whole workgroup leaves together
+  const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int r16 = lane & 15, q = lane >> 4;
+  const GTile tile = ld_tile(tiles, ti);
+  const int M = tile.M, N = tile.N, m0 = tile.m0, n0 = tile.n0, seg0 = tile.seg0, nst = tile.nseg;
+
+  // copy role: op 0 copies A panels (rows), op 1 B panels (columns); panels 2h, 2h + 1
+  const int op = wave >> 1, h = wave & 1;
+  const int lim = op == 0 ? M - m0 : N - n0;
+  const int org = op == 0 ? m0 : n0;
+  bool lok[2];
+  int lrow[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    lok[u] = (2 * h + u) * 16 + r16 < lim;
+    lrow[u] = org + (2 * h + u) * 16 + r16;
+  }
+  const unsigned char* zero = g_zero_page + lane * 16;
+  auto issue = [&](const GSeg& g, int k) {
+    unsigned char* dst = ring + (k % S) * R::kStage + (op * 4 + 2 * h) * NPL * 1024;
+    const int nch = (g.K + 7) >> 3;
+    const bool skip = op == 0 && (g.flags & kIdentA);
+    const unsigned char* base = reinterpret_cast<const unsigned char*>(op == 0 ? g.A : g.B);
+    const int64_t ld = op == 0 ? g.lda : g.ldb;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const bool ok = lok[u] && q < nch && !skip;
+      const unsigned char* src = ok ? base + plane_off(lrow[u], q, 0, ld) * 2 : zero;
+#pragma unroll
+      for (int pl = 0; pl < NPL; ++pl)
+        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void*>(src + (ok ? pl * 128 : 0)),
+                                         (__attribute__((address_space(3))) void*)(dst + (u * NPL + pl) * 1024),
+                                         16, 0, 0);
+    }
+  };
+
+  // multiply role: quadrant (qm, qn) of the tile
+  const int qm = wave >> 1, qn = wave & 1;
+  const int mt = min(32, M - m0 - 32 * qm), nt = min(32, N - n0 - 32 * qn);
+  const bool active = mt > 0 && nt > 0;
+  const int ni = active ? (mt + 15) >> 4 : 0, nj = active ? (nt + 15) >> 4 : 0;
+  float4_t t[2][2];
+  double4_t acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      t[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+      acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
+    }
+
+  // prologue: the first S - 1 steps in flight (a tile without steps reads no
+  // descriptor and writes beta C)
+  if (nst > 0) {
+#pragma unroll
+  for (int k = 0; k < S - 1; ++k)
+    if (k < nst) issue(ld_seg(segs, seg0 + k), k);
+  GSeg gl = ld_seg(segs, seg0 + min(S - 1, nst - 1));   // copies of iteration 0
+  GSeg gc = ld_seg(segs, seg0);                          // multiply of iteration 0
+  for (int s = 0; s < nst; ++s) {
+    // this wave's copies of step s have landed (later steps may still be in flight)
+    const int ahead = min(nst - 1 - s, S - 2);
+    if (ahead >= 2) wg_step_barrier<2 * R::kCopies>();
+    else if (ahead == 1) wg_step_barrier<R::kCopies>();
+    else wg_step_barrier<0>();
+    if (s + S - 1 < nst) issue(gl, s + S - 1);
+    const GSeg cur = gc;
+    gc = ld_seg(segs, seg0 + min(s + 1, nst - 1));
+    gl = ld_seg(segs, seg0 + min(s + S, nst - 1));
+    if (active) {
+      const unsigned char* st = ring + (s % S) * R::kStage + lane * 16;
+      u32x4_t a[2][NPL], b[2][NPL];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int pl = 0; pl < NPL; ++pl) {
+          a[i][pl] = *reinterpret_cast<const u32x4_t*>(st + ((2 * qm + i) * NPL + pl) * 1024);
+          b[i][pl] = *reinterpret_cast<const u32x4_t*>(st + ((4 + 2 * qn + i) * NPL + pl) * 1024);
+        }
+      PSeg d;
+      d.nch = (cur.K + 7) >> 3;
+      d.kbase = (cur.flags >> kStepPassShift) * 32;
+      d.m0 = m0 + 32 * qm;
+      d.mt = mt;
+      if (cur.flags & kIdentA) ident_rows<2, NPL>(d, r16, q, a);
+      planes_mfma<2, NPL, NPROD>(a, b, t, cur.flags & kStepFresh, ni, nj);
+      if (cur.flags & kStepEnd) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[i][j][v] += cur.alpha * (double)t[i][j][v];
+      }
+    }
+  }
+  }
+  if (!active) return;
+  double* C = const_cast<double*>(resolve(tile.C, bases)) + (int64_t)(32 * qm) * tile.ldc + 32 * qn;
+  const double beta = tile.beta;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = i * 16 + 4 * q + v;
+        const int c = j * 16 + r16;
+        if (r < mt && c < nt) {
+          double* p = C + (int64_t)r * tile.ldc + c;
+          double x = acc[i][j][v];
+          if (beta != 0.0) x += beta * (*p);
+          *p = x;
+        }
+      }
+}
+
 template <int TW, int OUTP>
 static void launch_planes_tw(const GTile* tiles, int ntiles, const GSeg* segs, const GBases& b, hipStream_t s,
                              int precision) {
@@ -580,9 +739,15 @@ static void launch_planes_tw(const GTile* tiles, int ntiles, const GSeg* segs, c
 void launch_planes_gemm(const GTile* tiles, int ntiles, int shape, const GSeg* segs, const GBases& b,
                         hipStream_t s, int precision, bool planes_out) {
   if (ntiles <= 0) return;
-  BSD_CHECK(shape == 4 || shape == 5, 1, "plane operands use wave tiles only");
+  BSD_CHECK(shape == 0 || shape == 4 || shape == 5, 1, "plane operands use wave or 64 x 64 workgroup tiles");
   BSD_CHECK(precision == 1 || precision == 2, 1, "plane operands are for split precision only");
-  if (shape == 4) {
+  if (shape == 0) {
+    BSD_CHECK(!planes_out, 1, "workgroup plane tiles write float64 only");
+    if (precision == 1)
+      hipLaunchKernelGGL(wg_planes_kernel<3>, dim3(ntiles), dim3(256), 0, s, tiles, ntiles, segs, b);
+    else
+      hipLaunchKernelGGL(wg_planes_kernel<6>, dim3(ntiles), dim3(256), 0, s, tiles, ntiles, segs, b);
+  } else if (shape == 4) {
     if (planes_out) launch_planes_tw<16, 1>(tiles, ntiles, segs, b, s, precision);
     else launch_planes_tw<16, 0>(tiles, ntiles, segs, b, s, precision);
   } else {

@@ -300,8 +300,11 @@ def test_dropped_blocks_are_rebuilt_from_the_nearest_one():
     B.bsdmrg_destroy(ctx2)
 
 
+# split precisions: wave_max 16 puts nearly every block on 64 x 64 workgroup
+# tiles (operands through LDS), 2^30 keeps wave tiles everywhere
 @pytest.mark.parametrize("precision,tw,xcd,wm", [(0, 4096, 0, 1 << 30), (0, 32768, 1, 16), (0, 8192, 1, 128),
-                                                 (2, 4096, 0, 64), (1, 32768, 1, 64)])
+                                                 (2, 4096, 0, 64), (1, 32768, 1, 64), (1, 8192, 1, 16),
+                                                 (2, 16384, 0, 16), (1, 8192, 1, 1 << 30), (2, 131072, 1, 1 << 30)])
 def test_explicit_schedule_keeps_the_product(precision, tw, xcd, wm):
     import torch
     from paper_2412_04676_amd import bsdmrg as B
