@@ -164,7 +164,7 @@ def kernel_names(prec):
             if c >= 4 and prec:
                 names[10 * ph + c] = f"wave_planes_kernel{sh[:-1]}, {3 * prec}, {2 - ph}>"
             elif c == 0 and prec:
-                names[10 * ph + c] = f"wg_planes_kernel<{3 * prec}>"
+                names[10 * ph + c] = f"wg_planes_kernel<{3 * prec}, {2 - ph}>"
             elif c >= 4:
                 names[10 * ph + c] = f"wave_gemm_kernel{sh}"
             else:

@@ -555,7 +555,7 @@ void GemmPlan::build(const std::vector<GemmProblem>& probs, const GemmBuildOpts&
     // workgroup tile with the smallest padded area, then fewer tiles
     int cls = 0;
     int64_t best = -1;
-    if (plane_operands && !opts.plane_output && p.M > opts.wave_max && p.N > opts.wave_max) {
+    if (plane_operands && p.M > opts.wave_max && p.N > opts.wave_max) {
       cls = 0;   // 64 x 64 workgroup tile on planes (operands shared through LDS)
       best = 0;
     } else if (plane_operands || (wave_tiles && p.M <= opts.wave_max && p.N <= opts.wave_max)) {

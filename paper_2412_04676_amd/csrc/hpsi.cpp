@@ -808,6 +808,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
       plan->phase1[k]->build(p1[k], o);
     } else if (j % 3 == 1) {
       o.plane_output = true;
+      o.wave_max = 32;   // blocks above 32 x 32: 64 x 64 workgroup tiles
       plan->phase1s[k]->build(p1s[k], o);
     } else {
       plan->phase1h[k]->build(p1h[k], o);

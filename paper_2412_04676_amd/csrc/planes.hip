@@ -376,8 +376,10 @@ planes_persistent_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GS
                                                 rc, o, 0, 0);
           __builtin_amdgcn_raw_buffer_store_b64(u32x2_t{m[0] | ((unsigned)m[1] << 16), m[2] | ((unsigned)m[3] << 16)},
                                                 rc, o + 128, 0, 0);
-          __builtin_amdgcn_raw_buffer_store_b64(u32x2_t{l[0] | ((unsigned)l[1] << 16), l[2] | ((unsigned)l[3] << 16)},
-                                                rc, o + 256, 0, 0);
+          // three products never read the l part
+          if (NPL == 3)
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2_t{l[0] | ((unsigned)l[1] << 16), l[2] | ((unsigned)l[3] << 16)},
+                                                  rc, o + 256, 0, 0);
         }
     } else {
       double* C = const_cast<double*>(resolve(e.C, bases));
@@ -408,7 +410,7 @@ planes_persistent_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GS
       const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(nullptr, (short)0, 0, kBufFlags);
       const u32x2_t z = {0u, 0u};
 #pragma unroll
-      for (int k = 0; k < NI * NI * 3; ++k) __builtin_amdgcn_raw_buffer_store_b64(z, rc, kBufOut, 0, 0);
+      for (int k = 0; k < NI * NI * NPL; ++k) __builtin_amdgcn_raw_buffer_store_b64(z, rc, kBufOut, 0, 0);
     }
   };
   clear_acc();
@@ -572,9 +574,14 @@ wave_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __
 // copies overwrite.
 __device__ __attribute__((aligned(16))) unsigned char g_zero_page[1024];
 
+// Two stages: the copies of the next step run during this step's MFMAs.  More
+// stages hide more latency per workgroup but cost LDS, and so workgroups per CU
+// (at L=76 D=4096: 4 stages 364 ms, 3 stages 272-283 ms, 2 stages 265 ms of
+// BF16X3 phase 2); two 16 KB (BF16X3) or 24 KB (BF16X6) stages keep five or
+// three workgroups on a CU.
 template <int NPL>
 struct WgRing {
-  static constexpr int kStages = NPL == 2 ? 4 : 3;
+  static constexpr int kStages = 2;
   static constexpr int kCopies = 2 * NPL;                // per wave and step
   static constexpr int kStage = 8 * NPL * 1024;          // 4 A + 4 B panels, every part
 };
@@ -589,7 +596,10 @@ __device__ __forceinline__ void wg_step_barrier() {
   asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-template <int NPROD>
+// OUTP 0: C is float64 (C = beta C + sum).  OUTP 1: the sum is split and
+// stored as the planes of C^T, as planes_persistent_kernel stores it (a tile
+// is one segment there, so the float64 sum holds the float32 one exactly).
+template <int NPROD, int OUTP>
 __global__ void __launch_bounds__(256)
 wg_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __restrict__ segs_g, GBases bases) {
   constexpr int NPL = NPROD == 6 ? 3 : 2;
@@ -617,8 +627,8 @@ wg_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __re
     lrow[u] = org + (2 * h + u) * 16 + r16;
   }
   const unsigned char* zero = g_zero_page + lane * 16;
-  auto issue = [&](const GSeg& g, int k) {
-    unsigned char* dst = ring + (k % S) * R::kStage + (op * 4 + 2 * h) * NPL * 1024;
+  auto issue = [&](const GSeg& g, int stage) {
+    unsigned char* dst = ring + stage * R::kStage + (op * 4 + 2 * h) * NPL * 1024;
     const int nch = (g.K + 7) >> 3;
     const bool skip = op == 0 && (g.flags & kIdentA);
     const unsigned char* base = reinterpret_cast<const unsigned char*>(op == 0 ? g.A : g.B);
@@ -650,53 +660,116 @@ wg_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __re
       acc[i][j] = double4_t{0.0, 0.0, 0.0, 0.0};
     }
 
-  // prologue: the first S - 1 steps in flight (a tile without steps reads no
-  // descriptor and writes beta C)
+  // The loop runs in blocks of S steps, unrolled, so the stage of every step
+  // and the ring of descriptors of the steps in flight (K, flags, alpha:
+  // copied when the step's copies are issued) are fixed at compile time; one
+  // descriptor is read per step, a step ahead of its use.  A tile without
+  // steps reads no descriptor and writes beta C.
   if (nst > 0) {
+    int dK[S], dF[S];
+    double dA[S];
 #pragma unroll
-  for (int k = 0; k < S - 1; ++k)
-    if (k < nst) issue(ld_seg(segs, seg0 + k), k);
-  GSeg gl = ld_seg(segs, seg0 + min(S - 1, nst - 1));   // copies of iteration 0
-  GSeg gc = ld_seg(segs, seg0);                          // multiply of iteration 0
-  for (int s = 0; s < nst; ++s) {
-    // this wave's copies of step s have landed (later steps may still be in flight)
-    const int ahead = min(nst - 1 - s, S - 2);
-    if (ahead >= 2) wg_step_barrier<2 * R::kCopies>();
-    else if (ahead == 1) wg_step_barrier<R::kCopies>();
-    else wg_step_barrier<0>();
-    if (s + S - 1 < nst) issue(gl, s + S - 1);
-    const GSeg cur = gc;
-    gc = ld_seg(segs, seg0 + min(s + 1, nst - 1));
-    gl = ld_seg(segs, seg0 + min(s + S, nst - 1));
-    if (active) {
-      const unsigned char* st = ring + (s % S) * R::kStage + lane * 16;
-      u32x4_t a[2][NPL], b[2][NPL];
+    for (int k = 0; k < S; ++k) {
+      dK[k] = 0;
+      dF[k] = 0;
+      dA[k] = 0.0;
+    }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+    for (int k = 0; k < S - 1; ++k)
+      if (k < nst) {
+        const GSeg g = ld_seg(segs, seg0 + k);
+        issue(g, k);
+        dK[k] = g.K;
+        dF[k] = g.flags;
+        dA[k] = g.alpha;
+      }
+    GSeg gl = ld_seg(segs, seg0 + min(S - 1, nst - 1));   // copies of the first iteration
+    for (int s0 = 0; s0 < nst; s0 += S) {
 #pragma unroll
-        for (int pl = 0; pl < NPL; ++pl) {
-          a[i][pl] = *reinterpret_cast<const u32x4_t*>(st + ((2 * qm + i) * NPL + pl) * 1024);
-          b[i][pl] = *reinterpret_cast<const u32x4_t*>(st + ((4 + 2 * qn + i) * NPL + pl) * 1024);
+      for (int j = 0; j < S; ++j) {
+        const int s = s0 + j;
+        if (s >= nst) break;
+        // this wave's copies of step s have landed (later steps may still be in flight)
+        const int ahead = min(nst - 1 - s, S - 2);
+        if (ahead >= 2) wg_step_barrier<2 * R::kCopies>();
+        else if (ahead == 1) wg_step_barrier<R::kCopies>();
+        else wg_step_barrier<0>();
+        const int jn = (j + S - 1) % S;   // stage of step s + S - 1
+        const bool more = s + S - 1 < nst;
+        if (more) {
+          issue(gl, jn);
+          dK[jn] = gl.K;
+          dF[jn] = gl.flags;
+          dA[jn] = gl.alpha;
         }
-      PSeg d;
-      d.nch = (cur.K + 7) >> 3;
-      d.kbase = (cur.flags >> kStepPassShift) * 32;
-      d.m0 = m0 + 32 * qm;
-      d.mt = mt;
-      if (cur.flags & kIdentA) ident_rows<2, NPL>(d, r16, q, a);
-      planes_mfma<2, NPL, NPROD>(a, b, t, cur.flags & kStepFresh, ni, nj);
-      if (cur.flags & kStepEnd) {
+        if (active) {
+          const unsigned char* st = ring + j * R::kStage + lane * 16;
+          u32x4_t a[2][NPL], b[2][NPL];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
+            for (int pl = 0; pl < NPL; ++pl) {
+              a[i][pl] = *reinterpret_cast<const u32x4_t*>(st + ((2 * qm + i) * NPL + pl) * 1024);
+              b[i][pl] = *reinterpret_cast<const u32x4_t*>(st + ((4 + 2 * qn + i) * NPL + pl) * 1024);
+            }
+          const int fl = dF[j];
+          if (fl & kIdentA) {
+            PSeg d;
+            d.nch = (dK[j] + 7) >> 3;
+            d.kbase = (fl >> kStepPassShift) * 32;
+            d.m0 = m0 + 32 * qm;
+            d.mt = mt;
+            ident_rows<2, NPL>(d, r16, q, a);
+          }
+          planes_mfma<2, NPL, NPROD>(a, b, t, fl & kStepFresh, ni, nj);
+          if (fl & kStepEnd) {
+            const double al = dA[j];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[i][j][v] += cur.alpha * (double)t[i][j][v];
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[i][jj][v] += al * (double)t[i][jj][v];
+          }
+        }
+        // the next step's copy descriptor: read after this step's LDS reads and
+        // MFMAs are issued, so the scalar load overlaps them instead of holding
+        // up the LDS reads (both count in lgkmcnt)
+        if (more) gl = ld_seg(segs, seg0 + min(s + S, nst - 1));
       }
     }
   }
-  }
   if (!active) return;
+  if (OUTP == 1) {
+    // planes of C^T: quadrant rows are K indices (chunks 4 qm ..), its columns
+    // plane rows (32 qn ..); the four values a lane holds are four consecutive
+    // K values of one chunk (mt is a multiple of 8)
+    typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<double*>(resolve(tile.C, bases)), (short)0, 0x7FFFFFFF, kBufFlags);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int r = i * 16 + 4 * q;
+        const int c = j * 16 + r16;
+        unsigned short hh[4], mm[4], ll[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) split3f((float)acc[i][j][v], hh[v], mm[v], ll[v]);
+        if (r < mt && c < nt) {
+          const unsigned o =
+              (unsigned)((plane_off(32 * qn + c, (32 * qm + r) >> 3, 0, tile.ldc) + (r & 7)) * 2);
+          __builtin_amdgcn_raw_buffer_store_b64(
+              u32x2_t{hh[0] | ((unsigned)hh[1] << 16), hh[2] | ((unsigned)hh[3] << 16)}, rc, o, 0, 0);
+          __builtin_amdgcn_raw_buffer_store_b64(
+              u32x2_t{mm[0] | ((unsigned)mm[1] << 16), mm[2] | ((unsigned)mm[3] << 16)}, rc, o + 128, 0, 0);
+          if (NPL == 3)   // three products never read the l part
+            __builtin_amdgcn_raw_buffer_store_b64(
+                u32x2_t{ll[0] | ((unsigned)ll[1] << 16), ll[2] | ((unsigned)ll[3] << 16)}, rc, o + 256, 0, 0);
+        }
+      }
+    return;
+  }
   double* C = const_cast<double*>(resolve(tile.C, bases)) + (int64_t)(32 * qm) * tile.ldc + 32 * qn;
   const double beta = tile.beta;
 #pragma unroll
@@ -742,11 +815,17 @@ void launch_planes_gemm(const GTile* tiles, int ntiles, int shape, const GSeg* s
   BSD_CHECK(shape == 0 || shape == 4 || shape == 5, 1, "plane operands use wave or 64 x 64 workgroup tiles");
   BSD_CHECK(precision == 1 || precision == 2, 1, "plane operands are for split precision only");
   if (shape == 0) {
-    BSD_CHECK(!planes_out, 1, "workgroup plane tiles write float64 only");
-    if (precision == 1)
-      hipLaunchKernelGGL(wg_planes_kernel<3>, dim3(ntiles), dim3(256), 0, s, tiles, ntiles, segs, b);
-    else
-      hipLaunchKernelGGL(wg_planes_kernel<6>, dim3(ntiles), dim3(256), 0, s, tiles, ntiles, segs, b);
+    if (planes_out) {
+      if (precision == 1)
+        hipLaunchKernelGGL((wg_planes_kernel<3, 1>), dim3(ntiles), dim3(256), 0, s, tiles, ntiles, segs, b);
+      else
+        hipLaunchKernelGGL((wg_planes_kernel<6, 1>), dim3(ntiles), dim3(256), 0, s, tiles, ntiles, segs, b);
+    } else {
+      if (precision == 1)
+        hipLaunchKernelGGL((wg_planes_kernel<3, 0>), dim3(ntiles), dim3(256), 0, s, tiles, ntiles, segs, b);
+      else
+        hipLaunchKernelGGL((wg_planes_kernel<6, 0>), dim3(ntiles), dim3(256), 0, s, tiles, ntiles, segs, b);
+    }
   } else if (shape == 4) {
     if (planes_out) launch_planes_tw<16, 1>(tiles, ntiles, segs, b, s, precision);
     else launch_planes_tw<16, 0>(tiles, ntiles, segs, b, s, precision);
