@@ -1028,9 +1028,15 @@ TuneResult autotune_hpsi(HpsiPlan& plan, int precision, hipStream_t s) {
   TuneResult res;
   res.n_candidates = (int)cand.size();
   double best = 1e300;
+  const bool verbose = std::getenv("BSDMRG_VERBOSE") != nullptr;
   for (size_t i = 0; i < cand.size(); ++i) {
     rebuild_phase2(plan, cand[i].first, cand[i].second, which);
     const double ms = time_it();
+    if (verbose) {
+      const GemmBuildOpts& o = precision == 0 ? cand[i].first : cand[i].second;
+      std::fprintf(stderr, "autotune: candidate %zu/%zu (waves %.0f, xcd %d, wave_max %d): %.3f ms\n", i + 1,
+                   cand.size(), o.target_waves, (int)o.xcd_order, o.wave_max, ms);
+    }
     if (i == 0) res.default_ms = ms;
     if (ms < best) {
       best = ms;

@@ -599,6 +599,9 @@ __device__ __forceinline__ void wg_step_barrier() {
 // OUTP 0: C is float64 (C = beta C + sum).  OUTP 1: the sum is split and
 // stored as the planes of C^T, as planes_persistent_kernel stores it (a tile
 // is one segment there, so the float64 sum holds the float32 one exactly).
+// lgkmcnt(0) (this wave's LDS reads are in registers), then a workgroup barrier
+__device__ __forceinline__ void wg_read_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <int NPROD, int OUTP>
 __global__ void __launch_bounds__(256)
 wg_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __restrict__ segs_g, GBases bases) {
@@ -665,77 +668,160 @@ wg_planes_kernel(const GTile* __restrict__ tiles_g, int ntiles, const GSeg* __re
   // copied when the step's copies are issued) are fixed at compile time; one
   // descriptor is read per step, a step ahead of its use.  A tile without
   // steps reads no descriptor and writes beta C.
-  if (nst > 0) {
-    int dK[S], dF[S];
-    double dA[S];
+  if constexpr (OUTP == 0) {
+    // long K (phase 2): one barrier per step, S - 1 steps in flight; the MFMAs
+    // read their operands straight from the stage
+    if (nst > 0) {
+      int dK[S], dF[S];
+      double dA[S];
 #pragma unroll
-    for (int k = 0; k < S; ++k) {
-      dK[k] = 0;
-      dF[k] = 0;
-      dA[k] = 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < S - 1; ++k)
-      if (k < nst) {
-        const GSeg g = ld_seg(segs, seg0 + k);
-        issue(g, k);
-        dK[k] = g.K;
-        dF[k] = g.flags;
-        dA[k] = g.alpha;
+      for (int k = 0; k < S; ++k) {
+        dK[k] = 0;
+        dF[k] = 0;
+        dA[k] = 0.0;
       }
-    GSeg gl = ld_seg(segs, seg0 + min(S - 1, nst - 1));   // copies of the first iteration
-    for (int s0 = 0; s0 < nst; s0 += S) {
 #pragma unroll
-      for (int j = 0; j < S; ++j) {
-        const int s = s0 + j;
-        if (s >= nst) break;
-        // this wave's copies of step s have landed (later steps may still be in flight)
-        const int ahead = min(nst - 1 - s, S - 2);
-        if (ahead >= 2) wg_step_barrier<2 * R::kCopies>();
-        else if (ahead == 1) wg_step_barrier<R::kCopies>();
-        else wg_step_barrier<0>();
-        const int jn = (j + S - 1) % S;   // stage of step s + S - 1
-        const bool more = s + S - 1 < nst;
-        if (more) {
-          issue(gl, jn);
-          dK[jn] = gl.K;
-          dF[jn] = gl.flags;
-          dA[jn] = gl.alpha;
+      for (int k = 0; k < S - 1; ++k)
+        if (k < nst) {
+          const GSeg g = ld_seg(segs, seg0 + k);
+          issue(g, k);
+          dK[k] = g.K;
+          dF[k] = g.flags;
+          dA[k] = g.alpha;
         }
-        if (active) {
-          const unsigned char* st = ring + j * R::kStage + lane * 16;
-          u32x4_t a[2][NPL], b[2][NPL];
+      GSeg gl = ld_seg(segs, seg0 + min(S - 1, nst - 1));   // copies of the first iteration
+      for (int s0 = 0; s0 < nst; s0 += S) {
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int pl = 0; pl < NPL; ++pl) {
-              a[i][pl] = *reinterpret_cast<const u32x4_t*>(st + ((2 * qm + i) * NPL + pl) * 1024);
-              b[i][pl] = *reinterpret_cast<const u32x4_t*>(st + ((4 + 2 * qn + i) * NPL + pl) * 1024);
-            }
-          const int fl = dF[j];
-          if (fl & kIdentA) {
-            PSeg d;
-            d.nch = (dK[j] + 7) >> 3;
-            d.kbase = (fl >> kStepPassShift) * 32;
-            d.m0 = m0 + 32 * qm;
-            d.mt = mt;
-            ident_rows<2, NPL>(d, r16, q, a);
+        for (int j = 0; j < S; ++j) {
+          const int s = s0 + j;
+          if (s >= nst) break;
+          // this wave's copies of step s have landed (later steps may still be in flight)
+          const int ahead = min(nst - 1 - s, S - 2);
+          if (ahead >= 2) wg_step_barrier<2 * R::kCopies>();
+          else if (ahead == 1) wg_step_barrier<R::kCopies>();
+          else wg_step_barrier<0>();
+          const int jn = (j + S - 1) % S;   // stage of step s + S - 1
+          const bool more = s + S - 1 < nst;
+          if (more) {
+            issue(gl, jn);
+            dK[jn] = gl.K;
+            dF[jn] = gl.flags;
+            dA[jn] = gl.alpha;
           }
-          planes_mfma<2, NPL, NPROD>(a, b, t, fl & kStepFresh, ni, nj);
-          if (fl & kStepEnd) {
-            const double al = dA[j];
+          if (active) {
+            const unsigned char* st = ring + j * R::kStage + lane * 16;
+            u32x4_t a[2][NPL], b[2][NPL];
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
-              for (int jj = 0; jj < 2; ++jj)
+              for (int pl = 0; pl < NPL; ++pl) {
+                a[i][pl] = *reinterpret_cast<const u32x4_t*>(st + ((2 * qm + i) * NPL + pl) * 1024);
+                b[i][pl] = *reinterpret_cast<const u32x4_t*>(st + ((4 + 2 * qn + i) * NPL + pl) * 1024);
+              }
+            const int fl = dF[j];
+            if (fl & kIdentA) {
+              PSeg d;
+              d.nch = (dK[j] + 7) >> 3;
+              d.kbase = (fl >> kStepPassShift) * 32;
+              d.m0 = m0 + 32 * qm;
+              d.mt = mt;
+              ident_rows<2, NPL>(d, r16, q, a);
+            }
+            planes_mfma<2, NPL, NPROD>(a, b, t, fl & kStepFresh, ni, nj);
+            if (fl & kStepEnd) {
+              const double al = dA[j];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[i][jj][v] += al * (double)t[i][jj][v];
+              for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+                  for (int v = 0; v < 4; ++v) acc[i][jj][v] += al * (double)t[i][jj][v];
+            }
           }
+          // the next step's copy descriptor: read after this step's LDS reads and
+          // MFMAs are issued, so the scalar load overlaps them instead of holding
+          // up the LDS reads (both count in lgkmcnt)
+          if (more) gl = ld_seg(segs, seg0 + min(s + S, nst - 1));
         }
-        // the next step's copy descriptor: read after this step's LDS reads and
-        // MFMAs are issued, so the scalar load overlaps them instead of holding
-        // up the LDS reads (both count in lgkmcnt)
-        if (more) gl = ld_seg(segs, seg0 + min(s + S, nst - 1));
+      }
+    }
+  } else {
+    // short K (phase 1, one segment per tile): a step reads its operands from
+    // its stage into registers, and once every wave has read them (second
+    // barrier) the copies of step s + S go into that stage while the MFMAs
+    // run, so S steps are in flight with S stages (138 vs 148 ms of BF16X3
+    // phase 1 at L=76 D=4096; the second barrier costs phase 2 more than the
+    // extra step in flight gains it)
+    if (nst > 0) {
+      int dK[S], dF[S];
+      double dA[S];
+#pragma unroll
+      for (int k = 0; k < S; ++k) {
+        dK[k] = 0;
+        dF[k] = 0;
+        dA[k] = 0.0;
+        if (k < nst) {
+          const GSeg g = ld_seg(segs, seg0 + k);
+          issue(g, k);
+          dK[k] = g.K;
+          dF[k] = g.flags;
+          dA[k] = g.alpha;
+        }
+      }
+      GSeg gl = ld_seg(segs, seg0 + min(S, nst - 1));   // copies of the first iteration
+      for (int s0 = 0; s0 < nst; s0 += S) {
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+          const int s = s0 + j;
+          if (s >= nst) break;
+          // this wave's copies of step s have landed (later steps may still be in flight)
+          const int ahead = min(nst - 1 - s, S - 1);
+          if (ahead >= 2) wg_step_barrier<2 * R::kCopies>();
+          else if (ahead == 1) wg_step_barrier<R::kCopies>();
+          else wg_step_barrier<0>();
+          u32x4_t a[2][NPL], b[2][NPL];
+          if (active) {
+            const unsigned char* st = ring + j * R::kStage + lane * 16;
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int pl = 0; pl < NPL; ++pl) {
+                a[i][pl] = *reinterpret_cast<const u32x4_t*>(st + ((2 * qm + i) * NPL + pl) * 1024);
+                b[i][pl] = *reinterpret_cast<const u32x4_t*>(st + ((4 + 2 * qn + i) * NPL + pl) * 1024);
+              }
+          }
+          // every wave has its operands of step s in registers: the stage is free
+          wg_read_barrier();
+          const int fl = dF[j], kk = dK[j];
+          const double al = dA[j];
+          const bool more = s + S < nst;
+          if (more) {
+            issue(gl, j);
+            dK[j] = gl.K;
+            dF[j] = gl.flags;
+            dA[j] = gl.alpha;
+          }
+          if (active) {
+            if (fl & kIdentA) {
+              PSeg d;
+              d.nch = (kk + 7) >> 3;
+              d.kbase = (fl >> kStepPassShift) * 32;
+              d.m0 = m0 + 32 * qm;
+              d.mt = mt;
+              ident_rows<2, NPL>(d, r16, q, a);
+            }
+            planes_mfma<2, NPL, NPROD>(a, b, t, fl & kStepFresh, ni, nj);
+            if (fl & kStepEnd) {
+#pragma unroll
+              for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+                  for (int v = 0; v < 4; ++v) acc[i][jj][v] += al * (double)t[i][jj][v];
+            }
+          }
+          if (more) gl = ld_seg(segs, seg0 + min(s + S + 1, nst - 1));
+        }
       }
     }
   }
