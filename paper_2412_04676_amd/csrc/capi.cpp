@@ -295,10 +295,15 @@ static void set_site_tensor_impl(Ctx& c, int site, int n_blocks, const int32_t* 
     BSD_HIP(hipMemcpy(T.mem.p, data, off * sizeof(double), hipMemcpyHostToDevice));
     T.set = true;
     c.sites[site] = std::move(T);
-    // blocks that depend on this site are stale
+    // blocks that depend on this site are stale, and so are the products that
+    // read them: the product at i reads the left block of bond i (sites < i) and
+    // the right block of bond i + 2 (sites >= i + 2)
     for (auto it = c.left.begin(); it != c.left.end();) it = it->first > site ? c.left.erase(it) : std::next(it);
     for (auto it = c.right.begin(); it != c.right.end();) it = it->first <= site ? c.right.erase(it) : std::next(it);
-    c.plans.clear();
+    for (auto it = c.plans.begin(); it != c.plans.end();) {
+      const int i = it->first.first;
+      it = (i > site || i + 2 <= site) ? c.plans.erase(it) : std::next(it);
+    }
 }
 
 int bsdmrg_set_site_tensor(bsdmrg_ctx* ctx, int site, int n_blocks, const int32_t* meta, const double* data) {
@@ -486,6 +491,9 @@ static HpsiPlan* get_plan(Ctx& c, int site, int precision, size_t ws, hipStream_
   if (it != c.plans.end() && !rebuild) return it->second.get();
   if (ws == 0) ws = c.hpsi_ws_default;
   PhaseTimer tm(c, BSDMRG_PH_TABLES);
+  // one product plan at a time: the plans of other positions (a sweep has
+  // moved on) and the one being replaced give their device memory back first
+  c.plans.clear();
   Block* Lb = get_block(c, true, site);
   Block* Rb = get_block(c, false, site + 2);
   const bool stream = c.hbm_budget > 0 && Lb && Rb && Lb->device_bytes() + Rb->device_bytes() > c.hbm_budget;
