@@ -242,6 +242,16 @@ int bsdmrg_load_integrals(bsdmrg_ctx* ctx, const double* h, const double* eri, d
 
 static HpsiPlan* get_plan(Ctx& c, int site, int precision, size_t ws, hipStream_t s, bool rebuild);
 
+// A renormalization that builds a block first frees the product plans: the
+// new block takes the device memory a plan held (at L=76 D=4096 a plan holds
+// tens of GB), and a sweep prepares the next position's plan after it anyway.
+// Work queued on the plans' buffers finishes first.
+static void release_plans(Ctx& c) {
+  if (c.plans.empty()) return;
+  BSD_HIP(hipDeviceSynchronize());
+  c.plans.clear();
+}
+
 // the environment blocks a prepared product reads must be on the device (a
 // streamed product reads its right operators from pinned host memory)
 static void need_env(Ctx& c, int site, const HpsiPlan* p, Block** Lo = nullptr, Block** Ro = nullptr) {
@@ -417,6 +427,7 @@ int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream
       int b0 = bond;
       while (b0 > 0 && !get_block(c, true, b0)) --b0;
       PhaseTimer tm(c, BSDMRG_PH_REN_L);
+      if (b0 < bond) release_plans(c);
       for (int b = b0; b < bond; ++b) {
         BSD_CHECK(c.sites[b].set, BSDMRG_ESTATE, "site tensor missing");
         Block* cur = get_block(c, true, b);
@@ -428,6 +439,7 @@ int bsdmrg_build_env(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stream
       int b0 = bond;
       while (b0 < c.L && !get_block(c, false, b0)) ++b0;
       PhaseTimer tm(c, BSDMRG_PH_REN_R);
+      if (b0 > bond) release_plans(c);
       for (int b = b0; b > bond; --b) {
         BSD_CHECK(c.sites[b - 1].set, BSDMRG_ESTATE, "site tensor missing");
         Block* cur = get_block(c, false, b);
@@ -454,12 +466,10 @@ int bsdmrg_renormalize(bsdmrg_ctx* ctx, int side, int bond, bsdmrg_stream_t stre
     BSD_CHECK(cur->resident, BSDMRG_EBUSY, "source block not resident");
     auto& m = left ? c.left : c.right;
     auto it = m.find(left ? bond + 1 : bond - 1);
-    if (it != m.end()) {
+    if (it != m.end())
       BSD_CHECK(!it->second->offload_pending, BSDMRG_EBUSY, "offload of the target block in flight; wait first");
-      BSD_HIP(hipDeviceSynchronize());
-      c.plans.clear();   // plans may reference the block that is replaced
-    }
     PhaseTimer tm(c, left ? BSDMRG_PH_REN_L : BSDMRG_PH_REN_R);
+    release_plans(c);
     if (left) renormalize_left_block(c, bond, S(stream));
     else renormalize_right_block(c, bond, S(stream));
     BSD_HIP(hipStreamSynchronize(S(stream)));

@@ -73,3 +73,39 @@ def rel(a, b):
 
 def psi_for(dims, site, seed):
     return random_two_site_psi(dims[site], dims[site + 2], seed)
+
+
+def split_energy_check(ctx, site, x, iters, stream):
+    """Float64 Davidson and the two-stage BF16X6 and BF16X3 Davidson runs from
+    the same start vector with the same iteration cap, and the energy shift of
+    one split product on the float64 Davidson vector (the Rayleigh quotient
+    change).  BF16X6 must reach the float64 energy within 1e-6 Eh and shift it
+    by at most 1e-6 Eh; the BF16X3 figures are returned for the record (the
+    runs are not converged, so their energies follow different trajectories)."""
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    x = x / torch.linalg.norm(x)
+    res = {}
+    vec = None
+    for p in (B.FP64, B.BF16X6, B.BF16X3):
+        xs = x.clone()
+        e, it, r, _ = B.bsdmrg_davidson(ctx, site, xs, max_iter=iters, tol=1e-8, precond=1, precision=p,
+                                        stream=stream)
+        torch.cuda.synchronize()
+        res[p] = e
+        if p == B.FP64:
+            vec = xs
+    y64 = torch.empty_like(vec)
+    B.bsdmrg_hpsi(ctx, site, vec, y64, B.FP64, stream)
+    shifts = {}
+    for p in (B.BF16X6, B.BF16X3):
+        y = torch.empty_like(vec)
+        B.bsdmrg_hpsi(ctx, site, vec, y, p, stream)
+        torch.cuda.synchronize()
+        shifts[p] = abs(float(torch.dot(vec, y - y64))) / float(torch.dot(vec, vec))
+    say(f"  Davidson {iters} it: E fp64 {res[B.FP64]:.10f}, bf16x6 dE {res[B.BF16X6] - res[B.FP64]:.2e}, "
+        f"bf16x3 dE {res[B.BF16X3] - res[B.FP64]:.2e} Eh; product shift on the fp64 vector bf16x6 "
+        f"{shifts[B.BF16X6]:.2e}, bf16x3 {shifts[B.BF16X3]:.2e} Eh")
+    assert abs(res[B.BF16X6] - res[B.FP64]) <= 1e-6
+    assert shifts[B.BF16X6] <= 1e-6
+    return res, shifts
