@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <thread>
+#include <unordered_map>
 
 namespace bsd {
 
@@ -221,6 +222,15 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   auto plan = std::make_unique<HpsiPlan>();
   plan->site = site;
   plan->precision = precision;
+  // BSDMRG_VERBOSE: host wall time of the stages
+  const bool verbose = std::getenv("BSDMRG_VERBOSE") != nullptr;
+  auto t_last = std::chrono::steady_clock::now();
+  auto note = [&](const char* what) {
+    if (!verbose) return;
+    const auto now = std::chrono::steady_clock::now();
+    std::fprintf(stderr, "plan: %s %.3f s\n", what, std::chrono::duration<double>(now - t_last).count());
+    t_last = now;
+  };
   build_psi_layout(*Lb, *Rb, C, ctx.target, plan->lay);
   const PsiLayout& lay = plan->lay;
 
@@ -399,6 +409,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     }
   }
 
+  note("channels and L-side references");
   // ---------------------------------------------------------------- chunks of channels
   const int nR = (int)Rb->basis.q.size();
   std::vector<std::vector<int>> by_c(16);
@@ -520,11 +531,23 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   plan->stream_r = stream_r;
   if (stream_r) plan->schunks.resize(nchunks);
   // distinct operator blocks the product reads (algorithmic bytes: each once)
-  std::map<const double*, int64_t> op_blocks;
+  std::unordered_map<const double*, int64_t> op_blocks;
   double heavy_flops = 0.0, ident_flops = 0.0;   // diagnostics
   std::vector<std::vector<GemmProblem>> p1(nchunks), p1s(nchunks), p1h(nchunks);
   // per chunk, per output psi block: list of segments
-  std::vector<std::map<int, GemmProblem>> p2(nchunks), p2s(nchunks), p2h(nchunks);
+  // (dense by output psi block; empty entries are skipped when the lists are handed on)
+  const int nblk = (int)lay.blocks.size();
+  std::vector<std::vector<GemmProblem>> p2(nchunks), p2s(nchunks), p2h(nchunks);
+  for (int k = 0; k < nchunks; ++k) {
+    p2[k].resize(nblk);
+    p2s[k].resize(nblk);
+    p2h[k].resize(nblk);
+  }
+  // psi block of (left index, local state, right index), dense
+  const int nLs = (int)Lb->basis.q.size(), nRs = (int)Rb->basis.q.size();
+  std::vector<int> bidx((size_t)nLs * 16 * nRs, -1);
+  for (int b = 0; b < nblk; ++b)
+    bidx[((size_t)lay.blocks[b].l * 16 + lay.blocks[b].c) * nRs + lay.blocks[b].r] = b;
   for (size_t ci = 0; ci < chans.size(); ++ci) {
     if (chunk_of[ci] < 0 || cgroups[ci].empty()) continue;
     const int ck = chunk_of[ci];
@@ -613,23 +636,46 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
       }
     }
     const int rpar = ch.rdq.parity();
+    // what an input block contributes does not depend on the output local
+    // state c2: its right sector, L operand and plane offset are found once per
+    // (group, c) and reused for every c2 (the segment order is unchanged)
+    struct InBlk {
+      int r2 = -1;
+      Operand2 o;
+      int64_t plane = -1;   // op_plane of o, taken at its first use
+    };
+    std::vector<InBlk> inb;
     for (const auto& g : cgroups[ci]) {
       const LRef& lr = lrefs[g.lref];
-      for (int c = 0; c < 16; ++c)
+      for (int c = 0; c < 16; ++c) {
+        bool any = false;
+        for (int c2 = 0; c2 < 16 && !any; ++c2) any = g.M(c2, c) != 0.0;
+        if (!any) continue;
+        inb.assign(by_c[c].size(), InBlk());
+        for (size_t k = 0; k < by_c[c].size(); ++k) {
+          const PsiBlk& pb = lay.blocks[by_c[c][k]];
+          int r2 = ch.rkind == 1 ? pb.r : Rb->basis.find(Rb->basis.q[pb.r] + ch.rdq);
+          if (r2 < 0) continue;
+          if (ch.rkind == 0 && (vi.off[r2] < 0 || vi.src[r2] != pb.r)) continue;
+          Operand2 o = lref_block(*Lb, lr, agg_sk, agg_off, agg_mem, pb.l);
+          if (!o.ok) continue;
+          inb[k].r2 = r2;
+          inb[k].o = o;
+        }
         for (int c2 = 0; c2 < 16; ++c2) {
           double m = g.M(c2, c);
           if (m == 0.0) continue;
-          for (int bi : by_c[c]) {
+          for (size_t k = 0; k < by_c[c].size(); ++k) {
+            InBlk& ib = inb[k];
+            if (ib.r2 < 0) continue;
+            const int bi = by_c[c][k];
             const PsiBlk& pb = lay.blocks[bi];
             // input block (l, c, r); output (l', c2, r')
-            int r2 = ch.rkind == 1 ? pb.r : Rb->basis.find(Rb->basis.q[pb.r] + ch.rdq);
-            if (r2 < 0) continue;
-            if (ch.rkind == 0 && (vi.off[r2] < 0 || vi.src[r2] != pb.r)) continue;
-            Operand2 o = lref_block(*Lb, lr, agg_sk, agg_off, agg_mem, pb.l);
-            if (!o.ok) continue;
-            auto oit = lay.index.find({o.out, c2, r2});
-            if (oit == lay.index.end()) continue;
-            const PsiBlk& ob = lay.blocks[oit->second];
+            const int r2 = ib.r2;
+            const Operand2& o = ib.o;
+            const int oidx = bidx[((size_t)o.out * 16 + c2) * nRs + r2];
+            if (oidx < 0) continue;
+            const PsiBlk& ob = lay.blocks[oidx];
             const int lpar = Lb->basis.q[pb.l].parity();
             const int cpar = C.q[c].parity();
             int sp = (g.mpar & lpar) ^ (rpar & (lpar ^ cpar));
@@ -647,7 +693,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
               sg.B = tag_ptr(0, (uint64_t)(V + vi.off[r2] + row0 * Rb->basis.dim[r2]));
               sg.ldb = Rb->basis.dim[r2];
             }
-            auto& gp = p2[ck][oit->second];
+            auto& gp = p2[ck][oidx];
             if (gp.segs.empty()) {
               gp.C = tag_ptr(2, (uint64_t)(ob.off * sizeof(double)));
               gp.ldc = ob.cols;
@@ -664,7 +710,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
               if (ch.rkind == 1) ident_flops += 2.0 * ob.rows * (double)ob.cols * pb.rows;
             }
             if (heavy) {
-              auto& gh = p2h[ck][oit->second];
+              auto& gh = p2h[ck][oidx];
               if (gh.segs.empty()) {
                 gh.C = gp.C;
                 gh.ldc = gp.ldc;
@@ -681,8 +727,8 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
             sq.alpha = sg.alpha;
             sq.K = pb.rows;
             sq.flags = o.ident ? kIdentA : 0;
-            sq.A = o.ident ? tag_ptr(3, 0)
-                           : tag_ptr(3, (uint64_t)(op_plane(o.p, o.ld, o.trans, ob.rows, pb.rows) * 2));
+            if (!o.ident && ib.plane < 0) ib.plane = op_plane(o.p, o.ld, o.trans, ob.rows, pb.rows);
+            sq.A = o.ident ? tag_ptr(3, 0) : tag_ptr(3, (uint64_t)(ib.plane * 2));
             sq.lda = (pb.rows + 7) / 8;
             if (ch.rkind == 1) {
               sq.B = tag_ptr(3, (uint64_t)(psi_poff[bi] * 2));
@@ -692,7 +738,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
               sq.B = tag_ptr(3, (uint64_t)(e * 2));
               sq.ldb = lay.stack_prows[pb.r] / 8;
             }
-            auto& gq = p2s[ck][oit->second];
+            auto& gq = p2s[ck][oidx];
             if (gq.segs.empty()) {
               gq.C = gp.C;
               gq.ldc = gp.ldc;
@@ -704,8 +750,10 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
             gq.segs.push_back(sq);
           }
         }
+      }
     }
   }
+  note("segments");
   // diagonal of H_eff: for every channel and group without a quantum-number
   // change, diag(Lambda) (x) M[c][c] (x) diag(R_b), as K = 1 sector products
   {
@@ -780,8 +828,8 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
         sg.B = absolute(sg.B);
       }
     }
-    for (auto& kv : p2s[k])
-      for (auto& sg : kv.second.segs) {
+    for (auto& gp : p2s[k])
+      for (auto& sg : gp.segs) {
         sg.A = absolute(sg.A);
         sg.B = absolute(sg.B);
       }
@@ -815,12 +863,15 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
     }
   });
   for (int k = 0; k < nchunks; ++k) {
-    for (auto& kv : p2[k]) {
-      plan->nseg += kv.second.segs.size();
-      plan->p2_probs[k].push_back(std::move(kv.second));
+    for (auto& gp : p2[k]) {
+      if (gp.segs.empty()) continue;
+      plan->nseg += gp.segs.size();
+      plan->p2_probs[k].push_back(std::move(gp));
     }
-    for (auto& kv : p2s[k]) plan->p2s_probs[k].push_back(std::move(kv.second));
-    for (auto& kv : p2h[k]) plan->p2h_probs[k].push_back(std::move(kv.second));
+    for (auto& gp : p2s[k])
+      if (!gp.segs.empty()) plan->p2s_probs[k].push_back(std::move(gp));
+    for (auto& gp : p2h[k])
+      if (!gp.segs.empty()) plan->p2h_probs[k].push_back(std::move(gp));
   }
   if (std::getenv("BSDMRG_PLAN_STATS")) {
     // diagnostic: MFMA work of phase 2 at the kernels' granularity (16 x 16
@@ -867,6 +918,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
       std::min(131072.0, std::max(8192.0, (double)plan->nseg / 128.0));
   rebuild_phase2(*plan, plan->opts64, plan->opts_planes, 3);
 
+  note("diagonal, phase-1 lists and phase-2 tile lists");
   // ---------------------------------------------------------------- split tasks
   // padded-row maps of the right-sector stacks: plane column -> stack row or -1
   std::vector<int64_t> kmap_off(nR, -1);
@@ -931,6 +983,7 @@ std::unique_ptr<HpsiPlan> build_hpsi_plan(Ctx& ctx, int site, int precision, siz
   for (const auto& kv : op_blocks) plan->op_elems += kv.second;
   plan->nchannels = (int)chans.size();
   plan->naggs = (int)agg_sk.size();
+  note("split tasks");
   return plan;
 }
 
