@@ -151,3 +151,143 @@ def family_from_ops(tag, ops):
     blocks = [(q, ops[0].blocks[q].shape[0], ops[0].blocks[q].shape[1]) for q in qs]
     data = np.stack([np.concatenate([op.blocks[q].ravel() for q in qs]) for op in ops])
     return {"tag": tag, "dq": dq, "blocks": blocks, "data": data}
+
+
+# ---------------------------------------------------------------- segments
+# Self-contained packages (Sec. III.B.3) cut for a small staging buffer (Sec.
+# III.A strategy 1, Fig. 4b).  The paper fixes the properties, not the bytes:
+# every segment says by itself which family and which layers it holds, so a
+# reader places segments in any order and can refuse a set that does not
+# cover the block exactly once.  The project's format, little-endian:
+#
+#   Segment header, 256 bytes
+#     0  magic        8 bytes  b"BSDSEG01"
+#     8  owner        u64      the block's family tags with the low 20 bits
+#                              (the family index) cleared
+#    16  family       u32      index of the family in the block
+#    20  n_families   u32
+#    24  layer0       u32      first layer held
+#    28  n_layers     u32      layers held (at least one)
+#    32  payload      u64      n_layers * layer_elems * 8
+#    40  print        u64      FNV-1a fingerprint of the family's skeleton
+#    48  index        u64      position of the segment in the writer's order
+#    56  zero bytes up to 256
+#   Payload: the layers, each laid out as in the one-stream payload, then zero
+#   bytes to the next 256-byte boundary.
+#
+# A family's layers are cut into runs of as many whole layers as fit half the
+# staging area (half = floor(staging / 2) rounded down to 256 bytes); a family
+# whose single layer exceeds that half cannot be segmented.  Families with no
+# layers or no elements give no segment.  Writer order: families in order,
+# runs in layer order.
+
+SEG_MAGIC = b"BSDSEG01"
+SEG_HEADER = 256
+FNV_OFFSET = 14695981039346656037
+FNV_PRIME = 1099511628211
+INDEX_BITS = 20
+
+
+def fnv1a64(data):
+    """The 64-bit FNV-1a hash of a byte string (Fowler, Noll and Vo): start
+    from the offset basis, and for every byte xor it in, then multiply by the
+    FNV prime modulo 2^64."""
+    h = FNV_OFFSET
+    for byte in bytes(data):
+        h ^= byte
+        h = (h * FNV_PRIME) % (1 << 64)
+    return h
+
+
+def skeleton_print(fam):
+    """Fingerprint of a family's block-sparse skeleton: FNV-1a over the 8-byte
+    little-endian two's-complement encodings of dq (both charges), the layer
+    count, and for every block in table order its input sector (both charges),
+    rows and cols.  Layer values do not enter."""
+    vals = [fam["dq"][0], fam["dq"][1], fam["data"].shape[0]]
+    for q, r, c in fam["blocks"]:
+        vals += [q[0], q[1], r, c]
+    return fnv1a64(b"".join(struct.pack("<q", v) for v in vals))
+
+
+def owner_of(families):
+    return families[0]["tag"] & ~((1 << INDEX_BITS) - 1) if families else 0
+
+
+def segment_half(staging_bytes):
+    return staging_bytes // 2 // ALIGN * ALIGN
+
+
+def segment_runs(families, staging_bytes):
+    """(family, layer0, n_layers) of every segment, in writer order."""
+    half = segment_half(staging_bytes)
+    runs = []
+    for f, fam in enumerate(families):
+        nl, lb = fam["data"].shape[0], layer_elems(fam) * 8
+        if nl == 0 or lb == 0:
+            continue
+        if lb > half:
+            raise ValueError("half the staging area is smaller than one layer")
+        per = max(1, half // lb)
+        for l0 in range(0, nl, per):
+            runs.append((f, l0, min(per, nl - l0)))
+    return runs
+
+
+def segments(families, staging_bytes):
+    """The segments of a block, as one list of byte strings in writer order."""
+    owner = owner_of(families)
+    out = []
+    for i, (f, l0, n) in enumerate(segment_runs(families, staging_bytes)):
+        fam = families[f]
+        raw = np.ascontiguousarray(fam["data"][l0:l0 + n], dtype="<f8").tobytes()
+        head = bytearray(SEG_HEADER)
+        struct.pack_into("<8sQIIIIQQQ", head, 0, SEG_MAGIC, owner, f, len(families), l0, n,
+                         len(raw), skeleton_print(fam), i)
+        out.append(bytes(head) + raw + bytes(align(len(raw)) - len(raw)))
+    return out
+
+
+def split_segments(stream):
+    """Cut a concatenation of segments back into single segments, using only
+    each header's payload size."""
+    out, at = [], 0
+    while at < len(stream):
+        if len(stream) - at < SEG_HEADER:
+            raise CorruptStream("short segment header")
+        payload = struct.unpack_from("<Q", stream, at + 32)[0]
+        n = SEG_HEADER + align(payload)
+        if len(stream) - at < n:
+            raise CorruptStream("short segment")
+        out.append(bytes(stream[at:at + n]))
+        at += n
+    return out
+
+
+def reassemble(stream, skeleton):
+    """Read a concatenation of segments, in any order, into the layers of a
+    block whose skeleton (families with tag, dq, blocks and the data shape) is
+    known.  Every header is checked and every layer must be held exactly once
+    before any layer is returned."""
+    owner = owner_of(skeleton)
+    data = [np.full(f["data"].shape, np.nan) for f in skeleton]
+    seen = [np.zeros(f["data"].shape[0], dtype=int) for f in skeleton]
+    parts = []
+    for seg in split_segments(stream):
+        magic, own, f, nf, l0, n, payload, fp, _ = struct.unpack_from("<8sQIIIIQQQ", seg, 0)
+        if magic != SEG_MAGIC or own != owner or nf != len(skeleton) or f >= nf:
+            raise CorruptStream("segment of another block")
+        fam = skeleton[f]
+        if fp != skeleton_print(fam) or n == 0 or l0 + n > fam["data"].shape[0] \
+                or payload != n * layer_elems(fam) * 8:
+            raise CorruptStream("segment does not fit the family")
+        seen[f][l0:l0 + n] += 1
+        parts.append((f, l0, n, seg))
+    for f, fam in enumerate(skeleton):
+        if layer_elems(fam) > 0 and np.any(seen[f] != 1):
+            raise CorruptStream("layers missing or repeated")
+    for f, l0, n, seg in parts:
+        le = layer_elems(skeleton[f])
+        data[f][l0:l0 + n] = np.frombuffer(seg, dtype="<f8", count=n * le,
+                                           offset=SEG_HEADER).reshape(n, le)
+    return data

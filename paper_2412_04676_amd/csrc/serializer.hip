@@ -329,12 +329,14 @@ static void upload(const std::vector<FamilyView>& fv, SerialPlan& d, hipStream_t
     });
     for (int l = 1; l <= v.n_layers; ++l) first[l] = std::max(first[l], first[l - 1]);
     int64_t le = 0;
-    // FNV-1a over the skeleton: dq, layer count, every block's sector and shape
-    uint64_t h = 1469598103934665603ull;
+    // 64-bit FNV-1a (offset basis 0xcbf29ce484222325, prime 0x100000001b3) over
+    // the little-endian bytes of the skeleton: dq, layer count, every block's
+    // sector and shape
+    uint64_t h = 0xcbf29ce484222325ull;
     auto mix = [&](int64_t x) {
       for (int k = 0; k < 8; ++k) {
         h ^= (uint64_t)((x >> (8 * k)) & 0xff);
-        h *= 1099511628211ull;
+        h *= 0x100000001b3ull;
       }
     };
     mix(v.dq.a);

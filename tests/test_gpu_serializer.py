@@ -376,6 +376,39 @@ def test_segments_round_trip_in_any_order():
     B.bsdmrg_destroy(ctx)
 
 
+def test_segments_match_the_oracle_bytes():
+    """The segments a block packs through a small staging area are, byte for
+    byte, the reference serializer's segments of the same block (headers,
+    skeleton fingerprints, layer runs, zero padding), read from the block's
+    one-stream form, at two staging sizes."""
+    import torch
+    from paper_2412_04676_amd import bsdmrg as B
+    L, na, nb, D, site = 10, 5, 5, 60, 4
+    say("segments vs oracle bytes")
+    ctx, h, eri, dims, T = build_system(L, na, nb, D, site)
+    comp, side = torch.cuda.current_stream(), torch.cuda.Stream()
+    for sd, bond in ((B.LEFT, site), (B.RIGHT, site + 2)):
+        n = B.bsdmrg_serialized_size(ctx, sd, bond)
+        dst = torch.empty(n // 8 + 32, dtype=torch.float64, device="cuda")
+        B.bsdmrg_pack(ctx, sd, bond, dst, dst.numel() * 8)
+        torch.cuda.synchronize()
+        fams = S.deserialize(dst.cpu().numpy().view(np.uint8)[:n].tobytes())
+        need = max(S.layer_elems(f) * 8 for f in fams if f["data"].shape[0])
+        smallest = 2 * ((need + 255) // 256 * 256)
+        for staging_bytes in (smallest, 4 * smallest):
+            expect = b"".join(S.segments(fams, staging_bytes))
+            total, nseg = B.bsdmrg_segments_size(ctx, sd, bond, staging_bytes)
+            say(f"  side {sd} staging {staging_bytes}: {nseg} segments, {total} bytes")
+            assert total == len(expect)
+            assert nseg == len(S.segment_runs(fams, staging_bytes))
+            staging = torch.empty(staging_bytes // 8, dtype=torch.float64, device="cuda")
+            pin = torch.full((total // 8,), 7.0, dtype=torch.float64, pin_memory=True)
+            written, k = B.bsdmrg_pack_segments(ctx, sd, bond, staging, staging_bytes, pin, total, comp, side)
+            assert written == total and k == nseg
+            assert pin.numpy().view(np.uint8).tobytes() == expect
+    B.bsdmrg_destroy(ctx)
+
+
 def test_pack_is_independent_of_the_workgroup_count():
     import torch
     from paper_2412_04676_amd import bsdmrg as B
