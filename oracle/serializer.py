@@ -38,6 +38,9 @@ project's own, little-endian throughout:
   each layer the blocks in table order, each block row-major and compact;
   zero padding to the next 256-byte boundary after every family.
 
+The segmented form (self-contained packages for a small staging buffer) is
+described and built at the end of this module.
+
 A family here is a dict {"tag": int, "dq": (a, b), "blocks": [(q_in, rows,
 cols)], "data": float64 array (n_layers, layer_elems)}.
 """
