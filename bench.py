@@ -77,14 +77,26 @@ def build_workload(L, na, nb, D, site):
 
 
 def cpu_model():
+    """Model name of the host CPU with its family, model and stepping numbers
+    (virtual machines often report a generic name; the numbers still name the
+    core generation) and the logical CPUs this process may run on."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break                      # first processor only
+                key, _, val = line.partition(":")
+                info.setdefault(key.strip(), val.strip())
     except OSError:
-        pass
-    return "unknown"
+        return "unknown"
+    name = info.get("model name", "unknown")
+    nums = [f"{k} {info[k]}" for k in ("cpu family", "model", "stepping") if k in info]
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return f"{name} ({', '.join(nums)}; {usable} logical CPUs usable)" if nums else name
 
 
 def cpu_baseline(L, na, nb, D, site, budget_s=20.0, single_budget_s=8.0):
