@@ -596,6 +596,7 @@ def main():
         log("bench: timing the CPU oracle on a bounded sample")
         try:
             cL, cN, cD = args.cpu_L, args.cpu_N, args.cpu_D
+            same = (cL, cN, cD) == (args.L, args.N, args.D)
             cna, cnb = (cN + 1) // 2, cN // 2
             csite = cL // 2 - 1
             cb = cpu_baseline(cL, cna, cnb, cD, csite, args.cpu_budget)
@@ -615,10 +616,12 @@ def main():
             B.bsdmrg_destroy(cctx)
             out["cpu_baseline"] = {
                 "value": cF * cb["n"] / cb["dt"] / 1e12, "unit": "TFLOP/s", "cores": cb["cores"], "kind": "oracle",
-                "sample": f"{cb['n']} full middle-site products H.psi of the oracle (numpy float64) on the smaller "
-                          f"workload L={cL} N={cN} S_z={(cna - cnb) / 2} D={cD} in {cb['dt']:.1f} s, after an "
-                          f"untimed {cb['setup_s']:.0f} s environment build; the oracle cannot build the "
-                          f"{wl} environments; flops counted as on the GPU path",
+                "sample": f"{cb['n']} full middle-site products H.psi of the oracle (numpy float64) on "
+                          f"{'the bench workload' if same else 'the smaller workload'} L={cL} N={cN} "
+                          f"S_z={(cna - cnb) / 2} D={cD} in {cb['dt']:.1f} s, after an untimed "
+                          f"{cb['setup_s']:.0f} s environment build; "
+                          + ("" if same else f"the oracle cannot build the {wl} environments; ")
+                          + "flops counted as on the GPU path",
                 "single_thread_value": cF * cb["n1"] / cb["dt1"] / 1e12,
                 "cpu_model": cpu_model(), "workload": f"L={cL} N={cN} D={cD}"}
         except Exception as e:  # report, never hide
