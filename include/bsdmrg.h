@@ -457,10 +457,15 @@ int bsdmrg_set_side_delay(bsdmrg_ctx* ctx, double ms);
  * block's families are cut into segments of whole layers that fit half of
  * staging_dev (staging_bytes, 256-byte aligned); a segment is packed into one
  * half on `compute` while the other half is copied to pinned_host on `side`.
- * Every segment starts with a 256-byte header (magic "BSDSEG01", owner block,
- * family, first layer, layer count, payload bytes, skeleton fingerprint,
- * index) followed by its layers (blocks compact row-major, padded to 256 B),
- * so segments can be stored, moved and read back in any order.
+ * Every segment starts with a 256-byte little-endian header: bytes 0-7 magic
+ * "BSDSEG01", u64 owner at 8 (the block's family tags with the low 20 bits
+ * cleared), u32 family at 16, u32 family count at 20, u32 first layer at 24,
+ * u32 layer count at 28, u64 payload bytes at 32, u64 skeleton fingerprint at
+ * 40 (64-bit FNV-1a over the 8-byte little-endian values of dq, the layer
+ * count and every block's sector, rows and cols), u64 segment index at 48,
+ * zeros to 256.  Its layers follow (blocks compact row-major, as in the
+ * one-stream payload), zero padded to 256 B, so segments can be stored, moved
+ * and read back in any order.
  * bsdmrg_segments_size gives the exact total and the segment count for a
  * staging size (host arithmetic).  ENOMEM if half the staging area cannot hold
  * one layer of a family or cap is too small.  Synchronizing; *written gets the
