@@ -149,3 +149,30 @@ def test_config_and_state_calls_validate_arguments():
         B.bsdmrg_next_guess(ctx, 2, 0, 256, 256)
     assert e.value.code == B.ESTATE
     B.bsdmrg_destroy(ctx)
+
+
+def test_noalloc_pack_limits_are_checked_on_the_host():
+    """The allocation-free pack states its fixed scratch size and refuses,
+    before any device call, descriptor tables that do not fit it and
+    destinations below the exact serialized size."""
+    from paper_2412_04676_amd import bsdmrg as B
+    assert B.bsdmrg_noalloc_scratch_bytes() == 16 << 20
+
+    def family(nb):
+        return {"tag": 0, "dq": (0, 0), "n_layers": 1, "block_q": np.zeros((nb, 2), dtype=np.int32),
+                "rows": np.ones(nb), "cols": np.ones(nb), "ld": np.ones(nb),
+                "elem_offset": np.arange(nb), "layer_stride": nb, "data": 256}
+
+    big = family(600_000)   # one descriptor and one offset per block: above 16 MiB
+    n = B.bsdmrg_serialized_size_desc([big])
+    with pytest.raises(B.BsdmrgError) as e:
+        B.bsdmrg_pack_desc_noalloc([big], 4096, n)
+    assert e.value.code == B.EINVAL and "exceed the no-allocation scratch" in str(e.value)
+    small = family(3)
+    n = B.bsdmrg_serialized_size_desc([small])
+    with pytest.raises(B.BsdmrgError) as e:
+        B.bsdmrg_pack_desc_noalloc([small], 4096, n - 1)
+    assert e.value.code == B.ENOMEM
+    with pytest.raises(B.BsdmrgError) as e:
+        B.bsdmrg_pack_desc_noalloc([small], 4096 + 8, n)
+    assert e.value.code == B.EINVAL
